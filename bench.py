@@ -1,0 +1,259 @@
+#!/usr/bin/env python3
+"""Benchmark of the chi0 / eps^-1 hot path on one MI355X.
+
+One step = one pass of the whole path over one q of the silicon-like bulk
+workload (48^3 grid, Ng = 1500, Nv = 4, Nc = 400, Nk = 64, static, FP64):
+pair densities by FFT -> energy weights + chi-sum -> epsilon and its
+inverse.  Inputs are generated once (seeded, synthetic) and are resident in
+HBM before the timed region; W untimed warm-up steps, then exactly K timed
+steps bracketed by torch.cuda.synchronize().
+
+Prints ONE JSON line.  `value` is the chi-sum algorithmic rate of the whole
+step: 4 Ng^2 K Nw flops / step time (TFLOP/s, FP64-equivalent).  Per-kernel
+times come from HIP events the library records on the launch stream during
+the timed steps; the roofline entry is for the kernel that dominates the
+step.  `cpu_baseline` times the oracle on a bounded sample of the same
+workload and extrapolates linearly in pairs.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2516.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="silicon-like-48")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-pairs", type=int, default=256)
+    return ap.parse_args()
+
+
+def source_digest(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, src_files):
+    """HBM bytes per launch measured by rocprofv3 PMC runs, if the committed
+    record was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_digest") != source_digest(src_files):
+        return None
+    return rec
+
+
+def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
+    import oracle
+
+    q = s["qs"][0]
+    K = s["nk"] * s["nv"] * s["nc"]
+    ng = q["ng"]
+    rng = np.random.default_rng(123)
+    pairs = np.sort(rng.choice(K, size=pairs_sample, replace=False))
+    t0 = time.perf_counter()
+    Ms = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
+    t_m = time.perf_counter() - t0
+    kk = pairs // (s["nv"] * s["nc"])
+    vv = (pairs // s["nc"]) % s["nv"]
+    cc = pairs % s["nc"]
+    w_all = oracle.weights(q["ev"], s["ec"], s["omega"])
+    w = w_all[:, pairs]
+    pf = 1.0 / (s["nk"] * s["vol"])
+    t0 = time.perf_counter()
+    chi_s = oracle.chi(Ms, w, pf)
+    t_c = time.perf_counter() - t0
+    v = oracle.vcoul(s["bmat"], q["q"], q["ge"])
+    t0 = time.perf_counter()
+    oracle.eps_inv(v, chi_s)
+    t_i = time.perf_counter() - t0
+    scale = K / pairs_sample
+    t_step = (t_m + t_c) * scale + t_i
+    del kk, vv, cc
+    return {
+        "value": chi_flops_step / t_step / 1e12,
+        "unit": "TFLOP/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"oracle on {pairs_sample} of {K} pairs: M by convolution ({t_m:.2f} s) and chi over all "
+                   f"{ng}x{ng} entries ({t_c:.2f} s), extrapolated x{scale:.0f}; plus one full {ng}x{ng} "
+                   f"inversion ({t_i:.2f} s); extrapolated step {t_step:.1f} s"),
+        "cpu": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (no multi-GPU path)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1111_4429_amd import bgw, synth
+
+    assert torch.cuda.is_available(), "bench needs a HIP device"
+    dev = torch.device("cuda:0")
+    wl = synth.WORKLOADS[args.workload]
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    s = synth.make_system(wl)
+    q = s["qs"][0]
+    n, ng, nk, nv, nc = s["n"], q["ng"], s["nk"], s["nv"], s["nc"]
+    K = nk * nv * nc
+    N = n ** 3
+    nw = len(s["omega"])
+    pf = 1.0 / (nk * s["vol"])
+
+    cv = torch.from_numpy(q["cv"]).to(dev)
+    cc = torch.from_numpy(s["cc"]).to(dev)
+    ev = torch.from_numpy(q["ev"]).to(dev)
+    ec = torch.from_numpy(s["ec"]).to(dev)
+    v = torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev)
+    M = torch.empty((K, ng), dtype=torch.complex128, device=dev)
+    chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
+    einv = torch.empty_like(chi)
+    info = torch.empty(nw, dtype=torch.int32, device=dev)
+    h = bgw.Handle(0)
+    qd = dict(M=M, ev=ev, ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf)
+
+    def step():
+        h.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
+        h.chi0([qd], s["omega"], precision=bgw.FP64, chis=[chi])
+        h.eps_inv(v, chi, epsinv=einv, info=info)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.reset_timing()
+    h.set_timing(True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    h.set_timing(False)
+    tm = h.timing()
+    assert int(info.cpu().max()) == 0 and int(info.cpu().min()) == 0
+
+    ms_step = elapsed * 1e3 / args.steps
+    chi_flops = 4.0 * ng * ng * K * nw
+    fft_bytes = K * 16.0 * (N + ng)
+    lu_flops = 8.0 * ng ** 3 * nw
+
+    def avg(name):
+        ms, cnt = tm[name]
+        return (ms / cnt if cnt else float("nan")), cnt
+
+    pair_ms, pair_n = avg("pair")
+    herk_ms, herk_n = avg("herk")
+    band_ms, band_n = avg("band")
+    inv_ms, inv_n = avg("invert")
+    per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
+    # pair-FFT launches per step: one per k-batch; algorithmic bytes per launch
+    pair_launch_per_step = pair_n / args.steps
+    bytes_per_launch = fft_bytes / pair_launch_per_step
+    herk_per_step = herk_n / args.steps
+    flops_per_herk = chi_flops / herk_per_step
+
+    stages = {
+        "pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0),
+        "band_ms": per_step.get("band", 0),
+        "pair_fft_ms": per_step.get("pair", 0),
+        "chi_ms": per_step.get("weights", 0) + per_step.get("herk", 0) + per_step.get("finalize", 0),
+        "herk_ms": per_step.get("herk", 0),
+        "eps_inv_ms": per_step.get("eps_build", 0) + per_step.get("invert", 0),
+        "chi_sum_TFLOPs": chi_flops / (herk_ms * herk_per_step * 1e-3) / 1e12,
+        "chi_sum_frac_fp64_peak": chi_flops / (herk_ms * herk_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "pair_fft_GBs_algorithmic": fft_bytes / (pair_ms * pair_launch_per_step * 1e-3) / 1e9,
+        "pair_fft_nominal_TFLOPs": 5.0 * N * np.log2(N) * K / (pair_ms * pair_launch_per_step * 1e-3) / 1e12,
+        "eps_inv_TFLOPs": lu_flops / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
+    }
+    kernel_share = {k: per_step[k] / ms_step for k in per_step}
+    dominant = max(("pair", "herk", "invert", "band"), key=lambda k: per_step.get(k, 0))
+    fft_src = ["paper_1111_4429_amd/csrc/fft.hip", "paper_1111_4429_amd/csrc/common.h"]
+    chi_src = ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/common.h"]
+    if dominant == "pair":
+        ach = bytes_per_launch / (pair_ms * 1e-3) / 1e9
+        tr = load_traffic("pair", fft_src)
+        roof = {"kernel": "k_pair_fft", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS,
+                "traffic": None if tr is None else tr["bytes_per_launch"],
+                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": pair_ms}
+    elif dominant == "herk":
+        ach = flops_per_herk / (herk_ms * 1e-3) / 1e12
+        tr = load_traffic("herk", chi_src)
+        roof = {"kernel": "k_herk_f64", "bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
+                "traffic": None if tr is None else tr["bytes_per_launch"],
+                "algorithmic_flops_per_launch": flops_per_herk, "avg_launch_ms": herk_ms}
+    else:
+        ms_ = per_step[dominant]
+        roof = {"kernel": dominant, "bound": "mfma", "achieved": None, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": None, "traffic": None}
+
+    out = {
+        "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
+        "value": chi_flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies)",
+        "config": {"workload": wl.name, "grid": f"{n}^3", "ng": ng, "ngw": len(s["gw"]), "nv": nv, "nc": nc,
+                   "nk": nk, "npairs": K, "nw": nw, "precision": "fp64", "q": list(map(float, q["q"]))},
+        "stages": stages,
+        "kernel_share": kernel_share,
+        "roofline": roof,
+        "split": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_pairs, chi_flops)
+    h.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * bgw.h -- C-ABI of the MI355X hot path of the RPA polarizability step of
+ * the GW method (Deslippe et al., "BerkeleyGW: A massively parallel computer
+ * package ...", section "RPA Dielectric Matrix: epsilon").
+ *
+ * The paper splits the epsilon step into three computationally intensive
+ * parts (epsilon section, paragraph that opens "The computation of
+ * epsilon^-1 ... involves three computationally intensive steps"):
+ *   1. the plane-wave matrix elements M_nn'(k,q,G)   -> bgw_pair_density
+ *   2. the chi summation                             -> bgw_chi0
+ *   3. the dielectric matrix and its inversion       -> bgw_eps_inv
+ *
+ * Conventions shared by every call:
+ *   - complex numbers are interleaved (re, im) doubles, row-major arrays,
+ *     i.e. the memory layout of numpy/torch complex128;
+ *   - "DEVICE" pointers are HIP device memory on the handle's GPU, "HOST"
+ *     pointers are ordinary host memory; the caller owns every input and
+ *     output buffer, the library owns only its workspace (held by the
+ *     handle, grown on demand, released by bgw_destroy);
+ *   - `stream` is a hipStream_t (NULL = default stream); all GPU work is
+ *     enqueued asynchronously on it and the call returns without waiting;
+ *     calls on one handle must not overlap (they share the workspace);
+ *   - every function returns BGW_OK or a negative BGW_ERR_* code and sets a
+ *     thread-local message readable with bgw_last_error(); no C++ exception
+ *     crosses this interface.
+ *
+ * Units: energies and frequencies in eV (converted with 1 Ha =
+ * 27.211386245988 eV), lengths in bohr, Miller indices in reciprocal-
+ * lattice units with components in [-n/2, n/2) (paper, Appendix on file
+ * formats).
+ */
+#ifndef BGW_H
+#define BGW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BGW_OK 0
+#define BGW_ERR_ARG (-1)         /* null/negative/inconsistent argument, omega < 0 */
+#define BGW_ERR_ALIAS (-2)       /* FFT grid too small: some axis has n_i <= 2 max|gw_i| + max|ge_i| */
+#define BGW_ERR_SHAPE (-3)       /* duplicate G, component outside [-n/2, n/2), |q+G| = 0 */
+#define BGW_ERR_HIP (-4)         /* a HIP runtime call failed */
+#define BGW_ERR_NOMEM (-5)       /* workspace could not be allocated (or exceeds BGW_WORKSPACE_LIMIT) */
+#define BGW_ERR_UNSUPPORTED (-6) /* e.g. an FFT length that is not 2^a 3^b in [4, 128] */
+
+#define BGW_FP64 0               /* chi-sum on FP64 MFMA */
+#define BGW_SPLIT_BF16 1         /* chi-sum as split BF16 slices, FP32 accumulation, FP64 recombination */
+
+typedef struct bgw_handle_s *bgw_handle_t;
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int bgw_version(void);
+
+/* Create a handle bound to HIP device `hip_device`.  Allocates nothing on
+ * the GPU until the first compute call. */
+int bgw_create(bgw_handle_t *h, int hip_device);
+
+/* Release the handle and its workspace.  Waits for the handle's device to
+ * finish outstanding work first.  NULL is accepted. */
+int bgw_destroy(bgw_handle_t h);
+
+/* Message for the last non-zero return on the calling thread ("" if none). */
+const char *bgw_last_error(void);
+
+/* Bytes of device workspace the handle currently holds. */
+size_t bgw_workspace_bytes(bgw_handle_t h);
+
+/* ------------------------------------------------------------------------
+ * Pair densities (plane-wave matrix elements)
+ *
+ * M_t(G) = <v,k+q| e^{i(q+G).r} |c,k>  (epsilon section, matrix-element
+ * equation) for every pair t = (k*nv + v)*nc + c, computed the paper's way
+ * (the FFT rewrite of the same section): the bands are taken to real space,
+ * the product conj(u_v(r)) u_c(r) is formed on the n1 x n2 x n3 grid and
+ * Fourier transformed back, and the dielectric-sphere entries are kept:
+ *     u_n(r_j) = sum_{G in wfn sphere} C_n(G) exp(+2 pi i m_G . j / n)
+ *     M_t(G)   = (1/N) sum_j conj(u_v(r_j)) u_c(r_j) exp(+2 pi i m_G . j / n)
+ * This equals the matrix element exactly when no axis aliases, i.e.
+ * n_i > 2 max|gw_i| + max|ge_i| for i = 1..3 (else BGW_ERR_ALIAS).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int n[3];          /* FFT grid; each n_i = 2^a 3^b with 4 <= n_i <= 128 */
+    int ngw;           /* wavefunction sphere size */
+    const int *gw;     /* HOST int32 [ngw][3] Miller indices of the coefficients */
+    int ng;            /* dielectric sphere size (columns of M) */
+    const int *ge;     /* HOST int32 [ng][3] Miller indices of the outputs */
+    int nk, nv, nc;    /* k-points, valence bands (at k+q), conduction bands (at k) */
+    const double *cv;  /* DEVICE complex128 [nk][nv][ngw]: valence at k+q */
+    const double *cc;  /* DEVICE complex128 [nk][nc][ngw]: conduction at k */
+} bgw_pair_desc;
+
+/* Host-only validation of a descriptor (sizes, null pointers, G-vector
+ * ranges and duplicates, alias-free grid).  Touches no GPU and no
+ * coefficient memory.  Returns BGW_OK or the code bgw_pair_density would. */
+int bgw_pair_desc_check(const bgw_pair_desc *d);
+
+/* M: DEVICE complex128 [nk*nv*nc][ng] (pair-major), written in full.
+ * Must not overlap cv/cc.  Deterministic: identical inputs give bitwise
+ * identical M. */
+int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Polarizability chi0_GG'(q, omega)
+ *
+ * Static chi equation of the epsilon section, with its compact form
+ * chi = M^H diag(w) M over the composite pair index (n, n', k), and the
+ * implicit 1/(N_k V_uc) of every k sum (GW-BSE overview) passed in as
+ * `prefactor`:
+ *     chi_GG'(omega) = prefactor * sum_t conj(M_t(G)) w_t(omega) M_t(G')
+ *     w_t(omega)     = Delta_t / (Delta_t^2 + omega^2),
+ *     Delta_t        = E_{v,k+q} - E_{c,k}  (hartree; < 0 for insulators)
+ * omega = 0 is the static case 1/Delta; omega > 0 is the imaginary-axis
+ * value, i.e. the paper's retarded/advanced bracket evaluated at E = i omega
+ * with vanishing broadening.  chi is Hermitian; the full matrix is
+ * returned (lower triangle = conjugate mirror of the upper one).  Row and
+ * column `head` (the index of G = 0, or -1) are always computed in FP64 from
+ * M, also in split precision, because v(q0+0) ~ 1/q0^2 amplifies them.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int ng;              /* rows/cols of chi for this q (uneven across q allowed) */
+    int nk, nv, nc;      /* pair count K = nk*nv*nc, t = (k*nv + v)*nc + c */
+    const double *M;     /* DEVICE complex128 [K][ng], e.g. from bgw_pair_density */
+    const double *ev;    /* DEVICE f64 [nk][nv], valence energies at k+q (eV) */
+    const double *ec;    /* DEVICE f64 [nk][nc], conduction energies at k (eV) */
+    int head;            /* index of G = 0 in this q's list, -1 if absent */
+    double prefactor;    /* usually 1/(N_k V_uc) in bohr^-3 */
+    double *chi;         /* DEVICE complex128 [nw][ng][ng], output */
+} bgw_chi_q;
+
+typedef struct {
+    int nq;              /* number of q entries, >= 1 */
+    const bgw_chi_q *q;  /* HOST array [nq] */
+    int nw;              /* number of frequencies, >= 1 */
+    const double *omega; /* HOST f64 [nw], imaginary-axis |omega| in eV, >= 0 */
+    int precision;       /* BGW_FP64 or BGW_SPLIT_BF16 */
+    int accumulate;      /* 0: chi = result; 1: chi += result (K-chunked sums) */
+} bgw_chi_desc;
+
+int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Dielectric matrix and its inverse
+ *
+ * epsilon_GG'(omega) = delta_GG' - v(q+G) chi_GG'(omega)   (epsilon section,
+ * dielectric-matrix equation, asymmetric Coulomb form), then epsilon^-1 by
+ * elimination with partial pivoting (the paper inverts with ZGESV).  The
+ * pivot sequence is that of LU with partial pivoting (largest |Re|+|Im|,
+ * first index on ties).  info[w] = 0 on success, i > 0 if the i-th pivot
+ * (1-based) is exactly zero; epsinv[w] is then unspecified.
+ * ---------------------------------------------------------------------- */
+/* vcoul: DEVICE f64 [ng]; chi: DEVICE complex128 [nw][ng][ng];
+ * epsinv: DEVICE complex128 [nw][ng][ng], may be the same pointer as chi
+ * (in-place); info: DEVICE int32 [nw]. */
+int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
+                double *epsinv, int *info, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Per-kernel timing.  When enabled, every kernel launch (or launch group)
+ * of the compute calls is bracketed by HIP events recorded on the call's
+ * stream.  bgw_get_timing waits for the recorded events, adds their elapsed
+ * times to the kernel's totals and returns the totals since the last reset.
+ * ---------------------------------------------------------------------- */
+#define BGW_KERNEL_BAND 0        /* band G -> r transforms */
+#define BGW_KERNEL_PAIR 1        /* pair product + FFT + sphere gather */
+#define BGW_KERNEL_WEIGHTS 2     /* energy weights */
+#define BGW_KERNEL_HERK 3        /* FP64 chi-sum (rank-K update) */
+#define BGW_KERNEL_FINALIZE 4    /* split reduction, prefactor, Hermitian mirror */
+#define BGW_KERNEL_SPLIT_SLICE 5 /* BF16 slicing of M (split precision) */
+#define BGW_KERNEL_SPLIT_HERK 6  /* BF16 chi-sum with FP64 recombination */
+#define BGW_KERNEL_HEADWING 7    /* FP64 head/wing row of chi (split precision) */
+#define BGW_KERNEL_EPS_BUILD 8   /* epsilon = 1 - v chi */
+#define BGW_KERNEL_INVERT 9      /* whole epsilon inversion (all panels) */
+#define BGW_KERNEL_COUNT 10
+
+int bgw_set_timing(bgw_handle_t h, int enable);
+/* total_ms and launches may be NULL.  Unknown kernel id: BGW_ERR_ARG. */
+int bgw_get_timing(bgw_handle_t h, int kernel, double *total_ms, long long *launches);
+int bgw_reset_timing(bgw_handle_t h);
+
+/* Host helper: bulk bare Coulomb v(q+G) = 4 pi / |q+G|^2 (epsilon section,
+ * untruncated bare-Coulomb equation).  bvec: HOST f64 [3][3], rows are the
+ * reciprocal lattice vectors in bohr^-1; q: HOST f64 [3] in crystal units;
+ * ge: HOST int32 [ng][3]; v: HOST f64 [ng].  BGW_ERR_SHAPE if |q+G| = 0. */
+int bgw_vcoul_bulk(const double *bvec, const double *q, int ng, const int *ge, double *v);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BGW_H */

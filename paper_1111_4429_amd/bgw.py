@@ -1,0 +1,293 @@
+"""ctypes binding of libbgw (include/bgw.h): argument marshalling only.
+
+Device buffers are torch tensors on a HIP device (``torch.complex128`` for
+complex arrays, ``torch.float64`` for energies/Coulomb, ``torch.int32`` for
+``info``); G-vector lists and frequencies are host numpy arrays.  Every call
+is enqueued on ``torch.cuda.current_stream()``.  There is no fallback: if the
+native library is missing or the GPU is absent, calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbgw.so")
+
+BGW_OK = 0
+BGW_ERR_ARG = -1
+BGW_ERR_ALIAS = -2
+BGW_ERR_SHAPE = -3
+BGW_ERR_HIP = -4
+BGW_ERR_NOMEM = -5
+BGW_ERR_UNSUPPORTED = -6
+FP64 = 0
+SPLIT_BF16 = 1
+
+# every symbol declared in include/bgw.h
+EXPORTS = [
+    "bgw_version", "bgw_create", "bgw_destroy", "bgw_last_error", "bgw_workspace_bytes",
+    "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
+    "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
+]
+
+KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
+           "invert"]
+
+
+class BgwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bgw error {code}: {msg}")
+        self.code = code
+
+
+class PairDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int * 3),
+        ("ngw", ctypes.c_int),
+        ("gw", ctypes.c_void_p),
+        ("ng", ctypes.c_int),
+        ("ge", ctypes.c_void_p),
+        ("nk", ctypes.c_int),
+        ("nv", ctypes.c_int),
+        ("nc", ctypes.c_int),
+        ("cv", ctypes.c_void_p),
+        ("cc", ctypes.c_void_p),
+    ]
+
+
+class ChiQ(ctypes.Structure):
+    _fields_ = [
+        ("ng", ctypes.c_int),
+        ("nk", ctypes.c_int),
+        ("nv", ctypes.c_int),
+        ("nc", ctypes.c_int),
+        ("M", ctypes.c_void_p),
+        ("ev", ctypes.c_void_p),
+        ("ec", ctypes.c_void_p),
+        ("head", ctypes.c_int),
+        ("prefactor", ctypes.c_double),
+        ("chi", ctypes.c_void_p),
+    ]
+
+
+class ChiDesc(ctypes.Structure):
+    _fields_ = [
+        ("nq", ctypes.c_int),
+        ("q", ctypes.POINTER(ChiQ)),
+        ("nw", ctypes.c_int),
+        ("omega", ctypes.POINTER(ctypes.c_double)),
+        ("precision", ctypes.c_int),
+        ("accumulate", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libbgw.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"native library {LIB_PATH} is missing; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        L.bgw_version.restype = I
+        L.bgw_create.argtypes = [ctypes.POINTER(P), I]
+        L.bgw_destroy.argtypes = [P]
+        L.bgw_last_error.restype = ctypes.c_char_p
+        L.bgw_workspace_bytes.argtypes = [P]
+        L.bgw_workspace_bytes.restype = ctypes.c_size_t
+        L.bgw_pair_desc_check.argtypes = [ctypes.POINTER(PairDesc)]
+        L.bgw_pair_density.argtypes = [P, ctypes.POINTER(PairDesc), P, P]
+        L.bgw_chi0.argtypes = [P, ctypes.POINTER(ChiDesc), P]
+        L.bgw_eps_inv.argtypes = [P, I, I, P, P, P, P, P]
+        L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
+        L.bgw_set_timing.argtypes = [P, I]
+        L.bgw_get_timing.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+        L.bgw_reset_timing.argtypes = [P]
+        for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
+                  "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing"):
+            getattr(L, f).restype = I
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != BGW_OK:
+        raise BgwError(rc, lib().bgw_last_error().decode())
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _dptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_pair_desc(n, gw, ge, cv=None, cc=None, nk=None, nv=None, nc=None):
+    """Build a PairDesc; gw/ge host int arrays, cv/cc device tensors (or None
+    for host-only validation, in which case nk/nv/nc must be given)."""
+    gw = _host_i32(gw)
+    ge = _host_i32(ge)
+    d = PairDesc()
+    nn = (n, n, n) if np.isscalar(n) else tuple(n)
+    d.n = (ctypes.c_int * 3)(*nn)
+    d.ngw = gw.shape[0]
+    d.gw = gw.ctypes.data
+    d.ng = ge.shape[0]
+    d.ge = ge.ctypes.data
+    if cv is not None:
+        nk, nv = int(cv.shape[0]), int(cv.shape[1])
+        nc = int(cc.shape[1])
+    d.nk, d.nv, d.nc = int(nk), int(nv), int(nc)
+    d.cv = _dptr(cv) if cv is not None else 1
+    d.cc = _dptr(cc) if cc is not None else 1
+    d._keep = (gw, ge)  # keep host arrays alive
+    return d
+
+
+def pair_desc_check(n, gw, ge, nk=1, nv=1, nc=1) -> int:
+    """Host-only validation; returns the BGW code (no GPU needed)."""
+    d = make_pair_desc(n, gw, ge, nk=nk, nv=nv, nc=nc)
+    return int(lib().bgw_pair_desc_check(ctypes.byref(d)))
+
+
+def vcoul_bulk(bvec, q, ge) -> np.ndarray:
+    bvec = np.ascontiguousarray(bvec, dtype=np.float64)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    ge = _host_i32(ge)
+    out = np.zeros(ge.shape[0])
+    _check(lib().bgw_vcoul_bulk(bvec.ctypes.data, q.ctypes.data, ge.shape[0], ge.ctypes.data, out.ctypes.data))
+    return out
+
+
+class Handle:
+    """A bgw handle bound to one HIP device (owns the workspace)."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available: the bgw library has no CPU path")
+        self.device = device
+        self._h = ctypes.c_void_p()
+        _check(lib().bgw_create(ctypes.byref(self._h), device))
+
+    def close(self):
+        if self._h:
+            lib().bgw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        return int(lib().bgw_workspace_bytes(self._h))
+
+    # ---------------------------------------------------------------- timing
+    def set_timing(self, enable: bool = True):
+        _check(lib().bgw_set_timing(self._h, 1 if enable else 0))
+
+    def reset_timing(self):
+        _check(lib().bgw_reset_timing(self._h))
+
+    def timing(self) -> dict:
+        """{kernel name: (total ms, launches)} accumulated since the last reset."""
+        out = {}
+        for i, name in enumerate(KERNELS):
+            ms = ctypes.c_double()
+            n = ctypes.c_longlong()
+            _check(lib().bgw_get_timing(self._h, i, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
+
+    # ---------------------------------------------------------------- pair densities
+    def pair_density(self, n, gw, ge, cv, cc, M=None):
+        """M[t][G] (complex128, device) for t = (k*nv + v)*nc + c."""
+        import torch
+        assert cv.dtype == torch.complex128 and cc.dtype == torch.complex128
+        assert cv.is_contiguous() and cc.is_contiguous()
+        nk, nv, ngw = cv.shape
+        nc = cc.shape[1]
+        assert cc.shape == (nk, nc, ngw) and len(gw) == ngw
+        ng = len(ge)
+        if M is None:
+            M = torch.empty((nk * nv * nc, ng), dtype=torch.complex128, device=cv.device)
+        assert M.shape == (nk * nv * nc, ng) and M.is_contiguous() and M.dtype == torch.complex128
+        d = make_pair_desc(n, gw, ge, cv, cc)
+        _check(lib().bgw_pair_density(self._h, ctypes.byref(d), _dptr(M), _stream()))
+        return M
+
+    # ---------------------------------------------------------------- chi0
+    def chi0(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64, accumulate: bool = False,
+             chis: Optional[List] = None):
+        """qs: list of dicts {M, ev, ec, nk, nv, nc, head, prefactor} (device tensors).
+        Returns the list of chi tensors [nw][ng][ng] (complex128)."""
+        import torch
+        om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1)
+        arr = (ChiQ * len(qs))()
+        outs = []
+        keep = []
+        for i, q in enumerate(qs):
+            M = q["M"]
+            ng = int(M.shape[1])
+            K = int(q["nk"]) * int(q["nv"]) * int(q["nc"])
+            assert M.shape[0] == K and M.dtype == torch.complex128 and M.is_contiguous()
+            ev = q["ev"].contiguous()
+            ec = q["ec"].contiguous()
+            assert ev.dtype == torch.float64 and ec.dtype == torch.float64
+            assert ev.numel() == q["nk"] * q["nv"] and ec.numel() == q["nk"] * q["nc"]
+            chi = None if chis is None else chis[i]
+            if chi is None:
+                chi = torch.empty((om.size, ng, ng), dtype=torch.complex128, device=M.device)
+            assert chi.shape == (om.size, ng, ng) and chi.is_contiguous()
+            keep += [ev, ec]
+            arr[i].ng = ng
+            arr[i].nk, arr[i].nv, arr[i].nc = int(q["nk"]), int(q["nv"]), int(q["nc"])
+            arr[i].M = _dptr(M)
+            arr[i].ev = _dptr(ev)
+            arr[i].ec = _dptr(ec)
+            arr[i].head = int(q.get("head", -1))
+            arr[i].prefactor = float(q["prefactor"])
+            arr[i].chi = _dptr(chi)
+            outs.append(chi)
+        d = ChiDesc()
+        d.nq = len(qs)
+        d.q = arr
+        d.nw = om.size
+        d.omega = om.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.precision = int(precision)
+        d.accumulate = 1 if accumulate else 0
+        _check(lib().bgw_chi0(self._h, ctypes.byref(d), _stream()))
+        return outs
+
+    # ---------------------------------------------------------------- eps^-1
+    def eps_inv(self, vcoul, chi, epsinv=None, info=None):
+        """epsilon^-1 for every frequency; returns (epsinv, info) device tensors."""
+        import torch
+        if chi.dim() == 2:
+            chi = chi.unsqueeze(0)
+        nw, ng, _ = chi.shape
+        assert chi.dtype == torch.complex128 and chi.is_contiguous()
+        assert vcoul.dtype == torch.float64 and vcoul.numel() == ng
+        if epsinv is None:
+            epsinv = torch.empty_like(chi)
+        if info is None:
+            info = torch.empty(nw, dtype=torch.int32, device=chi.device)
+        _check(lib().bgw_eps_inv(self._h, ng, nw, _dptr(vcoul.contiguous()), _dptr(chi), _dptr(epsinv),
+                                 _dptr(info), _stream()))
+        return epsinv, info

@@ -1,0 +1,540 @@
+// C-ABI entry points (include/bgw.h): argument validation, the handle with its
+// workspace and plan cache, and the sequencing of the kernels on the caller's
+// stream.  No arithmetic of the method happens on the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace bgw {
+
+// ---- kernels' launchers (fft.hip, chi.hip, eps.hip)
+size_t band_lds_bytes(const AxisPlan &, const AxisPlan &, const AxisPlan &, int bwz, int lc);
+size_t pair_lds_bytes(const AxisPlan &, const AxisPlan &, const AxisPlan &, int bez, int lc);
+int launch_band_to_real(const double2 *C, int nbands, int ngw, const AxisPlan &, const AxisPlan &,
+                        const AxisPlan &, const SphereMaps &, int lc, double2 *grids, hipStream_t);
+int launch_pair_fft(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
+                    const AxisPlan &, const AxisPlan &, const SphereMaps &, int lc, double2 *M, long long row0,
+                    hipStream_t);
+int launch_weights(const double *ev, const double *ec, int nk, int nv, int nc, double omega_ev, double *w,
+                   hipStream_t);
+int herk_f64_splits(long long K, int ng);
+int launch_herk_f64(const double2 *M, long long K, int ng, const double *w, int nsplit, double2 *part,
+                    hipStream_t);
+int launch_chi_finalize(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
+                        hipStream_t);
+int launch_eps_build(const double2 *chi, const double *v, int ng, int nw, double2 *eps, hipStream_t);
+size_t gje_workspace_bytes(int n, int nmat, int R);
+int gje_rows_per_wg(int n);
+int gje_max_group(int n);
+int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t);
+int split_workspace_bytes(long long K, int ng, size_t *bytes);
+int launch_chi_split(const double2 *M, long long K, int ng, const double *w, int head, double pf, double2 *chi,
+                     int accumulate, void *ws, hipStream_t);
+
+namespace {
+thread_local std::string g_err;
+constexpr int kMaxNg = 8192;
+constexpr size_t kLdsBudget = 150 * 1024;
+}  // namespace
+
+void set_error(const std::string &msg) { g_err = msg; }
+void clear_error() { g_err.clear(); }
+
+static int fail(int code, const std::string &msg) {
+    set_error(msg);
+    return code;
+}
+
+// ---------------------------------------------------------------- validation (host only)
+
+static bool is_2a3b(int n) {
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+static int check_glist(const int *g, int count, const int n[3], const char *what, int maxabs[3]) {
+    maxabs[0] = maxabs[1] = maxabs[2] = 0;
+    std::vector<long long> keys((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        long long key = 0;
+        for (int d = 0; d < 3; ++d) {
+            const int m = g[3 * i + d];
+            if (m < -n[d] / 2 || m >= n[d] - n[d] / 2)
+                return fail(BGW_ERR_SHAPE, std::string(what) + ": Miller index outside [-n/2, n/2)");
+            maxabs[d] = std::max(maxabs[d], std::abs(m));
+            key = key * 512 + (m + 256);
+        }
+        keys[(size_t)i] = key;
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+        return fail(BGW_ERR_SHAPE, std::string(what) + ": duplicate G-vector");
+    return BGW_OK;
+}
+
+}  // namespace bgw
+
+using namespace bgw;
+
+extern "C" int bgw_pair_desc_check(const bgw_pair_desc *d) {
+    clear_error();
+    if (!d) return fail(BGW_ERR_ARG, "null descriptor");
+    for (int i = 0; i < 3; ++i) {
+        if (d->n[i] < 1) return fail(BGW_ERR_ARG, "FFT grid dimensions must be positive");
+        if (!is_2a3b(d->n[i]) || d->n[i] < 4 || d->n[i] > kMaxFFT)
+            return fail(BGW_ERR_UNSUPPORTED, "FFT grid dimensions must be 2^a 3^b in [4, 128]");
+    }
+    if (d->ngw < 1 || d->ng < 1 || d->nk < 1 || d->nv < 1 || d->nc < 1)
+        return fail(BGW_ERR_ARG, "ngw, ng, nk, nv, nc must be >= 1");
+    if (!d->gw || !d->ge || !d->cv || !d->cc) return fail(BGW_ERR_ARG, "null pointer in descriptor");
+    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "dielectric sphere larger than 8192 G-vectors");
+    int mw[3], me[3];
+    BGW_TRY(check_glist(d->gw, d->ngw, d->n, "wavefunction sphere", mw));
+    BGW_TRY(check_glist(d->ge, d->ng, d->n, "dielectric sphere", me));
+    for (int i = 0; i < 3; ++i)
+        if (d->n[i] <= 2 * mw[i] + me[i])
+            return fail(BGW_ERR_ALIAS, "FFT grid too small: need n_i > 2 max|gw_i| + max|ge_i| on every axis");
+    return BGW_OK;
+}
+
+extern "C" int bgw_vcoul_bulk(const double *bvec, const double *q, int ng, const int *ge, double *v) {
+    clear_error();
+    if (!bvec || !q || !ge || !v || ng < 1) return fail(BGW_ERR_ARG, "bad arguments to bgw_vcoul_bulk");
+    for (int g = 0; g < ng; ++g) {
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < 3; ++i) {
+            const double m = q[i] + ge[3 * g + i];
+            for (int c = 0; c < 3; ++c) x[c] += m * bvec[3 * i + c];
+        }
+        const double q2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+        if (!(q2 > 0.0)) return fail(BGW_ERR_SHAPE, "|q+G| = 0 in bgw_vcoul_bulk");
+        v[g] = 4.0 * M_PI / q2;
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_version(void) { return 100; }
+
+extern "C" const char *bgw_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- handle, plans, workspace
+
+namespace bgw {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct FFTPlan {
+    AxisPlan ax[3];
+    SphereMaps sm;
+    std::vector<std::unique_ptr<DevBuf>> bufs;
+};
+
+}  // namespace bgw
+
+struct bgw_handle_s {
+    int device = 0;
+    DevBuf ws;
+    std::map<std::string, std::unique_ptr<bgw::FFTPlan>> plans;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double total_ms[BGW_KERNEL_COUNT] = {};
+    long long launches[BGW_KERNEL_COUNT] = {};
+    ~bgw_handle_s() {
+        for (auto &p : pending) {
+            pool.push_back(p.second.first);
+            pool.push_back(p.second.second);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace bgw {
+
+static int upload(FFTPlan &pl, const void *host, size_t bytes, const void **dev) {
+    auto b = std::make_unique<DevBuf>();
+    BGW_HIP(hipMalloc(&b->p, std::max<size_t>(bytes, 16)));
+    b->bytes = bytes;
+    if (bytes) BGW_HIP(hipMemcpy(b->p, host, bytes, hipMemcpyHostToDevice));
+    *dev = b->p;
+    pl.bufs.push_back(std::move(b));
+    return BGW_OK;
+}
+
+static void radices(int n, int *nrad, int *rad) {
+    int k = 0;
+    while (n % 4 == 0) { rad[k++] = 4; n /= 4; }
+    while (n % 2 == 0) { rad[k++] = 2; n /= 2; }
+    while (n % 3 == 0) { rad[k++] = 3; n /= 3; }
+    *nrad = k;
+}
+
+static size_t env_limit() {
+    const char *s = std::getenv("BGW_WORKSPACE_LIMIT");
+    if (!s || !*s) return (size_t)-1;
+    return (size_t)std::strtoull(s, nullptr, 10);
+}
+
+static int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st) {
+    if (h->ws.bytes >= bytes) return BGW_OK;
+    if (bytes > env_limit()) return fail(BGW_ERR_NOMEM, "workspace request exceeds BGW_WORKSPACE_LIMIT");
+    BGW_HIP(hipStreamSynchronize(st));
+    if (h->ws.p) {
+        BGW_HIP(hipFree(h->ws.p));
+        h->ws.p = nullptr;
+        h->ws.bytes = 0;
+    }
+    if (hipMalloc(&h->ws.p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        h->ws.p = nullptr;
+        return fail(BGW_ERR_NOMEM, "device workspace allocation failed (" + std::to_string(bytes) + " bytes)");
+    }
+    h->ws.bytes = bytes;
+    return BGW_OK;
+}
+
+static std::string plan_key(const bgw_pair_desc *d) {
+    // grid + exact G lists (FNV-1a over the index bytes)
+    unsigned long long hw = 1469598103934665603ull, he = hw;
+    const unsigned char *pw = reinterpret_cast<const unsigned char *>(d->gw);
+    for (size_t i = 0; i < sizeof(int) * 3 * (size_t)d->ngw; ++i) hw = (hw ^ pw[i]) * 1099511628211ull;
+    const unsigned char *pe = reinterpret_cast<const unsigned char *>(d->ge);
+    for (size_t i = 0; i < sizeof(int) * 3 * (size_t)d->ng; ++i) he = (he ^ pe[i]) * 1099511628211ull;
+    return std::to_string(d->n[0]) + "x" + std::to_string(d->n[1]) + "x" + std::to_string(d->n[2]) + ":" +
+           std::to_string(d->ngw) + ":" + std::to_string(hw) + ":" + std::to_string(d->ng) + ":" + std::to_string(he);
+}
+
+static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
+    const std::string key = plan_key(d);
+    auto it = h->plans.find(key);
+    if (it != h->plans.end()) {
+        *out = it->second.get();
+        return BGW_OK;
+    }
+    auto pl = std::make_unique<FFTPlan>();
+    // twiddles exp(+2 pi i j / n), evaluated in long double and rounded once
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int a = 0; a < 3; ++a) {
+        const int n = d->n[a];
+        std::vector<double2> tw((size_t)n);
+        for (int j = 0; j < n; ++j) {
+            const long double ang = 2.0L * pi * (long double)j / (long double)n;
+            tw[(size_t)j] = make_double2((double)cosl(ang), (double)sinl(ang));
+        }
+        pl->ax[a].n = n;
+        radices(n, &pl->ax[a].nrad, pl->ax[a].rad);
+        const void *dp = nullptr;
+        BGW_TRY(upload(*pl, tw.data(), sizeof(double2) * n, &dp));
+        pl->ax[a].tw = (const double2 *)dp;
+    }
+    const int n1 = d->n[0], n2 = d->n[1];
+    auto mod = [](int m, int n) { return ((m % n) + n) % n; };
+    // wavefunction sticks along x, keyed by (my, mz), entries in ascending G order
+    int rwz = 0;
+    for (int g = 0; g < d->ngw; ++g) rwz = std::max(rwz, std::abs(d->gw[3 * g + 2]));
+    std::map<std::pair<int, int>, std::vector<int>> sticks;
+    for (int g = 0; g < d->ngw; ++g) sticks[{d->gw[3 * g + 1], d->gw[3 * g + 2]}].push_back(g);
+    std::vector<int> start, sg, smx, syz;
+    start.push_back(0);
+    for (auto &kv : sticks) {
+        for (int g : kv.second) {
+            sg.push_back(g);
+            smx.push_back(mod(d->gw[3 * g], n1));
+        }
+        start.push_back((int)sg.size());
+        syz.push_back(mod(kv.first.first, n2) | ((kv.first.second + rwz) << 16));
+    }
+    SphereMaps &sm = pl->sm;
+    sm.nstick = (int)syz.size();
+    sm.rwz = rwz;
+    sm.bwz = 2 * rwz + 1;
+    const void *dp = nullptr;
+    BGW_TRY(upload(*pl, start.data(), sizeof(int) * start.size(), &dp));
+    sm.stick_start = (const int *)dp;
+    BGW_TRY(upload(*pl, sg.data(), sizeof(int) * sg.size(), &dp));
+    sm.stick_g = (const int *)dp;
+    BGW_TRY(upload(*pl, smx.data(), sizeof(int) * smx.size(), &dp));
+    sm.stick_mx = (const int *)dp;
+    BGW_TRY(upload(*pl, syz.data(), sizeof(int) * syz.size(), &dp));
+    sm.stick_yz = (const int *)dp;
+    int rez = 0;
+    for (int g = 0; g < d->ng; ++g) rez = std::max(rez, std::abs(d->ge[3 * g + 2]));
+    std::vector<int> code((size_t)d->ng);
+    for (int g = 0; g < d->ng; ++g)
+        code[(size_t)g] = mod(d->ge[3 * g], n1) | (mod(d->ge[3 * g + 1], n2) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
+    BGW_TRY(upload(*pl, code.data(), sizeof(int) * code.size(), &dp));
+    sm.ge_code = (const int *)dp;
+    sm.ng = d->ng;
+    sm.rez = rez;
+    sm.bez = 2 * rez + 1;
+    *out = pl.get();
+    h->plans[key] = std::move(pl);
+    return BGW_OK;
+}
+
+static int pick_lc(int n2, int n3, size_t fixed_bytes) {
+    // lines per z chunk: all n2 if the LDS budget allows
+    if (fixed_bytes >= kLdsBudget) return 0;
+    const size_t per_line = 2 * sizeof(double2) * (size_t)n3;
+    const int lc = (int)std::min<size_t>(n2, (kLdsBudget - fixed_bytes) / per_line);
+    return lc;
+}
+
+static hipEvent_t take_event(bgw_handle_t h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a start event on construction and an end event on destruction.
+struct Timed {
+    bgw_handle_t h;
+    int id;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(bgw_handle_t h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
+        if (h->timing && (a = take_event(h)) != nullptr) (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(h);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        h->pending.push_back({id, {a, b}});
+    }
+};
+
+static int set_device(bgw_handle_t h) {
+    BGW_HIP(hipSetDevice(h->device));
+    return BGW_OK;
+}
+
+}  // namespace bgw
+
+extern "C" int bgw_create(bgw_handle_t *h, int hip_device) {
+    clear_error();
+    if (!h) return fail(BGW_ERR_ARG, "null handle pointer");
+    *h = nullptr;
+    int count = 0;
+    BGW_HIP(hipGetDeviceCount(&count));
+    if (hip_device < 0 || hip_device >= count) return fail(BGW_ERR_ARG, "no such HIP device");
+    auto *hh = new (std::nothrow) bgw_handle_s();
+    if (!hh) return fail(BGW_ERR_NOMEM, "out of host memory");
+    hh->device = hip_device;
+    *h = hh;
+    return BGW_OK;
+}
+
+extern "C" int bgw_destroy(bgw_handle_t h) {
+    clear_error();
+    if (!h) return BGW_OK;
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    delete h;
+    return BGW_OK;
+}
+
+extern "C" size_t bgw_workspace_bytes(bgw_handle_t h) { return h ? h->ws.bytes : 0; }
+
+extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream) {
+    BGW_TRY(bgw_pair_desc_check(d));
+    if (!h || !M) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    FFTPlan *pl = nullptr;
+    BGW_TRY(get_plan(h, d, &pl));
+    const AxisPlan &px = pl->ax[0], &py = pl->ax[1], &pz = pl->ax[2];
+    const int n2 = d->n[1], n3 = d->n[2];
+    const size_t fixed_b = band_lds_bytes(px, py, pz, pl->sm.bwz, 0) + sizeof(int) * n3;
+    const size_t fixed_p = pair_lds_bytes(px, py, pz, pl->sm.bez, 0);
+    const int lcb = pick_lc(n2, n3, fixed_b), lcp = pick_lc(n2, n3, fixed_p);
+    if (lcb < 1 || lcp < 1) return fail(BGW_ERR_UNSUPPORTED, "FFT grid/sphere too large for the LDS budget");
+
+    const size_t N = (size_t)d->n[0] * n2 * n3;
+    const size_t per_k = sizeof(double2) * N * (size_t)(d->nv + d->nc);
+    size_t free_b = 0, total_b = 0;
+    BGW_HIP(hipMemGetInfo(&free_b, &total_b));
+    size_t budget = std::min(env_limit(), h->ws.bytes + (size_t)(0.85 * (double)free_b));
+    int kb = (int)std::min<size_t>((size_t)d->nk, budget / per_k);
+    if (kb < 1) return fail(BGW_ERR_NOMEM, "workspace for one k-point of band grids does not fit");
+    BGW_TRY(ensure_ws(h, per_k * kb, st));
+    double2 *gv = (double2 *)h->ws.p;
+    const double2 *cv = (const double2 *)d->cv, *cc = (const double2 *)d->cc;
+    for (int k0 = 0; k0 < d->nk; k0 += kb) {
+        const int kn = std::min(kb, d->nk - k0);
+        double2 *gc = gv + (size_t)kn * d->nv * N;
+        {
+            Timed tm(h, BGW_KERNEL_BAND, st);
+            BGW_TRY(launch_band_to_real(cv + (size_t)k0 * d->nv * d->ngw, kn * d->nv, d->ngw, px, py, pz, pl->sm,
+                                        lcb, gv, st));
+            BGW_TRY(launch_band_to_real(cc + (size_t)k0 * d->nc * d->ngw, kn * d->nc, d->ngw, px, py, pz, pl->sm,
+                                        lcb, gc, st));
+        }
+        {
+            Timed tm(h, BGW_KERNEL_PAIR, st);
+            BGW_TRY(launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M,
+                                    (long long)k0 * d->nv * d->nc, st));
+        }
+    }
+    return BGW_OK;
+}
+
+static int check_chi_desc(const bgw_chi_desc *d) {
+    if (!d || d->nq < 1 || !d->q || d->nw < 1 || !d->omega) return fail(BGW_ERR_ARG, "bad chi descriptor");
+    if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16)
+        return fail(BGW_ERR_ARG, "unknown precision");
+    for (int i = 0; i < d->nw; ++i)
+        if (!(d->omega[i] >= 0.0)) return fail(BGW_ERR_ARG, "frequencies must be >= 0");
+    for (int i = 0; i < d->nq; ++i) {
+        const bgw_chi_q &q = d->q[i];
+        if (q.ng < 1 || q.nk < 1 || q.nv < 1 || q.nc < 1) return fail(BGW_ERR_ARG, "chi q entry: sizes must be >= 1");
+        if (q.ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "chi q entry: ng > 8192");
+        if (!q.M || !q.ev || !q.ec || !q.chi) return fail(BGW_ERR_ARG, "chi q entry: null pointer");
+        if (q.head < -1 || q.head >= q.ng) return fail(BGW_ERR_ARG, "chi q entry: head index out of range");
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
+    clear_error();
+    BGW_TRY(check_chi_desc(d));
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    // workspace: weights [K] + partial sums
+    size_t need = 0;
+    for (int i = 0; i < d->nq; ++i) {
+        const bgw_chi_q &q = d->q[i];
+        const long long K = (long long)q.nk * q.nv * q.nc;
+        size_t b = 0;
+        if (d->precision == BGW_FP64) {
+            const int ns = herk_f64_splits(K, q.ng);
+            b = 256 + sizeof(double) * K + sizeof(double2) * (size_t)ns * q.ng * q.ng;
+        } else {
+            BGW_TRY(split_workspace_bytes(K, q.ng, &b));
+            b += 256 + sizeof(double) * K;
+        }
+        need = std::max(need, b);
+    }
+    BGW_TRY(ensure_ws(h, need, st));
+    for (int i = 0; i < d->nq; ++i) {
+        const bgw_chi_q &q = d->q[i];
+        const long long K = (long long)q.nk * q.nv * q.nc;
+        double *w = (double *)h->ws.p;
+        void *rest = (char *)h->ws.p + ((sizeof(double) * K + 255) / 256) * 256;
+        for (int iw = 0; iw < d->nw; ++iw) {
+            double2 *chi = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
+            {
+                Timed tm(h, BGW_KERNEL_WEIGHTS, st);
+                BGW_TRY(launch_weights(q.ev, q.ec, q.nk, q.nv, q.nc, d->omega[iw], w, st));
+            }
+            if (d->precision == BGW_FP64) {
+                const int ns = herk_f64_splits(K, q.ng);
+                double2 *part = (double2 *)rest;
+                {
+                    Timed tm(h, BGW_KERNEL_HERK, st);
+                    BGW_TRY(launch_herk_f64((const double2 *)q.M, K, q.ng, w, ns, part, st));
+                }
+                Timed tm(h, BGW_KERNEL_FINALIZE, st);
+                BGW_TRY(launch_chi_finalize(part, ns, q.ng, q.prefactor, chi, d->accumulate, st));
+            } else {
+                BGW_TRY(launch_chi_split((const double2 *)q.M, K, q.ng, w, q.head, q.prefactor, chi, d->accumulate,
+                                         rest, st));
+            }
+        }
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi, double *epsinv,
+                           int *info, void *stream) {
+    clear_error();
+    if (!h || ng < 1 || nw < 1 || !vcoul || !chi || !epsinv || !info)
+        return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    const int group = std::max(1, std::min(nw, gje_max_group(ng)));
+    const int rows = gje_rows_per_wg(ng);
+    const int R = (ng + rows - 1) / rows;
+    const size_t gws = gje_workspace_bytes(ng, group, R);
+    BGW_TRY(ensure_ws(h, gws + sizeof(int) * 2 * (size_t)group * ng + 512, st));
+    int *ipiv = (int *)((char *)h->ws.p + ((gws + 255) / 256) * 256);
+    {
+        Timed tm(h, BGW_KERNEL_EPS_BUILD, st);
+        BGW_TRY(launch_eps_build((const double2 *)chi, vcoul, ng, nw, (double2 *)epsinv, st));
+    }
+    Timed tm(h, BGW_KERNEL_INVERT, st);
+    for (int w0 = 0; w0 < nw; w0 += group) {
+        const int gn = std::min(group, nw - w0);
+        BGW_TRY(launch_gje_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, info + w0, h->ws.p, ipiv, st));
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_set_timing(bgw_handle_t h, int enable) {
+    clear_error();
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    h->timing = enable != 0;
+    return BGW_OK;
+}
+
+static int drain_timing(bgw_handle_t h) {
+    for (auto &p : h->pending) {
+        BGW_HIP(hipEventSynchronize(p.second.second));
+        float ms = 0.f;
+        BGW_HIP(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        h->total_ms[p.first] += ms;
+        h->launches[p.first] += 1;
+        h->pool.push_back(p.second.first);
+        h->pool.push_back(p.second.second);
+    }
+    h->pending.clear();
+    return BGW_OK;
+}
+
+extern "C" int bgw_get_timing(bgw_handle_t h, int kernel, double *total_ms, long long *launches) {
+    clear_error();
+    if (!h || kernel < 0 || kernel >= BGW_KERNEL_COUNT) return fail(BGW_ERR_ARG, "bad handle or kernel id");
+    BGW_TRY(set_device(h));
+    BGW_TRY(drain_timing(h));
+    if (total_ms) *total_ms = h->total_ms[kernel];
+    if (launches) *launches = h->launches[kernel];
+    return BGW_OK;
+}
+
+extern "C" int bgw_reset_timing(bgw_handle_t h) {
+    clear_error();
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    BGW_TRY(set_device(h));
+    BGW_TRY(drain_timing(h));
+    for (int i = 0; i < BGW_KERNEL_COUNT; ++i) {
+        h->total_ms[i] = 0.0;
+        h->launches[i] = 0;
+    }
+    return BGW_OK;
+}

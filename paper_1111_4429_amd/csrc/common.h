@@ -1,0 +1,76 @@
+// Internal definitions shared by the HIP translation units of libbgw.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "bgw.h"
+
+namespace bgw {
+
+// thread-local error message (bgw_last_error)
+void set_error(const std::string &msg);
+void clear_error();
+
+#define BGW_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            ::bgw::set_error(std::string("HIP error in ") + #call + ": " + hipGetErrorString(e_)); \
+            return BGW_ERR_HIP;                                                                    \
+        }                                                                                          \
+    } while (0)
+
+#define BGW_TRY(expr)              \
+    do {                           \
+        int rc_ = (expr);          \
+        if (rc_ != BGW_OK) return rc_; \
+    } while (0)
+
+constexpr double kHartreeEv = 27.211386245988;  // CODATA 2018
+constexpr int kMaxFFT = 128;
+
+// ---------------------------------------------------------------- complex helpers
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// ---------------------------------------------------------------- FFT plans
+// One axis of a 3D transform: length n = product of radices (each 2, 3 or 4),
+// twiddle table tw[j] = exp(+2 pi i j / n), j in [0, n), in device memory.
+struct AxisPlan {
+    int n;
+    int nrad;
+    int rad[8];
+    const double2 *tw;
+};
+
+// Sphere description used by the kernels (device pointers).
+struct SphereMaps {
+    // wavefunction sphere grouped in sticks along x: stick s covers
+    // stick_g[stick_start[s] .. stick_start[s+1]) (indices into the coefficient
+    // list), with yz position stick_yz[s] = (my mod n2) | (iz << 16), iz = mz + Rwz,
+    // and stick_mx[g] = mx mod n1 for each entry.
+    int nstick;
+    const int *stick_start;
+    const int *stick_g;
+    const int *stick_mx;
+    const int *stick_yz;
+    int bwz, rwz;          // wavefunction box extent along z (2 Rwz + 1), Rwz
+    // dielectric sphere outputs: ge_code[g] = (mx mod n1) | ((my mod n2) << 8) | (iz << 16),
+    // iz = mz + Rez
+    int ng;
+    const int *ge_code;
+    int bez, rez;          // dielectric box extent along z, Rez
+};
+
+}  // namespace bgw

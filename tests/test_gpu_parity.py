@@ -1,0 +1,318 @@
+"""GPU parity of the HIP path against the oracle, through the C-ABI.
+
+Bar (FP64 path): relative Frobenius error <= 1e-12 per result (M per q,
+chi and epsilon^-1 per (q, omega)).  Full-size workloads are checked on
+sampled pairs / sampled (G, G') blocks the oracle computes one by one, and
+by properties that hold at any size.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1111_4429_amd import bgw, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def handle(torch_dev):
+    h = bgw.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(torch_dev, a):
+    torch, d = torch_dev
+    return torch.from_numpy(np.ascontiguousarray(a)).to(d)
+
+
+def gpu_M(h, torch_dev, s, iq=0, n=None):
+    q = s["qs"][iq]
+    M = h.pair_density(s["n"] if n is None else n, s["gw"], q["ge"], dev(torch_dev, q["cv"]), dev(torch_dev, s["cc"]))
+    return M
+
+
+def gpu_chi(h, torch_dev, s, M, omega, iq=0, precision=bgw.FP64):
+    q = s["qs"][iq]
+    pf = 1.0 / (s["nk"] * s["vol"])
+    (chi,) = h.chi0([dict(M=M, ev=dev(torch_dev, q["ev"]), ec=dev(torch_dev, s["ec"]), nk=s["nk"], nv=s["nv"],
+                          nc=s["nc"], head=0, prefactor=pf)], omega, precision=precision)
+    return chi
+
+
+@pytest.fixture(scope="module")
+def tiny(torch_dev, handle):
+    s = synth.make_system(synth.WORKLOADS["tiny-static-16"])
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    om = np.array([0.0, 3.0, 25.0])
+    chi = gpu_chi(handle, torch_dev, s, M, om)
+    v = bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])
+    einv, info = handle.eps_inv(dev(torch_dev, v), chi)
+    torch = torch_dev[0]
+    torch.cuda.synchronize()
+    return dict(s=s, M=M.cpu().numpy(), chi=chi.cpu().numpy(), einv=einv.cpu().numpy(), info=info.cpu().numpy(),
+                om=om, v=v)
+
+
+# ---------------------------------------------------------------- pair densities
+
+
+def test_pair_density_tiny_full(tiny):
+    s = tiny["s"]
+    q = s["qs"][0]
+    ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    assert rel(tiny["M"], ref) <= TOL
+    # per-pair bound too (every row, not just the aggregate)
+    for t in range(ref.shape[0]):
+        assert rel(tiny["M"][t], ref[t]) <= 10 * TOL
+
+
+def test_pair_density_ragged_noncubic_multik(torch_dev, handle):
+    """Non-cubic grid (12 x 18 x 16), ng = 51 (not a tile multiple), nk = 3."""
+    s = synth.small_system(n=16, ngw=123, ng=51, nv=3, nc=5, nk=3, seed=21)
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s, n=(12, 18, 16)).cpu().numpy()
+    ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    assert rel(M, ref) <= TOL
+
+
+def test_pair_density_kbatch_bitwise(torch_dev, handle):
+    """Forcing several k-batches (small workspace cap) changes nothing."""
+    s = synth.small_system(n=16, ngw=181, ng=65, nv=2, nc=7, nk=5, seed=8)
+    full = gpu_M(handle, torch_dev, s).cpu().numpy()
+    per_k = 16 * 16 ** 3 * (2 + 7)
+    os.environ["BGW_WORKSPACE_LIMIT"] = str(2 * per_k + 1)
+    try:
+        h2 = bgw.Handle(0)
+        batched = gpu_M(h2, torch_dev, s).cpu().numpy()
+        h2.close()
+    finally:
+        del os.environ["BGW_WORKSPACE_LIMIT"]
+    assert np.array_equal(full, batched)
+    q = s["qs"][0]
+    assert rel(full, oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])) <= TOL
+
+
+def test_pair_density_single_plane_waves(torch_dev, handle):
+    """C_v = delta(G, Ga), C_c = delta(G, Gb)  =>  M(G) = delta(G, Ga - Gb)."""
+    gw = synth.gvector_list(81)
+    ge = synth.gvector_list(33)
+    cv = np.zeros((1, 3, 81), complex)
+    cc = np.zeros((1, 4, 81), complex)
+    for i, a in enumerate([0, 5, 20]):
+        cv[0, i, a] = 1
+    for i, b in enumerate([1, 7, 0, 30]):
+        cc[0, i, b] = 1
+    M = handle.pair_density(16, gw, ge, dev(torch_dev, cv), dev(torch_dev, cc)).cpu().numpy()
+    ref = oracle.pair_density(gw, ge, cv, cc)
+    assert np.abs(M - ref).max() < 1e-15
+
+
+def test_pair_density_degenerate_sizes(torch_dev, handle):
+    """One pair, one output G (the head), and a one-G wavefunction sphere."""
+    s = synth.small_system(n=8, ngw=27, ng=1, nv=1, nc=1, nk=1, seed=2)
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s).cpu().numpy()
+    ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    assert M.shape == (1, 1) and abs(M[0, 0] - ref[0, 0]) <= 1e-15
+    gw1 = np.zeros((1, 3), np.int32)
+    c1 = np.full((1, 2, 1), 0.5 + 0.25j)
+    c2 = np.full((1, 1, 1), -1.0 + 2.0j)
+    M1 = handle.pair_density(4, gw1, gw1, dev(torch_dev, c1), dev(torch_dev, c2)).cpu().numpy()
+    assert np.allclose(M1, oracle.pair_density(gw1, gw1, c1, c2), rtol=1e-15, atol=0)
+
+
+def test_pair_density_silicon_like_sampled(torch_dev, handle):
+    """Full 48^3 / Ng = 1500 / K = 102400 run; 48 sampled pairs vs the oracle."""
+    s = synth.make_system(synth.WORKLOADS["silicon-like-48"])
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    K = s["nk"] * s["nv"] * s["nc"]
+    rng = np.random.default_rng(0)
+    pairs = np.unique(np.concatenate([[0, K - 1], rng.integers(0, K, 46)]))
+    ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
+    got = M[torch_dev[0].from_numpy(pairs).to(M.device)].cpu().numpy()
+    assert rel(got, ref) <= TOL
+    # properties at full size: |M_t(G)| <= |C_v| |C_c| = 1 (Cauchy-Schwarz on the
+    # convolution), and the shifted-grid head |M_t(G=0)| = |<v,k+q|c,k>| <= |q| (1 + O(q))
+    absM = M.abs()
+    assert float(absM.max()) <= 1.0 + 1e-12
+    assert float(absM[:, 0].max()) <= 1.01 * np.linalg.norm(q["q"])
+
+
+# ---------------------------------------------------------------- chi
+
+
+def test_chi_tiny_vs_oracle(tiny):
+    s = tiny["s"]
+    q = s["qs"][0]
+    pf = 1.0 / (s["nk"] * s["vol"])
+    w = oracle.weights(q["ev"], s["ec"], tiny["om"])
+    # chi-sum parity on the same M
+    ref = oracle.chi(tiny["M"], w, pf)
+    for i in range(len(tiny["om"])):
+        assert rel(tiny["chi"][i], ref[i]) <= TOL
+    # end to end: oracle M -> oracle chi
+    Mo = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    ref2 = oracle.chi(Mo, w, pf)
+    for i in range(len(tiny["om"])):
+        assert rel(tiny["chi"][i], ref2[i]) <= TOL
+        x = tiny["chi"][i]
+        assert np.array_equal(x, x.conj().T)  # exact Hermitian by construction
+        assert np.linalg.eigvalsh(x).max() <= 1e-14 * np.abs(x).max()
+
+
+def test_chi_ragged_frequencies(torch_dev, handle):
+    s = synth.small_system(n=16, ngw=151, ng=97, nv=3, nc=7, nk=2, seed=4)
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    om = np.array([0.0, 0.5, 7.0, 60.0, 100.0])
+    chi = gpu_chi(handle, torch_dev, s, M, om).cpu().numpy()
+    w = oracle.weights(q["ev"], s["ec"], om)
+    ref = oracle.chi(M.cpu().numpy(), w, 1.0 / (s["nk"] * s["vol"]))
+    for i in range(len(om)):
+        assert rel(chi[i], ref[i]) <= TOL
+
+
+def test_chi_accumulate_kchunks(torch_dev, handle):
+    """chi over k-points 0..1 then accumulate k-points 2..3 equals the one-shot sum."""
+    torch = torch_dev[0]
+    s = synth.small_system(n=16, ngw=151, ng=77, nv=2, nc=6, nk=4, seed=6)
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    pf = 1.0 / (s["nk"] * s["vol"])
+    om = [0.0, 10.0]
+    full = gpu_chi(handle, torch_dev, s, M, om)
+    half = 2 * s["nv"] * s["nc"]
+
+    def part(rows, ks, acc, chis=None):
+        return handle.chi0([dict(M=M[rows].contiguous(), ev=dev(torch_dev, q["ev"][ks]), ec=dev(torch_dev, s["ec"][ks]),
+                                 nk=2, nv=s["nv"], nc=s["nc"], head=0, prefactor=pf)], om, accumulate=acc, chis=chis)
+
+    (c,) = part(slice(0, half), slice(0, 2), False)
+    (c,) = part(slice(half, None), slice(2, 4), True, chis=[c])
+    torch.cuda.synchronize()
+    assert rel(c.cpu().numpy(), full.cpu().numpy()) <= 1e-13
+
+
+def test_chi_silicon_like_sampled_block(torch_dev, handle):
+    """Full 48^3 chi (Ng = 1500, K = 102400); a 40 x 40 block incl. head and
+    last index vs the oracle summed one entry at a time from the same M."""
+    s = synth.make_system(synth.WORKLOADS["silicon-like-48"])
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    chi = gpu_chi(handle, torch_dev, s, M, [0.0])[0].cpu().numpy()
+    ng = q["ng"]
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([[0, ng - 1], rng.integers(0, ng, 38)])).astype(np.int32)
+    cols = np.unique(np.concatenate([[0, 63, 64, ng - 1], rng.integers(0, ng, 36)])).astype(np.int32)
+    w = oracle.weights(q["ev"], s["ec"], [0.0])
+    ref = oracle.chi(M.cpu().numpy(), w, 1.0 / (s["nk"] * s["vol"]), rows=rows, cols=cols)[0]
+    assert rel(chi[np.ix_(rows, cols)], ref) <= TOL
+    assert np.array_equal(chi, chi.conj().T)
+    assert np.linalg.eigvalsh(chi).max() <= 1e-14 * np.abs(chi).max()
+
+
+# ---------------------------------------------------------------- epsilon^-1
+
+
+def test_eps_inv_tiny(tiny):
+    s = tiny["s"]
+    assert np.all(tiny["info"] == 0)
+    ref, info = oracle.eps_inv(tiny["v"], tiny["chi"])
+    assert np.all(info == 0)
+    for i in range(len(tiny["om"])):
+        assert rel(tiny["einv"][i], ref[i]) <= TOL
+        W = tiny["einv"][i] * tiny["v"][None, :]
+        assert np.linalg.norm(W - W.conj().T) <= 1e-12 * np.linalg.norm(W)
+
+
+def test_eps_inv_pivoting_and_batch(torch_dev, handle):
+    """Random non-Hermitian chi (pivoting needed), 6 frequencies, n = 129."""
+    rng = np.random.default_rng(5)
+    n, nw = 129, 6
+    chi = (rng.standard_normal((nw, n, n)) + 1j * rng.standard_normal((nw, n, n))) * 0.3
+    chi[:, :5, :5] = 0  # zero leading block: first pivots come from below
+    v = rng.uniform(0.5, 2.0, n)
+    einv, info = handle.eps_inv(dev(torch_dev, v), dev(torch_dev, chi))
+    einv = einv.cpu().numpy()
+    ref, rinfo = oracle.eps_inv(v, chi)
+    assert np.all(info.cpu().numpy() == 0) and np.all(rinfo == 0)
+    for i in range(nw):
+        assert rel(einv[i], ref[i]) <= TOL
+
+
+def test_eps_inv_singular_info(torch_dev, handle):
+    """eps with an exactly zero pivot: info = 1-based index, other frequencies fine."""
+    n = 70
+    d = np.linspace(1.0, 2.0, n)
+    chi = np.zeros((2, n, n), complex)
+    chi[0] = np.diag(1 - d)
+    chi[1] = np.diag(1 - d)
+    chi[1, 40, 40] = 1.0  # eps_40,40 = 1 - 1*1 = 0, rows below have no entry in column 40
+    v = np.ones(n)
+    _, info = handle.eps_inv(dev(torch_dev, v), dev(torch_dev, chi))
+    assert list(info.cpu().numpy()) == [0, 41]
+    _, rinfo = oracle.eps_inv(v, chi)
+    assert list(rinfo) == [0, 41]
+
+
+def test_eps_inv_in_place(torch_dev, handle):
+    torch = torch_dev[0]
+    rng = np.random.default_rng(9)
+    n = 100
+    chi = -(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    chi = chi @ chi.conj().T / n
+    v = rng.uniform(0.1, 3.0, n)
+    t = dev(torch_dev, chi[None])
+    einv, info = handle.eps_inv(dev(torch_dev, v), t, epsinv=t)
+    torch.cuda.synchronize()
+    ref, _ = oracle.eps_inv(v, chi[None])
+    assert rel(t.cpu().numpy()[0], ref[0]) <= TOL
+
+
+def test_eps_inv_silicon_like(torch_dev, handle):
+    """Full Ng = 1500 inversion from the GPU chi vs the oracle elimination."""
+    s = synth.make_system(synth.WORKLOADS["silicon-like-48"])
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    chi = gpu_chi(handle, torch_dev, s, M, [0.0])
+    v = bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])
+    einv, info = handle.eps_inv(dev(torch_dev, v), chi)
+    einv = einv.cpu().numpy()[0]
+    assert int(info.cpu().numpy()[0]) == 0
+    ref, rinfo = oracle.eps_inv(v, chi.cpu().numpy())
+    assert rinfo[0] == 0
+    assert rel(einv, ref[0]) <= TOL
+    # blocks of the q -> 0 structure (head, wing, wing', body) separately
+    for blk in [(slice(0, 1), slice(0, 1)), (slice(1, None), slice(0, 1)), (slice(0, 1), slice(1, None)),
+                (slice(1, None), slice(1, None))]:
+        assert rel(einv[blk], ref[0][blk]) <= 10 * TOL
+
+
+def test_pipeline_bitwise_deterministic(torch_dev, handle, tiny):
+    s = tiny["s"]
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    chi = gpu_chi(handle, torch_dev, s, M, tiny["om"])
+    einv, _ = handle.eps_inv(dev(torch_dev, tiny["v"]), chi)
+    assert np.array_equal(M.cpu().numpy(), tiny["M"])
+    assert np.array_equal(chi.cpu().numpy(), tiny["chi"])
+    assert np.array_equal(einv.cpu().numpy(), tiny["einv"])
