@@ -25,6 +25,11 @@ int launch_band_to_real(const double2 *C, int nbands, int ngw, const AxisPlan &,
 int launch_pair_fft(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
                     const AxisPlan &, const AxisPlan &, const SphereMaps &, int lc, double2 *M, long long row0,
                     hipStream_t);
+int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
+                     const AxisPlan &, const AxisPlan &, const int *ge_code2, int ng, int rey, int rez, double2 *M,
+                     long long row0, hipStream_t);
+int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &, const AxisPlan &,
+                         const AxisPlan &, const SphereMaps &, int rwy, double2 *grids, hipStream_t);
 int launch_weights(const double *ev, const double *ec, int nk, int nv, int nc, double omega_ev, double *w,
                    hipStream_t);
 int herk_f64_splits(long long K, int ng);
@@ -249,11 +254,14 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
     const int n1 = d->n[0], n2 = d->n[1];
     auto mod = [](int m, int n) { return ((m % n) + n) % n; };
     // wavefunction sticks along x, keyed by (my, mz), entries in ascending G order
-    int rwz = 0;
-    for (int g = 0; g < d->ngw; ++g) rwz = std::max(rwz, std::abs(d->gw[3 * g + 2]));
+    int rwz = 0, rwy = 0;
+    for (int g = 0; g < d->ngw; ++g) {
+        rwz = std::max(rwz, std::abs(d->gw[3 * g + 2]));
+        rwy = std::max(rwy, std::abs(d->gw[3 * g + 1]));
+    }
     std::map<std::pair<int, int>, std::vector<int>> sticks;
     for (int g = 0; g < d->ngw; ++g) sticks[{d->gw[3 * g + 1], d->gw[3 * g + 2]}].push_back(g);
-    std::vector<int> start, sg, smx, syz;
+    std::vector<int> start, sg, smx, syz, syz2;
     start.push_back(0);
     for (auto &kv : sticks) {
         for (int g : kv.second) {
@@ -262,6 +270,7 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
         }
         start.push_back((int)sg.size());
         syz.push_back(mod(kv.first.first, n2) | ((kv.first.second + rwz) << 16));
+        syz2.push_back((kv.first.first + rwy) | ((kv.first.second + rwz) << 16));
     }
     SphereMaps &sm = pl->sm;
     sm.nstick = (int)syz.size();
@@ -276,13 +285,24 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
     sm.stick_mx = (const int *)dp;
     BGW_TRY(upload(*pl, syz.data(), sizeof(int) * syz.size(), &dp));
     sm.stick_yz = (const int *)dp;
-    int rez = 0;
-    for (int g = 0; g < d->ng; ++g) rez = std::max(rez, std::abs(d->ge[3 * g + 2]));
-    std::vector<int> code((size_t)d->ng);
-    for (int g = 0; g < d->ng; ++g)
+    BGW_TRY(upload(*pl, syz2.data(), sizeof(int) * syz2.size(), &dp));
+    sm.stick_yz2 = (const int *)dp;
+    sm.rwy = rwy;
+    int rez = 0, rey = 0;
+    for (int g = 0; g < d->ng; ++g) {
+        rez = std::max(rez, std::abs(d->ge[3 * g + 2]));
+        rey = std::max(rey, std::abs(d->ge[3 * g + 1]));
+    }
+    std::vector<int> code((size_t)d->ng), code2((size_t)d->ng);
+    for (int g = 0; g < d->ng; ++g) {
         code[(size_t)g] = mod(d->ge[3 * g], n1) | (mod(d->ge[3 * g + 1], n2) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
+        code2[(size_t)g] = mod(d->ge[3 * g], n1) | ((d->ge[3 * g + 1] + rey) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
+    }
     BGW_TRY(upload(*pl, code.data(), sizeof(int) * code.size(), &dp));
     sm.ge_code = (const int *)dp;
+    BGW_TRY(upload(*pl, code2.data(), sizeof(int) * code2.size(), &dp));
+    sm.ge_code2 = (const int *)dp;
+    sm.rey = rey;
     sm.ng = d->ng;
     sm.rez = rez;
     sm.bez = 2 * rez + 1;
@@ -327,6 +347,12 @@ struct Timed {
         h->pending.push_back({id, {a, b}});
     }
 };
+
+// BGW_GENERIC_FFT=1 forces the generic (any 2^a 3^b length) transform kernels.
+static bool generic_fft() {
+    const char *s = std::getenv("BGW_GENERIC_FFT");
+    return s && *s == '1';
+}
 
 static int set_device(bgw_handle_t h) {
     BGW_HIP(hipSetDevice(h->device));
@@ -389,15 +415,26 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
         double2 *gc = gv + (size_t)kn * d->nv * N;
         {
             Timed tm(h, BGW_KERNEL_BAND, st);
-            BGW_TRY(launch_band_to_real(cv + (size_t)k0 * d->nv * d->ngw, kn * d->nv, d->ngw, px, py, pz, pl->sm,
-                                        lcb, gv, st));
-            BGW_TRY(launch_band_to_real(cc + (size_t)k0 * d->nc * d->ngw, kn * d->nc, d->ngw, px, py, pz, pl->sm,
-                                        lcb, gc, st));
+            const double2 *cvk = cv + (size_t)k0 * d->nv * d->ngw, *cck = cc + (size_t)k0 * d->nc * d->ngw;
+            int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
+                                   : launch_band_to_real2(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gv, st);
+            if (rc == BGW_ERR_UNSUPPORTED) {
+                BGW_TRY(launch_band_to_real(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, lcb, gv, st));
+                BGW_TRY(launch_band_to_real(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, lcb, gc, st));
+            } else {
+                BGW_TRY(rc);
+                BGW_TRY(launch_band_to_real2(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gc, st));
+            }
         }
         {
             Timed tm(h, BGW_KERNEL_PAIR, st);
-            BGW_TRY(launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M,
-                                    (long long)k0 * d->nv * d->nc, st));
+            const long long row0 = (long long)k0 * d->nv * d->nc;
+            int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
+                                   : launch_pair_fft2(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm.ge_code2, d->ng,
+                                                      pl->sm.rey, pl->sm.rez, (double2 *)M, row0, st);
+            if (rc == BGW_ERR_UNSUPPORTED)
+                rc = launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M, row0, st);
+            BGW_TRY(rc);
         }
     }
     return BGW_OK;

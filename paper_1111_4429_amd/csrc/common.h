@@ -65,12 +65,16 @@ struct SphereMaps {
     const int *stick_g;
     const int *stick_mx;
     const int *stick_yz;
+    const int *stick_yz2;  // (my + Rwy) | (iz << 16): box row instead of FFT row
     int bwz, rwz;          // wavefunction box extent along z (2 Rwz + 1), Rwz
+    int rwy;               // wavefunction box half-extent along y
     // dielectric sphere outputs: ge_code[g] = (mx mod n1) | ((my mod n2) << 8) | (iz << 16),
     // iz = mz + Rez
     int ng;
     const int *ge_code;
+    const int *ge_code2;   // (mx mod n1) | ((my + Rey) << 8) | ((mz + Rez) << 16)
     int bez, rez;          // dielectric box extent along z, Rez
+    int rey;               // dielectric box half-extent along y
 };
 
 }  // namespace bgw

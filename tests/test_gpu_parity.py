@@ -110,6 +110,24 @@ def test_pair_density_kbatch_bitwise(torch_dev, handle):
     assert rel(full, oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])) <= TOL
 
 
+@pytest.mark.parametrize("n", [16, 24, 32, 48, 64])
+def test_pair_density_fast_and_generic_kernels(torch_dev, handle, n):
+    """Both transform paths (compile-time-size kernels and the generic
+    any-length kernels) against the oracle on every fast grid length."""
+    ngw = {16: 181, 24: 411, 32: 411, 48: 881, 64: 881}[n]
+    s = synth.small_system(n=n, ngw=ngw, ng=113, nv=2, nc=3, nk=2, seed=n)
+    q = s["qs"][0]
+    ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    fast = gpu_M(handle, torch_dev, s).cpu().numpy()
+    os.environ["BGW_GENERIC_FFT"] = "1"
+    try:
+        generic = gpu_M(handle, torch_dev, s).cpu().numpy()
+    finally:
+        del os.environ["BGW_GENERIC_FFT"]
+    assert rel(fast, ref) <= TOL
+    assert rel(generic, ref) <= TOL
+
+
 def test_pair_density_single_plane_waves(torch_dev, handle):
     """C_v = delta(G, Ga), C_c = delta(G, Gb)  =>  M(G) = delta(G, Ga - Gb)."""
     gw = synth.gvector_list(81)
