@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="silicon-like-48")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-pairs", type=int, default=256)
+    ap.add_argument("--cpu-sample-pairs", type=int, default=6400)
+    ap.add_argument("--split-reps", type=int, default=3)
+    ap.add_argument("--no-split", action="store_true")
     return ap.parse_args()
 
 
@@ -102,6 +104,56 @@ def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
                    f"{ng}x{ng} entries ({t_c:.2f} s), extrapolated x{scale:.0f}; plus one full {ng}x{ng} "
                    f"inversion ({t_i:.2f} s); extrapolated step {t_step:.1f} s"),
         "cpu": _cpu_model(),
+    }
+
+
+def split_vs_fp64(torch, h, bgw, qd, omega, chi64, ng, K, reps):
+    """Split-BF16 vs FP64 chi-sum on the same resident M (whole chi0 calls,
+    HIP events on the launch stream), with the relative Frobenius error of
+    the split result against the FP64 one."""
+    chisp = torch.empty_like(chi64)
+    res = {}
+    for name, prec, buf in (("fp64", bgw.FP64, chi64), ("split", bgw.SPLIT_BF16, chisp)):
+        h.chi0([qd], omega, precision=prec, chis=[buf])  # warm-up
+        torch.cuda.synchronize()
+        h.reset_timing()
+        h.set_timing(True)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            h.chi0([qd], omega, precision=prec, chis=[buf])
+        e1.record()
+        torch.cuda.synchronize()
+        h.set_timing(False)
+        res[name] = (e0.elapsed_time(e1) / reps, h.timing())
+    err = float(torch.linalg.vector_norm(chisp - chi64) / torch.linalg.vector_norm(chi64))
+    head_err = float(torch.linalg.vector_norm(chisp[:, 0] - chi64[:, 0]) / torch.linalg.vector_norm(chi64[:, 0]))
+    nw = chi64.shape[0]
+    flops = 4.0 * ng * ng * K * nw
+    gpad = (ng + 63) // 64 * 64
+    tiles = (gpad // 64) * (gpad // 64 + 1) // 2
+    nchunk = (K + 127) // 128
+    issued = tiles * 64.0 * 64.0 * nchunk * 256 * 2 * 20 * nw
+    tsp = res["split"][1]
+    herk_ms = tsp["split_herk"][0] / reps
+    t64 = res["fp64"][0]
+    tspl = res["split"][0]
+    return {
+        "fp64_chi_ms": t64,
+        "split_chi_ms": tspl,
+        "speedup": t64 / tspl,
+        "rel_err_vs_fp64": err,
+        "head_row_rel_err": head_err,
+        "bar": 1e-9,
+        "meets_bar": err <= 1e-9,
+        "split_slice_ms": tsp["split_slice"][0] / reps,
+        "split_herk_ms": herk_ms,
+        "split_headwing_ms": tsp["headwing"][0] / reps,
+        "split_finalize_ms": tsp["finalize"][0] / reps,
+        "split_chi_TFLOPs_fp64_equiv": flops / (tspl * 1e-3) / 1e12,
+        "split_herk_bf16_issued_TFLOPs": issued / (herk_ms * 1e-3) / 1e12,
+        "split_herk_frac_bf16_peak": issued / (herk_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
     }
 
 
@@ -248,6 +300,8 @@ def main():
         "split": None,
         "cpu_baseline": None,
     }
+    if not args.no_split:
+        out["split"] = split_vs_fp64(torch, h, bgw, qd, s["omega"], chi, ng, K, args.split_reps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_pairs, chi_flops)

@@ -43,8 +43,14 @@ int gje_rows_per_wg(int n);
 int gje_max_group(int n);
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t);
 int split_workspace_bytes(long long K, int ng, size_t *bytes);
-int launch_chi_split(const double2 *M, long long K, int ng, const double *w, int head, double pf, double2 *chi,
-                     int accumulate, void *ws, hipStream_t);
+SplitLayout split_layout(long long K, int ng, void *ws);
+int launch_split_slices(const SplitLayout &, const double2 *M, long long K, int ng, const double *w, long long t0,
+                        int nch, hipStream_t);
+int launch_split_gemm(const SplitLayout &, int ng, int nch, int add, int *used, hipStream_t);
+int launch_split_headwing(const SplitLayout &, const double2 *M, long long K, int ng, int head, const double *w,
+                          double pf, double2 *chi, int accumulate, hipStream_t);
+int launch_chi_finalize_skip(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
+                             int skip, hipStream_t);
 
 namespace {
 thread_local std::string g_err;
@@ -499,8 +505,30 @@ extern "C" int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
                 Timed tm(h, BGW_KERNEL_FINALIZE, st);
                 BGW_TRY(launch_chi_finalize(part, ns, q.ng, q.prefactor, chi, d->accumulate, st));
             } else {
-                BGW_TRY(launch_chi_split((const double2 *)q.M, K, q.ng, w, q.head, q.prefactor, chi, d->accumulate,
-                                         rest, st));
+                const SplitLayout L = split_layout(K, q.ng, rest);
+                int nslots = 0;  // slots initialised by the first (largest) super-chunk
+                for (long long t0 = 0; t0 < K; t0 += L.sc_pairs) {
+                    const long long kn = std::min<long long>(L.sc_pairs, K - t0);
+                    const int nch = (int)((kn + 127) / 128);
+                    {
+                        Timed tm(h, BGW_KERNEL_SPLIT_SLICE, st);
+                        BGW_TRY(launch_split_slices(L, (const double2 *)q.M, K, q.ng, w, t0, nch, st));
+                    }
+                    Timed tm(h, BGW_KERNEL_SPLIT_HERK, st);
+                    int used = 0;
+                    BGW_TRY(launch_split_gemm(L, q.ng, nch, nslots ? 1 : 0, &used, st));
+                    if (!nslots) nslots = used;
+                }
+                {
+                    Timed tm(h, BGW_KERNEL_FINALIZE, st);
+                    BGW_TRY(launch_chi_finalize_skip(L.part, nslots, q.ng, q.prefactor, chi, d->accumulate, q.head,
+                                                     st));
+                }
+                if (q.head >= 0) {
+                    Timed tm(h, BGW_KERNEL_HEADWING, st);
+                    BGW_TRY(launch_split_headwing(L, (const double2 *)q.M, K, q.ng, q.head, w, q.prefactor, chi,
+                                                  d->accumulate, st));
+                }
             }
         }
     }

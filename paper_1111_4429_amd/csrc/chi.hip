@@ -124,12 +124,14 @@ __global__ __launch_bounds__(256) void k_herk_f64(const double2 *__restrict__ M,
 
 // chi[G][H] (+)= pf * sum_s part[s][G][H] for G <= H, conjugate mirror below the
 // diagonal, diagonal made exactly real.  The split sum runs in fixed order.
+// Row and column `skip` (>= 0) are left untouched (written by the FP64 head kernel).
 __global__ void k_chi_finalize(const double2 *__restrict__ part, int nsplit, int ng, double pf,
-                               double2 *__restrict__ chi, int accumulate) {
+                               double2 *__restrict__ chi, int accumulate, int skip) {
     const size_t total = (size_t)ng * ng;
     const size_t pstride = total;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const int G = (int)(e / ng), H = (int)(e % ng);
+        if (G == skip || H == skip) continue;
         const bool up = G <= H;
         const size_t src = up ? e : (size_t)H * ng + G;
         double2 s = make_double2(0.0, 0.0);
@@ -172,13 +174,18 @@ int launch_herk_f64(const double2 *M, long long K, int ng, const double *w, int 
     return BGW_OK;
 }
 
-int launch_chi_finalize(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
-                        hipStream_t st) {
+int launch_chi_finalize_skip(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
+                             int skip, hipStream_t st) {
     const size_t total = (size_t)ng * ng;
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_chi_finalize, dim3(blocks), dim3(256), 0, st, part, nsplit, ng, pf, chi, accumulate);
+    hipLaunchKernelGGL(k_chi_finalize, dim3(blocks), dim3(256), 0, st, part, nsplit, ng, pf, chi, accumulate, skip);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
+}
+
+int launch_chi_finalize(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
+                        hipStream_t st) {
+    return launch_chi_finalize_skip(part, nsplit, ng, pf, chi, accumulate, -1, st);
 }
 
 }  // namespace bgw

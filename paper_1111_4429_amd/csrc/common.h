@@ -77,4 +77,16 @@ struct SphereMaps {
     int rey;               // dielectric box half-extent along y
 };
 
+// Workspace carve-up of the split-precision chi sum (split.hip).
+struct SplitLayout {
+    int gpad, nt;
+    long long tiles;
+    long long sc_pairs;      // pairs per slice super-chunk (multiple of 128)
+    int nsplit;              // split slots of the partial sums
+    unsigned short *SA, *SB; // BF16 digit slices of X_w and X
+    int *EA, *EB;            // chunk-column exponents
+    double2 *part;           // [nsplit][ng][ng] FP64 partial sums
+    double2 *hw;             // FP64 head-row partials
+};
+
 }  // namespace bgw

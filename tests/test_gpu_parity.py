@@ -248,6 +248,74 @@ def test_chi_silicon_like_sampled_block(torch_dev, handle):
     assert np.linalg.eigvalsh(chi).max() <= 1e-14 * np.abs(chi).max()
 
 
+# ---------------------------------------------------------------- split precision
+
+SPLIT_TOL = 1e-9
+
+
+def test_split_chi_tiny(tiny, torch_dev, handle):
+    """Split BF16 chi-sum vs the oracle on the same M: <= 1e-9 per frequency;
+    the head row/column is the FP64 one."""
+    s = tiny["s"]
+    q = s["qs"][0]
+    M = dev(torch_dev, tiny["M"])
+    chi = gpu_chi(handle, torch_dev, s, M, tiny["om"], precision=bgw.SPLIT_BF16).cpu().numpy()
+    w = oracle.weights(q["ev"], s["ec"], tiny["om"])
+    ref = oracle.chi(tiny["M"], w, 1.0 / (s["nk"] * s["vol"]))
+    for i in range(len(tiny["om"])):
+        assert rel(chi[i], ref[i]) <= SPLIT_TOL
+        assert rel(chi[i][0], ref[i][0]) <= 1e-13 and rel(chi[i][:, 0], ref[i][:, 0]) <= 1e-13
+        assert np.array_equal(chi[i], chi[i].conj().T)
+
+
+def test_split_chi_ragged_superchunks(torch_dev, handle):
+    """K not a multiple of the 128-pair chunk, ng not a tile multiple, several
+    slice super-chunks (forced small), several frequencies, accumulate."""
+    torch = torch_dev[0]
+    s = synth.small_system(n=16, ngw=181, ng=93, nv=3, nc=11, nk=9, seed=13)  # K = 297
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    om = np.array([0.0, 2.0, 40.0])
+    w = oracle.weights(q["ev"], s["ec"], om)
+    pf = 1.0 / (s["nk"] * s["vol"])
+    ref = oracle.chi(M.cpu().numpy(), w, pf)
+    one = gpu_chi(handle, torch_dev, s, M, om, precision=bgw.SPLIT_BF16).cpu().numpy()
+    os.environ["BGW_SPLIT_SLICE_BYTES"] = str(5 * 256 * 128 * 2)  # one chunk per super-chunk
+    try:
+        many = gpu_chi(handle, torch_dev, s, M, om, precision=bgw.SPLIT_BF16).cpu().numpy()
+    finally:
+        del os.environ["BGW_SPLIT_SLICE_BYTES"]
+    for i in range(len(om)):
+        assert rel(one[i], ref[i]) <= SPLIT_TOL
+        assert rel(many[i], ref[i]) <= SPLIT_TOL
+    # accumulate: second call adds the same sum again
+    (c,) = handle.chi0([dict(M=M, ev=dev(torch_dev, q["ev"]), ec=dev(torch_dev, s["ec"]), nk=s["nk"], nv=s["nv"],
+                             nc=s["nc"], head=0, prefactor=pf)], om, precision=bgw.SPLIT_BF16)
+    handle.chi0([dict(M=M, ev=dev(torch_dev, q["ev"]), ec=dev(torch_dev, s["ec"]), nk=s["nk"], nv=s["nv"],
+                      nc=s["nc"], head=0, prefactor=pf)], om, precision=bgw.SPLIT_BF16, accumulate=True, chis=[c])
+    torch.cuda.synchronize()
+    c = c.cpu().numpy()
+    for i in range(len(om)):
+        assert rel(c[i], 2 * ref[i]) <= SPLIT_TOL
+
+
+def test_split_chi_silicon_like(torch_dev, handle):
+    """Full 48^3 workload: split chi vs the FP64 GPU chi and an oracle block."""
+    s = synth.make_system(synth.WORKLOADS["silicon-like-48"])
+    q = s["qs"][0]
+    M = gpu_M(handle, torch_dev, s)
+    c64 = gpu_chi(handle, torch_dev, s, M, [0.0])[0].cpu().numpy()
+    csp = gpu_chi(handle, torch_dev, s, M, [0.0], precision=bgw.SPLIT_BF16)[0].cpu().numpy()
+    assert rel(csp, c64) <= SPLIT_TOL
+    ng = q["ng"]
+    rows = np.array([0, 1, 700, ng - 1], dtype=np.int32)
+    cols = np.array([0, 5, 64, 1000, ng - 1], dtype=np.int32)
+    w = oracle.weights(q["ev"], s["ec"], [0.0])
+    ref = oracle.chi(M.cpu().numpy(), w, 1.0 / (s["nk"] * s["vol"]), rows=rows, cols=cols)[0]
+    assert rel(csp[np.ix_(rows, cols)], ref) <= SPLIT_TOL
+    assert rel(csp[0], c64[0]) <= 1e-13
+
+
 # ---------------------------------------------------------------- epsilon^-1
 
 
