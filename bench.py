@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-sample-pairs", type=int, default=6400)
     ap.add_argument("--split-reps", type=int, default=3)
     ap.add_argument("--no-split", action="store_true")
+    ap.add_argument("--no-full-grid", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (PMC byte-counter calibration)")
     return ap.parse_args()
 
 
@@ -105,6 +108,32 @@ def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
                    f"inversion ({t_i:.2f} s); extrapolated step {t_step:.1f} s"),
         "cpu": _cpu_model(),
     }
+
+
+def full_grid_pairs(torch, bgw, n, s, q, cv, cc, M, fft_bytes_nominal, reps=2):
+    """Pair densities on the caller's full FFT grid (BGW_FFT_BOX=full) instead of
+    the minimal alias-free box, for comparison: same M, more work."""
+    os.environ["BGW_FFT_BOX"] = "full"
+    try:
+        h2 = bgw.Handle(0)
+        ref = M.clone()
+        h2.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
+        torch.cuda.synchronize()
+        diff = float(torch.linalg.vector_norm(M - ref) / torch.linalg.vector_norm(ref))
+        h2.reset_timing()
+        h2.set_timing(True)
+        for _ in range(reps):
+            h2.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
+        torch.cuda.synchronize()
+        tm = h2.timing()
+        h2.close()
+    finally:
+        del os.environ["BGW_FFT_BOX"]
+    band = tm["band"][0] / reps
+    pair = (tm["pair"][0] + tm["pair_x"][0]) / reps
+    return {"grid": f"{n}^3", "band_ms": band, "pair_fft_ms": pair,
+            "pair_fft_GBs_algorithmic": fft_bytes_nominal / (pair * 1e-3) / 1e9,
+            "rel_diff_vs_minimal_box": diff}
 
 
 def split_vs_fp64(torch, h, bgw, qd, omega, chi64, ng, K, reps):
@@ -179,6 +208,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # 4 GiB read + 4 GiB written by one copy kernel, 3 times
+        nbytes = 4 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
+        return
     wl = synth.WORKLOADS[args.workload]
     print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
     s = synth.make_system(wl)
@@ -224,8 +263,12 @@ def main():
     assert int(info.cpu().max()) == 0 and int(info.cpu().min()) == 0
 
     ms_step = elapsed * 1e3 / args.steps
+    box = bgw.pair_transform_box(n, s["gw"], q["ge"])
+    Nb = box[0] * box[1] * box[2]
     chi_flops = 4.0 * ng * ng * K * nw
-    fft_bytes = K * 16.0 * (N + ng)
+    # algorithmic bytes of the pair transform on the box actually transformed
+    fft_bytes = K * 16.0 * (Nb + ng)
+    fft_bytes_nominal = K * 16.0 * (N + ng)
     lu_flops = 8.0 * ng ** 3 * nw
 
     def avg(name):
@@ -234,50 +277,56 @@ def main():
 
     pair_ms, pair_n = avg("pair")
     herk_ms, herk_n = avg("herk")
-    band_ms, band_n = avg("band")
-    inv_ms, inv_n = avg("invert")
     per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
-    # pair-FFT launches per step: one per k-batch; algorithmic bytes per launch
-    pair_launch_per_step = pair_n / args.steps
-    bytes_per_launch = fft_bytes / pair_launch_per_step
-    herk_per_step = herk_n / args.steps
-    flops_per_herk = chi_flops / herk_per_step
-
+    launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
+    herk_per_step = launches.get("herk", 1)
+    box_bytes = 16.0 * Nb
+    nbox = None
     stages = {
-        "pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0),
+        "pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
         "band_ms": per_step.get("band", 0),
         "pair_fft_ms": per_step.get("pair", 0),
+        "pair_x_ms": per_step.get("pair_x", 0),
         "chi_ms": per_step.get("weights", 0) + per_step.get("herk", 0) + per_step.get("finalize", 0),
         "herk_ms": per_step.get("herk", 0),
         "eps_inv_ms": per_step.get("eps_build", 0) + per_step.get("invert", 0),
-        "chi_sum_TFLOPs": chi_flops / (herk_ms * herk_per_step * 1e-3) / 1e12,
-        "chi_sum_frac_fp64_peak": chi_flops / (herk_ms * herk_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "pair_fft_GBs_algorithmic": fft_bytes / (pair_ms * pair_launch_per_step * 1e-3) / 1e9,
-        "pair_fft_nominal_TFLOPs": 5.0 * N * np.log2(N) * K / (pair_ms * pair_launch_per_step * 1e-3) / 1e12,
+        "chi_sum_TFLOPs": chi_flops / (per_step["herk"] * 1e-3) / 1e12,
+        "chi_sum_frac_fp64_peak": chi_flops / (per_step["herk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "pair_fft_GBs_algorithmic": fft_bytes / ((per_step.get("pair", 0) + per_step.get("pair_x", 0)) * 1e-3) / 1e9,
+        "pair_fft_nominal_TFLOPs": 5.0 * Nb * np.log2(Nb) * K
+        / ((per_step.get("pair", 0) + per_step.get("pair_x", 0)) * 1e-3) / 1e12,
         "eps_inv_TFLOPs": lu_flops / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
     }
     kernel_share = {k: per_step[k] / ms_step for k in per_step}
-    dominant = max(("pair", "herk", "invert", "band"), key=lambda k: per_step.get(k, 0))
-    fft_src = ["paper_1111_4429_amd/csrc/fft.hip", "paper_1111_4429_amd/csrc/common.h"]
-    chi_src = ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/common.h"]
-    if dominant == "pair":
-        ach = bytes_per_launch / (pair_ms * 1e-3) / 1e9
-        tr = load_traffic("pair", fft_src)
-        roof = {"kernel": "k_pair_fft", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS,
-                "traffic": None if tr is None else tr["bytes_per_launch"],
-                "algorithmic_bytes_per_launch": bytes_per_launch, "avg_launch_ms": pair_ms}
-    elif dominant == "herk":
-        ach = flops_per_herk / (herk_ms * 1e-3) / 1e12
-        tr = load_traffic("herk", chi_src)
-        roof = {"kernel": "k_herk_f64", "bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFLOPS,
-                "traffic": None if tr is None else tr["bytes_per_launch"],
-                "algorithmic_flops_per_launch": flops_per_herk, "avg_launch_ms": herk_ms}
+    # work per launch of each timed kernel group (algorithmic)
+    rey = int(np.abs(q["ge"][:, 1]).max())
+    rez = int(np.abs(q["ge"][:, 2]).max())
+    nbox = (2 * rey + 1) * (2 * rez + 1)
+    t_bytes = K * 16.0 * box[0] * nbox
+    work = {
+        "pair": ("k_pair_yz (product + z/y FFT)", "hbm", (K * box_bytes + t_bytes), "GB/s"),
+        "pair_x": ("k_pair_x (x transform + sphere gather)", "hbm", (t_bytes + K * 16.0 * ng), "GB/s"),
+        "band": ("k_band_to_real3", "hbm", (nk * (nv + nc)) * box_bytes, "GB/s"),
+        "herk": ("k_herk_f64", "mfma", chi_flops, "TFLOP/s"),
+        "invert": ("Gauss-Jordan inversion (k_gje_*)", "mfma", lu_flops, "TFLOP/s"),
+    }
+    dominant = max(work, key=lambda k: per_step.get(k, 0))
+    name, bound, per_step_work, unit = work[dominant]
+    nl = launches.get(dominant, 1)
+    avg_ms = per_step[dominant] / nl
+    per_launch = per_step_work / nl
+    if unit == "GB/s":
+        ach = per_launch / (avg_ms * 1e-3) / 1e9
+        peak = HBM_PEAK_GBS
     else:
-        ms_ = per_step[dominant]
-        roof = {"kernel": dominant, "bound": "mfma", "achieved": None, "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": None, "traffic": None}
+        ach = per_launch / (avg_ms * 1e-3) / 1e12
+        peak = FP64_PEAK_TFLOPS
+    fft_src = ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"]
+    tr = load_traffic(dominant, fft_src if dominant in ("pair", "pair_x", "band") else
+                      ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/eps.hip"])
+    roof = {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+            "traffic": None if tr is None else tr["bytes_per_launch"],
+            "algorithmic_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_per_step": nl}
 
     out = {
         "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
@@ -292,7 +341,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies)",
-        "config": {"workload": wl.name, "grid": f"{n}^3", "ng": ng, "ngw": len(s["gw"]), "nv": nv, "nc": nc,
+        "config": {"workload": wl.name, "grid": f"{n}^3", "transform_box": "x".join(map(str, box)), "ng": ng,
+                   "ngw": len(s["gw"]), "nv": nv, "nc": nc,
                    "nk": nk, "npairs": K, "nw": nw, "precision": "fp64", "q": list(map(float, q["q"]))},
         "stages": stages,
         "kernel_share": kernel_share,
@@ -300,6 +350,8 @@ def main():
         "split": None,
         "cpu_baseline": None,
     }
+    if not args.no_full_grid:
+        out["full_grid_pair_density"] = full_grid_pairs(torch, bgw, n, s, q, cv, cc, M, fft_bytes_nominal)
     if not args.no_split:
         out["split"] = split_vs_fp64(torch, h, bgw, qd, s["omega"], chi, ng, K, args.split_reps)
     if not args.no_cpu_baseline:

@@ -80,6 +80,10 @@ size_t bgw_workspace_bytes(bgw_handle_t h);
  *     M_t(G)   = (1/N) sum_j conj(u_v(r_j)) u_c(r_j) exp(+2 pi i m_G . j / n)
  * This equals the matrix element exactly when no axis aliases, i.e.
  * n_i > 2 max|gw_i| + max|ge_i| for i = 1..3 (else BGW_ERR_ALIAS).
+ * Because the result does not depend on the grid once it is alias-free, the
+ * transforms run on the smallest alias-free box: b_i = the least 2^a 3^b
+ * length >= 2 max|gw_i| + max|ge_i| + 1 (at most n_i); setting the
+ * environment variable BGW_FFT_BOX=full makes the library use n itself.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int n[3];          /* FFT grid; each n_i = 2^a 3^b with 4 <= n_i <= 128 */
@@ -96,6 +100,9 @@ typedef struct {
  * ranges and duplicates, alias-free grid).  Touches no GPU and no
  * coefficient memory.  Returns BGW_OK or the code bgw_pair_density would. */
 int bgw_pair_desc_check(const bgw_pair_desc *d);
+
+/* Host-only: the transform box b[3] bgw_pair_density will use for d. */
+int bgw_pair_transform_box(const bgw_pair_desc *d, int box[3]);
 
 /* M: DEVICE complex128 [nk*nv*nc][ng] (pair-major), written in full.
  * Must not overlap cv/cc.  Deterministic: identical inputs give bitwise
@@ -164,7 +171,7 @@ int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const doubl
  * times to the kernel's totals and returns the totals since the last reset.
  * ---------------------------------------------------------------------- */
 #define BGW_KERNEL_BAND 0        /* band G -> r transforms */
-#define BGW_KERNEL_PAIR 1        /* pair product + FFT + sphere gather */
+#define BGW_KERNEL_PAIR 1        /* pair product + z/y FFTs (+ x and gather when single-pass) */
 #define BGW_KERNEL_WEIGHTS 2     /* energy weights */
 #define BGW_KERNEL_HERK 3        /* FP64 chi-sum (rank-K update) */
 #define BGW_KERNEL_FINALIZE 4    /* split reduction, prefactor, Hermitian mirror */
@@ -173,7 +180,8 @@ int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const doubl
 #define BGW_KERNEL_HEADWING 7    /* FP64 head/wing row of chi (split precision) */
 #define BGW_KERNEL_EPS_BUILD 8   /* epsilon = 1 - v chi */
 #define BGW_KERNEL_INVERT 9      /* whole epsilon inversion (all panels) */
-#define BGW_KERNEL_COUNT 10
+#define BGW_KERNEL_PAIR_X 10     /* x pass + sphere gather of the two-pass pair transform */
+#define BGW_KERNEL_COUNT 11
 
 int bgw_set_timing(bgw_handle_t h, int enable);
 /* total_ms and launches may be NULL.  Unknown kernel id: BGW_ERR_ARG. */

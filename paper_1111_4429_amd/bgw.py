@@ -32,11 +32,11 @@ SPLIT_BF16 = 1
 EXPORTS = [
     "bgw_version", "bgw_create", "bgw_destroy", "bgw_last_error", "bgw_workspace_bytes",
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
-    "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
+    "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
-           "invert"]
+           "invert", "pair_x"]
 
 
 class BgwError(RuntimeError):
@@ -111,8 +111,10 @@ def lib():
         L.bgw_set_timing.argtypes = [P, I]
         L.bgw_get_timing.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
         L.bgw_reset_timing.argtypes = [P]
+        L.bgw_pair_transform_box.argtypes = [ctypes.POINTER(PairDesc), ctypes.POINTER(ctypes.c_int)]
         for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
-                  "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing"):
+                  "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
+                  "bgw_pair_transform_box"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -162,6 +164,14 @@ def pair_desc_check(n, gw, ge, nk=1, nv=1, nc=1) -> int:
     """Host-only validation; returns the BGW code (no GPU needed)."""
     d = make_pair_desc(n, gw, ge, nk=nk, nv=nv, nc=nc)
     return int(lib().bgw_pair_desc_check(ctypes.byref(d)))
+
+
+def pair_transform_box(n, gw, ge):
+    """The transform box the library will use (host-only, no GPU)."""
+    d = make_pair_desc(n, gw, ge, nk=1, nv=1, nc=1)
+    box = (ctypes.c_int * 3)()
+    _check(lib().bgw_pair_transform_box(ctypes.byref(d), box))
+    return tuple(box)
 
 
 def vcoul_bulk(bvec, q, ge) -> np.ndarray:

@@ -26,8 +26,16 @@ int launch_pair_fft(const double2 *gv, const double2 *gc, int nkb, int nv, int n
                     const AxisPlan &, const AxisPlan &, const SphereMaps &, int lc, double2 *M, long long row0,
                     hipStream_t);
 int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
-                     const AxisPlan &, const AxisPlan &, const int *ge_code2, int ng, int rey, int rez, double2 *M,
-                     long long row0, hipStream_t);
+                     const AxisPlan &, const AxisPlan &, const int *ge_code2, const int *ge_out, int ng, int rey,
+                     int rez, double2 *M, long long row0, hipStream_t);
+size_t pair_yz_bytes_per_pair(int n1, int rey, int rez);
+bool pair_two_pass_supported(const AxisPlan &py, const AxisPlan &pz);
+int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                   const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                   hipStream_t st);
+int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int rey, int rez, const int *ge_code2,
+                  const int *ge_out, int ng, double2 *M, int nv, int nc, int c0, int ncb, long long row0, size_t N,
+                  hipStream_t st);
 int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &, const AxisPlan &,
                          const AxisPlan &, const SphereMaps &, int rwy, double2 *grids, hipStream_t);
 int launch_weights(const double *ev, const double *ec, int nk, int nv, int nc, double omega_ev, double *w,
@@ -153,6 +161,7 @@ struct DevBuf {
 };
 
 struct FFTPlan {
+    int box[3];  // transform box actually used (see transform_box)
     AxisPlan ax[3];
     SphereMaps sm;
     std::vector<std::unique_ptr<DevBuf>> bufs;
@@ -223,6 +232,31 @@ static int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st) {
     return BGW_OK;
 }
 
+// Transform box: the matrix element is the integral of the matrix-element
+// equation, and the discrete transform reproduces it exactly on any box whose
+// every axis satisfies b_i > 2 max|gw_i| + max|ge_i| (no aliasing of the
+// product's Fourier components onto the dielectric sphere).  The smallest such
+// 2^a 3^b length (at most the caller's n_i) is used; BGW_FFT_BOX=full forces
+// the caller's grid.
+static void transform_box(const bgw_pair_desc *d, int box[3]) {
+    const char *env = std::getenv("BGW_FFT_BOX");
+    const bool full = env && std::strcmp(env, "full") == 0;
+    int mw[3] = {0, 0, 0}, me[3] = {0, 0, 0};
+    for (int g = 0; g < d->ngw; ++g)
+        for (int a = 0; a < 3; ++a) mw[a] = std::max(mw[a], std::abs(d->gw[3 * g + a]));
+    for (int g = 0; g < d->ng; ++g)
+        for (int a = 0; a < 3; ++a) me[a] = std::max(me[a], std::abs(d->ge[3 * g + a]));
+    for (int a = 0; a < 3; ++a) {
+        if (full) {
+            box[a] = d->n[a];
+            continue;
+        }
+        int b = std::max(4, 2 * mw[a] + me[a] + 1);
+        while (!is_2a3b(b)) ++b;
+        box[a] = std::min(b, d->n[a]);
+    }
+}
+
 static std::string plan_key(const bgw_pair_desc *d) {
     // grid + exact G lists (FNV-1a over the index bytes)
     unsigned long long hw = 1469598103934665603ull, he = hw;
@@ -230,7 +264,9 @@ static std::string plan_key(const bgw_pair_desc *d) {
     for (size_t i = 0; i < sizeof(int) * 3 * (size_t)d->ngw; ++i) hw = (hw ^ pw[i]) * 1099511628211ull;
     const unsigned char *pe = reinterpret_cast<const unsigned char *>(d->ge);
     for (size_t i = 0; i < sizeof(int) * 3 * (size_t)d->ng; ++i) he = (he ^ pe[i]) * 1099511628211ull;
-    return std::to_string(d->n[0]) + "x" + std::to_string(d->n[1]) + "x" + std::to_string(d->n[2]) + ":" +
+    int box[3];
+    transform_box(d, box);
+    return std::to_string(box[0]) + "x" + std::to_string(box[1]) + "x" + std::to_string(box[2]) + ":" +
            std::to_string(d->ngw) + ":" + std::to_string(hw) + ":" + std::to_string(d->ng) + ":" + std::to_string(he);
 }
 
@@ -242,10 +278,11 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
         return BGW_OK;
     }
     auto pl = std::make_unique<FFTPlan>();
+    transform_box(d, pl->box);
     // twiddles exp(+2 pi i j / n), evaluated in long double and rounded once
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int a = 0; a < 3; ++a) {
-        const int n = d->n[a];
+        const int n = pl->box[a];
         std::vector<double2> tw((size_t)n);
         for (int j = 0; j < n; ++j) {
             const long double ang = 2.0L * pi * (long double)j / (long double)n;
@@ -257,7 +294,7 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
         BGW_TRY(upload(*pl, tw.data(), sizeof(double2) * n, &dp));
         pl->ax[a].tw = (const double2 *)dp;
     }
-    const int n1 = d->n[0], n2 = d->n[1];
+    const int n1 = pl->box[0], n2 = pl->box[1];
     auto mod = [](int m, int n) { return ((m % n) + n) % n; };
     // wavefunction sticks along x, keyed by (my, mz), entries in ascending G order
     int rwz = 0, rwy = 0;
@@ -299,15 +336,27 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
         rez = std::max(rez, std::abs(d->ge[3 * g + 2]));
         rey = std::max(rey, std::abs(d->ge[3 * g + 1]));
     }
-    std::vector<int> code((size_t)d->ng), code2((size_t)d->ng);
+    std::vector<int> code((size_t)d->ng), code2((size_t)d->ng), order((size_t)d->ng);
     for (int g = 0; g < d->ng; ++g) {
         code[(size_t)g] = mod(d->ge[3 * g], n1) | (mod(d->ge[3 * g + 1], n2) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
-        code2[(size_t)g] = mod(d->ge[3 * g], n1) | ((d->ge[3 * g + 1] + rey) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
+        order[(size_t)g] = g;
+    }
+    // accumulation order of the fast pair kernel: by (mx, my, mz)
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        for (int c = 0; c < 3; ++c)
+            if (d->ge[3 * a + c] != d->ge[3 * b + c]) return d->ge[3 * a + c] < d->ge[3 * b + c];
+        return false;
+    });
+    for (int p = 0; p < d->ng; ++p) {
+        const int g = order[(size_t)p];
+        code2[(size_t)p] = mod(d->ge[3 * g], n1) | ((d->ge[3 * g + 1] + rey) << 8) | ((d->ge[3 * g + 2] + rez) << 16);
     }
     BGW_TRY(upload(*pl, code.data(), sizeof(int) * code.size(), &dp));
     sm.ge_code = (const int *)dp;
     BGW_TRY(upload(*pl, code2.data(), sizeof(int) * code2.size(), &dp));
     sm.ge_code2 = (const int *)dp;
+    BGW_TRY(upload(*pl, order.data(), sizeof(int) * order.size(), &dp));
+    sm.ge_out = (const int *)dp;
     sm.rey = rey;
     sm.ng = d->ng;
     sm.rez = rez;
@@ -400,21 +449,36 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
     FFTPlan *pl = nullptr;
     BGW_TRY(get_plan(h, d, &pl));
     const AxisPlan &px = pl->ax[0], &py = pl->ax[1], &pz = pl->ax[2];
-    const int n2 = d->n[1], n3 = d->n[2];
+    const int n2 = pl->box[1], n3 = pl->box[2];
     const size_t fixed_b = band_lds_bytes(px, py, pz, pl->sm.bwz, 0) + sizeof(int) * n3;
     const size_t fixed_p = pair_lds_bytes(px, py, pz, pl->sm.bez, 0);
     const int lcb = pick_lc(n2, n3, fixed_b), lcp = pick_lc(n2, n3, fixed_p);
     if (lcb < 1 || lcp < 1) return fail(BGW_ERR_UNSUPPORTED, "FFT grid/sphere too large for the LDS budget");
 
-    const size_t N = (size_t)d->n[0] * n2 * n3;
+    const size_t N = (size_t)pl->box[0] * n2 * n3;
     const size_t per_k = sizeof(double2) * N * (size_t)(d->nv + d->nc);
+    // two-pass transform (y,z pass -> T in workspace -> x pass) on the fast sizes,
+    // unless BGW_PAIR_FUSED=1 asks for the single-pass kernel
+    const char *fused_env = std::getenv("BGW_PAIR_FUSED");
+    const bool two_pass = !generic_fft() && !(fused_env && *fused_env == '1') && pair_two_pass_supported(py, pz);
+    const size_t t_per_pair = pair_yz_bytes_per_pair(pl->box[0], pl->sm.rey, pl->sm.rez);
     size_t free_b = 0, total_b = 0;
     BGW_HIP(hipMemGetInfo(&free_b, &total_b));
-    size_t budget = std::min(env_limit(), h->ws.bytes + (size_t)(0.85 * (double)free_b));
-    int kb = (int)std::min<size_t>((size_t)d->nk, budget / per_k);
+    const size_t budget = std::min(env_limit(), h->ws.bytes + (size_t)(0.85 * (double)free_b));
+    // T for one k-point's pairs of a c-batch is capped at 8 GiB (or a quarter of the budget)
+    const size_t t_cap = std::min<size_t>((size_t)8 << 30, budget / 4);
+    int ncb = d->nc;
+    if (two_pass) {
+        ncb = (int)std::max<size_t>(1, std::min<size_t>((size_t)d->nc, t_cap / (t_per_pair * d->nv)));
+    }
+    const size_t t_bytes_for = two_pass ? t_per_pair * (size_t)d->nv * ncb : 0;  // per k in the batch
+    int kb = (int)std::min<size_t>((size_t)d->nk, budget / (per_k + t_bytes_for + 1));
     if (kb < 1) return fail(BGW_ERR_NOMEM, "workspace for one k-point of band grids does not fit");
-    BGW_TRY(ensure_ws(h, per_k * kb, st));
+    if (two_pass) kb = (int)std::min<size_t>((size_t)kb, std::max<size_t>(1, t_cap / (t_per_pair * d->nv * ncb)));
+    const size_t grid_bytes = per_k * kb;
+    BGW_TRY(ensure_ws(h, grid_bytes + (two_pass ? t_bytes_for * kb + 256 : 0), st));
     double2 *gv = (double2 *)h->ws.p;
+    double2 *T = (double2 *)((char *)h->ws.p + ((grid_bytes + 255) / 256) * 256);
     const double2 *cv = (const double2 *)d->cv, *cc = (const double2 *)d->cc;
     for (int k0 = 0; k0 < d->nk; k0 += kb) {
         const int kn = std::min(kb, d->nk - k0);
@@ -432,12 +496,24 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
                 BGW_TRY(launch_band_to_real2(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gc, st));
             }
         }
-        {
+        const long long row0 = (long long)k0 * d->nv * d->nc;
+        if (two_pass) {
+            for (int c0 = 0; c0 < d->nc; c0 += ncb) {
+                const int cn = std::min(ncb, d->nc - c0);
+                {
+                    Timed tm(h, BGW_KERNEL_PAIR, st);
+                    BGW_TRY(launch_pair_yz(gv, gc, kn, d->nv, d->nc, c0, cn, px, py, pz, pl->sm.rey, pl->sm.rez, T, st));
+                }
+                Timed tm(h, BGW_KERNEL_PAIR_X, st);
+                BGW_TRY(launch_pair_x(T, (long long)kn * d->nv * cn, px, pl->sm.rey, pl->sm.rez, pl->sm.ge_code2,
+                                      pl->sm.ge_out, d->ng, (double2 *)M, d->nv, d->nc, c0, cn, row0, N, st));
+            }
+        } else {
             Timed tm(h, BGW_KERNEL_PAIR, st);
-            const long long row0 = (long long)k0 * d->nv * d->nc;
             int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
-                                   : launch_pair_fft2(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm.ge_code2, d->ng,
-                                                      pl->sm.rey, pl->sm.rez, (double2 *)M, row0, st);
+                                   : launch_pair_fft2(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm.ge_code2,
+                                                      pl->sm.ge_out, d->ng, pl->sm.rey, pl->sm.rez, (double2 *)M, row0,
+                                                      st);
             if (rc == BGW_ERR_UNSUPPORTED)
                 rc = launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M, row0, st);
             BGW_TRY(rc);
@@ -558,6 +634,13 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
         const int gn = std::min(group, nw - w0);
         BGW_TRY(launch_gje_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, info + w0, h->ws.p, ipiv, st));
     }
+    return BGW_OK;
+}
+
+extern "C" int bgw_pair_transform_box(const bgw_pair_desc *d, int box[3]) {
+    BGW_TRY(bgw_pair_desc_check(d));
+    if (!box) return fail(BGW_ERR_ARG, "null box");
+    transform_box(d, box);
     return BGW_OK;
 }
 

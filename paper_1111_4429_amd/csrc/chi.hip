@@ -33,7 +33,8 @@ constexpr int TM = 64;       // tile rows (G)
 constexpr int TN = 64;       // tile cols (G')
 constexpr int KC = 16;       // complex pairs per LDS stage
 constexpr int KR = 2 * KC;   // real contraction rows per stage
-constexpr int LDA = TM + 4;  // padded LDS row (doubles)
+constexpr int LDA = TM + 16; // padded LDS row: 640 B = 128 B mod 256 B, so the two half-waves of a
+                             // 64-bit MFMA operand read hit disjoint bank halves
 }  // namespace
 
 // grid.x: upper-triangle tiles (ti <= tj) of an nt x nt tile grid, grid.y: K splits.

@@ -72,7 +72,8 @@ struct SphereMaps {
     // iz = mz + Rez
     int ng;
     const int *ge_code;
-    const int *ge_code2;   // (mx mod n1) | ((my + Rey) << 8) | ((mz + Rez) << 16)
+    const int *ge_code2;   // (mx mod n1) | ((my + Rey) << 8) | ((mz + Rez) << 16), in (mx, my, mz) order
+    const int *ge_out;     // original index of the p-th point of that order
     int bez, rez;          // dielectric box extent along z, Rez
     int rey;               // dielectric box half-extent along y
 };

@@ -77,15 +77,28 @@ __device__ inline void matrix_barrier(unsigned int *bar, unsigned int target, in
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long spins = 0;
         while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
             if (++spins > (1ull << 24)) {  // bounded wait: report and give up
                 atomicExch(info, kInfoBarrierTimeout);
                 break;
             }
         }
     }
+    // thread 0's acquire invalidated this CU's stale cache lines; the exchanged
+    // values are then read with device-scope atomic loads
     __syncthreads();
-    __threadfence();
+}
+
+__device__ inline double2 ld_agent(const double2 *p) {
+    const double *d = reinterpret_cast<const double *>(p);
+    return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                        __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ inline void st_agent(double2 *p, double2 v) {
+    double *d = reinterpret_cast<double *>(p);
+    __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // A: matrices of a group, [nmat][n][n]; each matrix is factored by R
@@ -94,12 +107,14 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
                                                    int *__restrict__ ipiv, int *__restrict__ info, GjeScratch sc,
                                                    unsigned int bar_done) {
     extern __shared__ double2 lds[];
-    double2 *P = lds;                        // [rows][nb]
-    double2 *prow = P + rows * kPanelMax;    // scaled pivot row [nb]
+    const int ps = nb + 1;                   // padded row stride of the panel in LDS
+    double2 *P = lds;                        // [rows][ps]
+    double2 *prow = P + rows * (kPanelMax + 1);  // scaled pivot row [nb]
     double2 *prow_raw = prow + kPanelMax;    // pivot row before scaling [nb]
     double2 *oldrow = prow_raw + kPanelMax;  // row k+j before the swap [nb]
     __shared__ double red_val[256];
     __shared__ int red_row[256];
+    __shared__ int red_win[256];
     __shared__ int s_p, s_win;
 
     const int mat = blockIdx.x / R, r = blockIdx.x % R;
@@ -115,7 +130,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
 
     for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
         const int i = e / nb, c = e % nb;
-        P[i * nb + c] = Am[(size_t)(row0 + i) * n + k + c];
+        P[i * ps + c] = Am[(size_t)(row0 + i) * n + k + c];
     }
     __syncthreads();
 
@@ -128,7 +143,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
         for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
             const int gi = row0 + i;
             if (gi >= col) {
-                const double a = cabs1(P[i * nb + j]);
+                const double a = cabs1(P[i * ps + j]);
                 if (a > best || (a == best && gi < brow)) {
                     best = a;
                     brow = gi;
@@ -152,20 +167,22 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
         const double lbest = red_val[0];
         const int lrow = red_row[0];
         if (threadIdx.x == 0) {
-            cval[slot * R + r] = lbest;
-            crow[slot * R + r] = lrow;
+            __hip_atomic_store(&cval[slot * R + r], lbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&crow[slot * R + r], lrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (lbest >= 0.0)
-            for (int c = threadIdx.x; c < nb; c += blockDim.x) crows[((size_t)slot * R + r) * nb + c] = P[(lrow - row0) * nb + c];
+            for (int c = threadIdx.x; c < nb; c += blockDim.x)
+                st_agent(&crows[((size_t)slot * R + r) * nb + c], P[(lrow - row0) * ps + c]);
         if (col >= row0 && col < row0 + nloc)
-            for (int c = threadIdx.x; c < nb; c += blockDim.x) rbuf[slot * nb + c] = P[(col - row0) * nb + c];
+            for (int c = threadIdx.x; c < nb; c += blockDim.x) st_agent(&rbuf[slot * nb + c], P[(col - row0) * ps + c]);
 
         matrix_barrier(bar, (bar_done + j + 1) * (unsigned)R, info + mat);
 
-        if (threadIdx.x == 0) {
+        // global pivot: every thread reads some of the R candidates, then a block reduction
+        {
             double bv = -1.0;
             int bp = 0x7fffffff, bw = 0;
-            for (int q = 0; q < R; ++q) {
+            for (int q = threadIdx.x; q < R; q += blockDim.x) {
                 const double v = __hip_atomic_load(&cval[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int rr = __hip_atomic_load(&crow[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (v > bv || (v == bv && rr < bp)) {
@@ -174,16 +191,34 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
                     bw = q;
                 }
             }
-            s_p = bp;
-            s_win = bw;
-            if (bv <= 0.0 && r == 0) atomicCAS(info + mat, 0, col + 1);
-            if (r == 0) ip[col] = bp;
+            red_val[threadIdx.x] = bv;
+            red_row[threadIdx.x] = bp;
+            red_win[threadIdx.x] = bw;
+            __syncthreads();
+            for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+                if (threadIdx.x < s2) {
+                    const double ov = red_val[threadIdx.x + s2];
+                    const int orow = red_row[threadIdx.x + s2];
+                    if (ov > red_val[threadIdx.x] || (ov == red_val[threadIdx.x] && orow < red_row[threadIdx.x])) {
+                        red_val[threadIdx.x] = ov;
+                        red_row[threadIdx.x] = orow;
+                        red_win[threadIdx.x] = red_win[threadIdx.x + s2];
+                    }
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) {
+                s_p = red_row[0];
+                s_win = red_win[0];
+                if (red_val[0] <= 0.0 && r == 0) atomicCAS(info + mat, 0, col + 1);
+                if (r == 0) ip[col] = red_row[0];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         const int p = s_p, win = s_win;
         for (int c = threadIdx.x; c < nb; c += blockDim.x) {
-            prow_raw[c] = crows[((size_t)slot * R + win) * nb + c];
-            oldrow[c] = rbuf[slot * nb + c];
+            prow_raw[c] = ld_agent(&crows[((size_t)slot * R + win) * nb + c]);
+            oldrow[c] = ld_agent(&rbuf[slot * nb + c]);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -196,13 +231,13 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
         // row interchange col <-> p inside the panel
         if (p != col) {
             if (p >= row0 && p < row0 + nloc)
-                for (int c = threadIdx.x; c < nb; c += blockDim.x) P[(p - row0) * nb + c] = oldrow[c];
+                for (int c = threadIdx.x; c < nb; c += blockDim.x) P[(p - row0) * ps + c] = oldrow[c];
         }
         __syncthreads();
         // eliminate: every row except col; row col becomes the scaled pivot row
         for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
             const int gi = row0 + i;
-            double2 *pr = P + i * nb;
+            double2 *pr = P + i * ps;
             if (gi == col) {
                 for (int c = 0; c < nb; ++c) pr[c] = prow[c];
             } else {
@@ -216,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
     }
     for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
         const int i = e / nb, c = e % nb;
-        Am[(size_t)(row0 + i) * n + k + c] = P[i * nb + c];
+        Am[(size_t)(row0 + i) * n + k + c] = P[i * ps + c];
     }
 }
 
@@ -386,7 +421,9 @@ size_t gje_workspace_bytes(int n, int nmat, int R) {
            sizeof(int) * (size_t)nmat * n * 2 + 512;
 }
 
-int gje_rows_per_wg(int n) { return std::min(256, std::max(32, (n + 127) / 128)); }
+// rows of the panel held by one workgroup: few workgroups per matrix keep the
+// per-column grid barrier cheap
+int gje_rows_per_wg(int n) { return std::min(256, std::max(64, (n + 15) / 16)); }
 
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t st) {
     const int rows = gje_rows_per_wg(n);
@@ -406,7 +443,7 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (unsigned int *)info, (size_t)nmat, 0u);
     BGW_HIP(hipGetLastError());
 
-    const size_t lds = sizeof(double2) * ((size_t)rows * kPanelMax + 3 * kPanelMax);
+    const size_t lds = sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 3 * kPanelMax);
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned int bar_done = 0;
     for (int k = 0; k < n; k += kPanelMax) {
@@ -434,7 +471,7 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
 int gje_max_group(int n) {
     const int rows = gje_rows_per_wg(n);
     const int R = (n + rows - 1) / rows;
-    const size_t lds = sizeof(double2) * ((size_t)rows * kPanelMax + 3 * kPanelMax);
+    const size_t lds = sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 3 * kPanelMax);
     int per_cu = 0;
     if (hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
         hipSuccess)

@@ -15,6 +15,8 @@
 // stage is a direct sum over the box rows, the z stage a direct sum over the
 // box columns evaluated by a thread that owns a fixed z (its twiddles live in
 // registers) and stored with coalesced writes.
+#include <cstdlib>
+
 #include "common.h"
 
 namespace bgw {
@@ -172,20 +174,26 @@ __host__ __device__ constexpr int plane_stride() {
     return Z1 * Z2 + ((Z2 % 16) - (Z1 * Z2) % 16 + 16) % 16;
 }
 
-template <int Z1, int Z2, int Y1, int Y2, int ACC, int NT>
+template <int Z1, int Z2, int Y1, int Y2, int ACC, int NT, int LC>
 __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
                                                   int nkb, int nv, int nc, int n1, const double2 *__restrict__ tw1g,
                                                   const double2 *__restrict__ tw2g, const double2 *__restrict__ tw3g,
-                                                  const int *__restrict__ ge_code, int ng, int rey, int rez, int lc,
-                                                  int vb, int cb, double2 *__restrict__ M, long long m_row0) {
+                                                  const int *__restrict__ ge_code, const int *__restrict__ ge_out,
+                                                  int ng, int rey, int rez, int vb, int cb,
+                                                  double2 *__restrict__ M, long long m_row0) {
     constexpr int n3 = Z1 * Z2, n2 = Y1 * Y2;
     constexpr int PS = plane_stride<Z1, Z2>();
+    constexpr int CH = LC * n3;               // product elements per z chunk
+    constexpr int PER = (CH + NT - 1) / NT;   // per thread
+    constexpr int NCHUNK = (n2 + LC - 1) / LC;
     const int bez = 2 * rez + 1, bey = 2 * rey + 1;
     const int QS = bez;
+    // e / bez as (e * mdiv) >> 20, exact for e * bez < 2^20 (here e < 128 bez and bez < 90)
+    const unsigned mdiv = (1u << 20) / (unsigned)bez + 1u;
     extern __shared__ double2 lds[];
     double2 *tw1 = lds, *tw2 = tw1 + n1, *tw3 = tw2 + n2;
-    double2 *P = tw3 + n3;            // [lc][PS]
-    double2 *Q = P + lc * PS;         // [n2][QS]
+    double2 *P = tw3 + n3;            // [LC][PS]
+    double2 *Q = P + LC * PS;         // [n2][QS]
     double2 *R = Q + n2 * QS;         // [bey][bez]
 
     for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
@@ -202,17 +210,14 @@ __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv
     const int vtiles = (nv + vb - 1) / vb;
     const int ctiles = (nc + cb - 1) / cb;
     long long rem = L;
-    // tiles may be ragged at the edges: walk (k, ct, vt) then the inner (c, v)
     int k = (int)(rem / ((long long)nv * nc));
     rem -= (long long)k * nv * nc;
     int v = 0, c = 0;
     {
-        // rem in [0, nv*nc): locate the (ct, vt) tile containing it
-        const int cw_full = cb;
         int done = 0;
         for (int ct = 0; ct < ctiles; ++ct) {
-            const int cw = min(cw_full, nc - ct * cb);
-            const int rowblock = cw * nv;  // pairs in this c-tile
+            const int cw = min(cb, nc - ct * cb);
+            const int rowblock = cw * nv;
             if (rem < done + rowblock) {
                 int r2 = (int)(rem - done);
                 for (int vt = 0; vt < vtiles; ++vt) {
@@ -235,6 +240,8 @@ __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv
     const double2 *uv = gv + (size_t)(k * nv + v) * N;
     const double2 *uc = gc + (size_t)(k * nc + c) * N;
 
+    // sphere points in (mx, my, mz) order: a wave shares the phase w^{mx x}
+    // (LDS broadcast) and reads neighbouring R entries
     int code[ACC], ph[ACC], mxs[ACC];
     double2 acc[ACC];
 #pragma unroll
@@ -245,22 +252,54 @@ __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv
         ph[i] = 0;
         acc[i] = make_double2(0.0, 0.0);
     }
+
+    // software pipeline: the u_c values of the next z chunk are loaded into
+    // registers while the current chunk is transformed; u_v (shared by all the
+    // concurrently running pairs of a c-tile, so L2-resident) is read when the
+    // product is formed
+    double2 fc[PER];
+    auto fetch = [&](int x, int y0) {
+        const int Lc = min(LC, n2 - y0);
+        const double2 *pc = uc + ((size_t)x * n2 + y0) * n3;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + j * NT;
+            if (e < Lc * n3) fc[j] = pc[e];
+        }
+    };
+    fetch(0, 0);
     __syncthreads();
 
     for (int x = 0; x < n1; ++x) {
-        for (int y0 = 0; y0 < n2; y0 += lc) {
-            const int Lc = min(lc, n2 - y0);
+#pragma unroll 1
+        for (int ci = 0; ci < NCHUNK; ++ci) {
+            const int y0 = ci * LC;
+            const int Lc = min(LC, n2 - y0);
             const double2 *pv = uv + ((size_t)x * n2 + y0) * n3;
-            const double2 *pc = uc + ((size_t)x * n2 + y0) * n3;
-            for (int e = threadIdx.x; e < Lc * n3; e += NT) {
-                const int yy = e / n3, z = e - yy * n3;
-                P[yy * PS + z] = cconjmul(pv[e], pc[e]);
+            double2 fv[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = threadIdx.x + j * NT;
+                if (e < Lc * n3) fv[j] = pv[e];
             }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = threadIdx.x + j * NT;
+                if (e < Lc * n3) {
+                    const int yy = e / n3, z = e - yy * n3;
+                    P[yy * PS + z] = cconjmul(fv[j], fc[j]);
+                }
+            }
+            // prefetch the next chunk (next y block, or the first block of the next plane)
+            if (ci + 1 < NCHUNK)
+                fetch(x, y0 + LC);
+            else if (x + 1 < n1)
+                fetch(x + 1, 0);
             __syncthreads();
             LineFFT<Z1, Z2>::stage1(P, Lc, PS, 1, tw3);
             __syncthreads();
             for (int e = threadIdx.x; e < Lc * bez; e += NT) {
-                const int yy = e / bez, iz = e - yy * bez;
+                const int yy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - yy * bez;
                 Q[(y0 + yy) * QS + iz] = LineFFT<Z1, Z2>::output(P + yy * PS, 1, wrap(iz - rez, n3), tw3);
             }
             __syncthreads();
@@ -268,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv
         LineFFT<Y1, Y2>::stage1(Q, bez, 1, QS, tw2);
         __syncthreads();
         for (int e = threadIdx.x; e < bey * bez; e += NT) {
-            const int iy = e / bez, iz = e - iy * bez;
+            const int iy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - iy * bez;
             R[e] = LineFFT<Y1, Y2>::output(Q + iz, QS, wrap(iy - rey, n2), tw2);
         }
         __syncthreads();
@@ -287,7 +326,167 @@ __global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv
 #pragma unroll
     for (int i = 0; i < ACC; ++i) {
         const int g = threadIdx.x + i * NT;
-        if (g < ng) out[g] = cscale(acc[i], inv);
+        if (g < ng) out[ge_out[g]] = cscale(acc[i], inv);
+    }
+}
+
+
+// ------------------------------------------------------------------ two-pass pair transform
+//
+// Pass A (k_pair_yz): one workgroup per (k, c, block of x-planes); for every x of
+// the block and every valence band v: product conj(u_v) u_c on the plane, z FFT
+// pruned to the dielectric box, y FFT pruned likewise; the bey x bez values are
+// written to T[t][x][iy][iz].  No per-pair accumulators, so the next chunk's
+// u_v, u_c values are prefetched into registers while the current one is
+// transformed.  Concurrent workgroups (same k and x-block, consecutive c) share
+// the u_v planes in L2.
+// Pass B (k_pair_x): one workgroup per pair; T[t] is staged through LDS a few
+// planes at a time and every sphere point accumulates w_{n1}^{mx x} T[x][iy][iz].
+template <int Z1, int Z2, int NT, int LC, bool PF, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
+                                                int nkb, int nv, int nc, int c0, int ncb, int n1,
+                                                const double2 *__restrict__ tw2g, const double2 *__restrict__ tw3g,
+                                                int rey, int rez, int xblk, double2 *__restrict__ T) {
+    constexpr int n3 = Z1 * Z2, n2 = n3;
+    constexpr int PS = plane_stride<Z1, Z2>();
+    constexpr int CH = LC * n3;
+    constexpr int PER = (CH + NT - 1) / NT;
+    constexpr int NCHUNK = (n2 + LC - 1) / LC;
+    const int bez = 2 * rez + 1, bey = 2 * rey + 1;
+    const int QS = bez;
+    const int nbox = bey * bez;
+    const unsigned mdiv = (1u << 20) / (unsigned)bez + 1u;
+    extern __shared__ double2 lds[];
+    double2 *tw2 = lds, *tw3 = tw2 + n2;
+    double2 *P = tw3 + n3;     // [LC][PS]
+    double2 *Q = P + LC * PS;  // [n2][QS]
+    for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
+    for (int i = threadIdx.x; i < n3; i += NT) tw3[i] = tw3g[i];
+
+    // c-batch [c0, c0 + ncb) of the k-batch; T is indexed by the batch-local
+    // pair (k * nv + v) * ncb + cl
+    const int nxb = (n1 + xblk - 1) / xblk;
+    const int cl = blockIdx.x % ncb;
+    const int c = c0 + cl;
+    const int rest = blockIdx.x / ncb;
+    const int xb = rest % nxb;
+    const int k = rest / nxb;
+    const int x0 = xb * xblk, x1 = min(n1, x0 + xblk);
+    const size_t N = (size_t)n1 * n2 * n3;
+    const double2 *uc = gc + (size_t)(k * nc + c) * N;
+    const double2 *uvk = gv + (size_t)k * nv * N;
+
+    double2 fv[PER], fc[PER];
+    auto fetch = [&](int x, int v, int ci) {
+        const int y0 = ci * LC;
+        const int Lc = min(LC, n2 - y0);
+        const size_t off = ((size_t)x * n2 + y0) * n3;
+        const double2 *pv = uvk + (size_t)v * N + off;
+        const double2 *pc = uc + off;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = threadIdx.x + j * NT;
+            if (e < Lc * n3) {
+                fv[j] = pv[e];
+                fc[j] = pc[e];
+            }
+        }
+    };
+    if (PF) fetch(x0, 0, 0);
+    __syncthreads();
+    for (int x = x0; x < x1; ++x) {
+#pragma unroll 1
+        for (int v = 0; v < nv; ++v) {
+#pragma unroll 1
+            for (int ci = 0; ci < NCHUNK; ++ci) {
+                const int y0 = ci * LC;
+                const int Lc = min(LC, n2 - y0);
+                if (!PF) fetch(x, v, ci);
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    const int e = threadIdx.x + j * NT;
+                    if (e < Lc * n3) {
+                        const int yy = e / n3, z = e - yy * n3;
+                        P[yy * PS + z] = cconjmul(fv[j], fc[j]);
+                    }
+                }
+                if (PF) {
+                    // prefetch the next chunk: next y block, next valence band, or next plane
+                    if (ci + 1 < NCHUNK)
+                        fetch(x, v, ci + 1);
+                    else if (v + 1 < nv)
+                        fetch(x, v + 1, 0);
+                    else if (x + 1 < x1)
+                        fetch(x + 1, 0, 0);
+                }
+                __syncthreads();
+                LineFFT<Z1, Z2>::stage1(P, Lc, PS, 1, tw3);
+                __syncthreads();
+                for (int e = threadIdx.x; e < Lc * bez; e += NT) {
+                    const int yy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - yy * bez;
+                    Q[(y0 + yy) * QS + iz] = LineFFT<Z1, Z2>::output(P + yy * PS, 1, wrap(iz - rez, n3), tw3);
+                }
+                __syncthreads();
+            }
+            LineFFT<Z1, Z2>::stage1(Q, bez, 1, QS, tw2);
+            __syncthreads();
+            const long long tl = ((long long)k * nv + v) * ncb + cl;
+            double2 *o = T + ((size_t)tl * n1 + x) * nbox;
+            for (int e = threadIdx.x; e < nbox; e += NT) {
+                const int iy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - iy * bez;
+                o[e] = LineFFT<Z1, Z2>::output(Q + iz, QS, wrap(iy - rey, n2), tw2);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Pass B.  T: [npairs][n1][nbox]; sphere points in (mx, my, mz) order (ge_code2),
+// written back in the original order (ge_out).  XS planes staged per round.
+template <int ACC, int NT, int XS>
+__global__ __launch_bounds__(NT) void k_pair_x(const double2 *__restrict__ T, int n1, int nbox, int bez,
+                                               const double2 *__restrict__ tw1g, const int *__restrict__ ge_code,
+                                               const int *__restrict__ ge_out, int ng, double inv_n,
+                                               double2 *__restrict__ M, int nv, int nc, int c0, int ncb,
+                                               long long m_row0) {
+    extern __shared__ double2 lds[];
+    double2 *tw1 = lds, *Ts = tw1 + n1;  // [XS][nbox]
+    for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
+    const long long t = blockIdx.x;
+    const double2 *Tt = T + (size_t)t * n1 * nbox;
+    int slot[ACC], ph[ACC], mxs[ACC];
+    double2 acc[ACC];
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) {
+        const int g = threadIdx.x + i * NT;
+        const int cd = g < ng ? ge_code[g] : -1;
+        slot[i] = cd >= 0 ? ((cd >> 8) & 0xff) * bez + (cd >> 16) : -1;
+        mxs[i] = cd >= 0 ? (cd & 0xff) : 0;
+        ph[i] = 0;
+        acc[i] = make_double2(0.0, 0.0);
+    }
+    for (int xs = 0; xs < n1; xs += XS) {
+        const int nx = min(XS, n1 - xs);
+        __syncthreads();
+        for (int e = threadIdx.x; e < nx * nbox; e += NT) Ts[e] = Tt[(size_t)xs * nbox + e];
+        __syncthreads();
+        for (int xx = 0; xx < nx; ++xx) {
+#pragma unroll
+            for (int i = 0; i < ACC; ++i) {
+                if (slot[i] >= 0) {
+                    acc[i] = cadd(acc[i], cmul(tw1[ph[i]], Ts[xx * nbox + slot[i]]));
+                    ph[i] += mxs[i];
+                    if (ph[i] >= n1) ph[i] -= n1;
+                }
+            }
+        }
+    }
+    const long long cl = t % ncb, kv = t / ncb;  // kv = k * nv + v within the k-batch
+    double2 *out = M + (size_t)(m_row0 + kv * nc + c0 + cl) * ng;
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) {
+        const int g = threadIdx.x + i * NT;
+        if (g < ng) out[ge_out[g]] = cscale(acc[i], inv_n);
     }
 }
 
@@ -374,46 +573,150 @@ __global__ __launch_bounds__(NT) void k_band_to_real2(const double2 *__restrict_
     }
 }
 
+
+// Band kernel for fast z lengths: x stage summed per stick (stick metadata in
+// registers, coefficients gathered once per band into LDS in stick order when
+// they fit), y stage as a direct sum over the box rows, z stage as the
+// register radix-R1 FFT of the zero-padded lines (all n3 outputs kept),
+// written with coalesced stores.
+template <int Z1, int Z2, int NT, int SPT>
+__global__ __launch_bounds__(NT) void k_band_to_real3(const double2 *__restrict__ C, int ngw, int n1, int n2,
+                                                      const double2 *__restrict__ tw1g,
+                                                      const double2 *__restrict__ tw2g,
+                                                      const double2 *__restrict__ tw3g, SphereMaps sm, int rwy, int lc,
+                                                      int cache_c, double2 *__restrict__ grids) {
+    constexpr int n3 = Z1 * Z2;
+    constexpr int PS = plane_stride<Z1, Z2>();
+    const int bwy = 2 * rwy + 1, bwz = sm.bwz, rwz = sm.rwz;
+    extern __shared__ double2 lds[];
+    double2 *tw1 = lds, *tw2 = tw1 + n1, *tw3 = tw2 + n2;
+    double2 *Qb = tw3 + n3;       // [bwy][bwz]  x-stick sums
+    double2 *S = Qb + bwy * bwz;  // [n2][bwz]   after the y expansion
+    double2 *Z = S + n2 * bwz;    // [lc][PS]    z lines
+    double2 *Cs = Z + lc * PS;    // [ngw]       coefficients in stick order (if cached)
+    int *mxl = reinterpret_cast<int *>(Cs + (cache_c ? ngw : 0));  // [ngw] mx mod n1 in stick order
+    for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
+    for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
+    for (int i = threadIdx.x; i < n3; i += NT) tw3[i] = tw3g[i];
+    const double2 *cg = C + (size_t)blockIdx.x * ngw;
+    for (int i = threadIdx.x; i < ngw; i += NT) {
+        if (cache_c) Cs[i] = cg[sm.stick_g[i]];
+        mxl[i] = sm.stick_mx[i];
+    }
+    int s0[SPT], s1[SPT], syz[SPT];
+#pragma unroll
+    for (int j = 0; j < SPT; ++j) {
+        const int s = threadIdx.x + j * NT;
+        s0[j] = s1[j] = 0;
+        syz[j] = -1;
+        if (s < sm.nstick) {
+            s0[j] = sm.stick_start[s];
+            s1[j] = sm.stick_start[s + 1];
+            syz[j] = sm.stick_yz2[s];
+        }
+    }
+    // (m * x) mod n1 as m*x - n1 * ((m*x*md) >> 20), exact for m*x < n1^2 <= 2^14
+    const unsigned md = (1u << 20) / (unsigned)n1 + 1u;
+    const size_t N = (size_t)n1 * n2 * n3;
+    double2 *out = grids + (size_t)blockIdx.x * N;
+    __syncthreads();
+
+    for (int x = 0; x < n1; ++x) {
+        for (int e = threadIdx.x; e < bwy * bwz; e += NT) Qb[e] = make_double2(0.0, 0.0);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < SPT; ++j) {
+            if (syz[j] < 0) continue;
+            double2 a = make_double2(0.0, 0.0);
+            for (int i = s0[j]; i < s1[j]; ++i) {
+                const unsigned prod = (unsigned)(mxl[i] * x);
+                const int idx = (int)(prod - (unsigned)n1 * (unsigned)(((unsigned long long)prod * md) >> 20));
+                const double2 cv = cache_c ? Cs[i] : cg[sm.stick_g[i]];
+                a = cadd(a, cmul(tw1[idx], cv));
+            }
+            Qb[(syz[j] & 0xffff) * bwz + (syz[j] >> 16)] = a;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n2 * bwz; e += NT) {
+            const int y = e / bwz, iz = e - y * bwz;
+            int idx = (-rwy * y) % n2;
+            if (idx < 0) idx += n2;
+            double2 a = make_double2(0.0, 0.0);
+            for (int iy = 0; iy < bwy; ++iy) {
+                a = cadd(a, cmul(tw2[idx], Qb[iy * bwz + iz]));
+                idx += y;
+                if (idx >= n2) idx -= n2;
+            }
+            S[e] = a;
+        }
+        __syncthreads();
+        for (int y0 = 0; y0 < n2; y0 += lc) {
+            const int L = min(lc, n2 - y0);
+            for (int e = threadIdx.x; e < L * n3; e += NT) {
+                const int yy = e / n3, z = e - yy * n3;
+                const int mz = z <= rwz ? z : z - n3;
+                Z[yy * PS + z] = (mz >= -rwz && mz <= rwz) ? S[(y0 + yy) * bwz + mz + rwz] : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            LineFFT<Z1, Z2>::stage1(Z, L, PS, 1, tw3);
+            __syncthreads();
+            double2 *o = out + ((size_t)x * n2 + y0) * n3;
+            for (int e = threadIdx.x; e < L * n3; e += NT) {
+                const int yy = e / n3, z = e - yy * n3;
+                o[e] = LineFFT<Z1, Z2>::output(Z + yy * PS, 1, z, tw3);
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
 
-template <int Z1, int Z2, int ACC, int NT>
+template <int Z1, int Z2, int ACC, int NT, int LC>
 int launch_pair2_t(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, int ng, int rey, int rez, double2 *M,
-                   long long row0, hipStream_t st) {
+                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, const int *ge_out, int ng, int rey,
+                   int rez, double2 *M, long long row0, hipStream_t st) {
     constexpr int n = Z1 * Z2;
     constexpr int PS = plane_stride<Z1, Z2>();
     const int bez = 2 * rez + 1, bey = 2 * rey + 1;
-    // lines per z chunk: keep the workgroup's LDS at or below ~80 KB (two per CU)
-    const size_t fixed = sizeof(double2) * ((size_t)px.n + n + n + (size_t)n * bez + (size_t)bey * bez);
-    const size_t budget = 78 * 1024;
-    int lc = n;
-    while (lc > 4 && fixed + sizeof(double2) * (size_t)lc * PS > budget) lc = (lc + 1) / 2;
-    const size_t lds = fixed + sizeof(double2) * (size_t)lc * PS;
-    auto kern = k_pair_fft2<Z1, Z2, Z1, Z2, ACC, NT>;
+    const size_t lds = sizeof(double2) * ((size_t)px.n + n + n + (size_t)LC * PS + (size_t)n * bez + (size_t)bey * bez);
+    if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
+    auto kern = k_pair_fft2<Z1, Z2, Z1, Z2, ACC, NT, LC>;
     BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const long long npairs = (long long)nkb * nv * nc;
     const int vb = std::min(nv, 8);
     const int cb = std::max(1, 256 / vb);
     hipLaunchKernelGGL(kern, dim3((unsigned)npairs), dim3(NT), lds, st, gv, gc, nkb, nv, nc, px.n, px.tw, py.tw,
-                       pz.tw, ge_code, ng, rey, rez, lc, vb, cb, M, row0);
+                       pz.tw, ge_code, ge_out, ng, rey, rez, vb, cb, M, row0);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
 
+// lines per z chunk: the whole plane up to 48, else a block that keeps two
+// workgroups per CU for the usual dielectric boxes
+template <int N>
+constexpr int pair_lc() {
+    return N <= 48 ? N : (N <= 64 ? 32 : 16);
+}
+
 template <int Z1, int Z2, int NT>
 int launch_pair2_n(int per, const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, int ng, int rey, int rez, double2 *M,
-                   long long row0, hipStream_t st) {
+                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, const int *ge_out, int ng, int rey,
+                   int rez, double2 *M, long long row0, hipStream_t st) {
 #define BGW_P2(A)                                                                                                \
     if (per <= A)                                                                                                \
-        return launch_pair2_t<Z1, Z2, A, NT>(gv, gc, nkb, nv, nc, px, py, pz, ge_code, ng, rey, rez, M, row0, st);
+        return launch_pair2_t<Z1, Z2, A, NT, pair_lc<Z1 * Z2>()>(gv, gc, nkb, nv, nc, px, py, pz, ge_code, ge_out, \
+                                                                 ng, rey, rez, M, row0, st);
     BGW_P2(1)
     BGW_P2(2)
     BGW_P2(4)
+    BGW_P2(6)
     BGW_P2(8)
+    BGW_P2(12)
     BGW_P2(16)
+    BGW_P2(24)
     BGW_P2(32)
 #undef BGW_P2
     return BGW_ERR_UNSUPPORTED;
@@ -421,28 +724,193 @@ int launch_pair2_n(int per, const double2 *gv, const double2 *gc, int nkb, int n
 
 }  // namespace
 
-// Returns BGW_ERR_UNSUPPORTED (without launching) when no fast path applies.
-int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                     const AxisPlan &py, const AxisPlan &pz, const int *ge_code2, int ng, int rey, int rez,
-                     double2 *M, long long row0, hipStream_t st) {
+
+namespace {
+template <int Z1, int Z2, int LC, bool PF, int MINW = 1>
+int launch_pair_yz_t(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                     const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                     hipStream_t st) {
+    constexpr int n = Z1 * Z2;
+    constexpr int PS = plane_stride<Z1, Z2>();
+    const int bez = 2 * rez + 1;
+    const size_t lds = sizeof(double2) * ((size_t)n + n + (size_t)LC * PS + (size_t)n * bez);
+    if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
+    auto kern = k_pair_yz<Z1, Z2, 256, LC, PF, MINW>;
+    BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int n1 = px.n;
+    const int xblk = std::max(1, std::min(n1, 8));
+    const int nxb = (n1 + xblk - 1) / xblk;
+    const long long grid = (long long)nkb * nxb * ncb;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, st, gv, gc, nkb, nv, nc, c0, ncb, n1, py.tw, pz.tw,
+                       rey, rez, xblk, T);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+template <int ACC>
+int launch_pair_x_t(const double2 *T, long long npairs, const AxisPlan &px, int nbox, int bez, const int *ge_code2,
+                    const int *ge_out, int ng, double inv_n, double2 *M, int nv, int nc, int c0, int ncb,
+                    long long row0, hipStream_t st) {
+    constexpr int XS = 8;
+    const size_t lds = sizeof(double2) * ((size_t)px.n + (size_t)XS * nbox);
+    if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
+    auto kern = k_pair_x<ACC, 256, XS>;
+    BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)npairs), dim3(256), lds, st, T, px.n, nbox, bez, px.tw, ge_code2, ge_out,
+                       ng, inv_n, M, nv, nc, c0, ncb, row0);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int pair_variant() {
+    const char *s = std::getenv("BGW_PAIR_VARIANT");
+    return (s && *s) ? std::atoi(s) : 0;
+}
+
+template <int Z1, int Z2, int LCF>
+int launch_pair_yz_sel(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                       const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                       hipStream_t st) {
+    // experimental variants (BGW_PAIR_VARIANT): 1 = prefetch, whole chunk; 2 = half chunk,
+    // no prefetch; 3 = whole chunk, >= 3 waves/SIMD; 4 = half chunk, >= 3 waves/SIMD
+    switch (pair_variant()) {
+        case 1: return launch_pair_yz_t<Z1, Z2, LCF, true>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 2: return launch_pair_yz_t<Z1, Z2, (LCF + 1) / 2, false>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 3: return launch_pair_yz_t<Z1, Z2, LCF, false, 3>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 4: return launch_pair_yz_t<Z1, Z2, (LCF + 1) / 2, false, 3>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        default: return launch_pair_yz_t<Z1, Z2, LCF, false>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+    }
+}
+}  // namespace
+
+size_t pair_yz_bytes_per_pair(int n1, int rey, int rez) {
+    return sizeof(double2) * (size_t)n1 * (size_t)(2 * rey + 1) * (2 * rez + 1);
+}
+
+bool pair_two_pass_supported(const AxisPlan &py, const AxisPlan &pz) {
+    if (py.n != pz.n) return false;
+    switch (pz.n) {
+        case 16: case 24: case 32: case 48: case 64: case 96: case 128: return true;
+        default: return false;
+    }
+}
+
+// Pass A for fast sizes (y and z lengths equal, 16 r or 24).
+int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                   const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                   hipStream_t st) {
     if (py.n != pz.n) return BGW_ERR_UNSUPPORTED;
-    const int n = pz.n;
-    const int per = (ng + 255) / 256;
-    switch (n) {
-        case 16: return launch_pair2_n<16, 1, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 24: return launch_pair2_n<8, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 32: return launch_pair2_n<16, 2, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 48: return launch_pair2_n<16, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 64: return launch_pair2_n<16, 4, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 96: return launch_pair2_n<16, 6, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
-        case 128: return launch_pair2_n<16, 8, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ng, rey, rez, M, row0, st);
+    switch (pz.n) {
+        case 16: return launch_pair_yz_sel<16, 1, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 24: return launch_pair_yz_sel<8, 3, 24>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 32: return launch_pair_yz_sel<16, 2, 32>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 48: {
+            const char *r8 = std::getenv("BGW_PAIR_RADIX8");
+            if (r8 && *r8 == '1') return launch_pair_yz_sel<8, 6, 48>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+            return launch_pair_yz_sel<16, 3, 48>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        }
+        case 64: return launch_pair_yz_sel<16, 4, 32>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 96: return launch_pair_yz_sel<16, 6, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
+        case 128: return launch_pair_yz_sel<16, 8, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         default: return BGW_ERR_UNSUPPORTED;
     }
 }
 
+int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int rey, int rez, const int *ge_code2,
+                  const int *ge_out, int ng, double2 *M, int nv, int nc, int c0, int ncb, long long row0, size_t N,
+                  hipStream_t st) {
+    const int bez = 2 * rez + 1, nbox = (2 * rey + 1) * bez;
+    const double inv_n = 1.0 / (double)N;
+    const int per = (ng + 255) / 256;
+#define BGW_PX(A)                                                                                               \
+    if (per <= A)                                                                                               \
+        return launch_pair_x_t<A>(T, npairs, px, nbox, bez, ge_code2, ge_out, ng, inv_n, M, nv, nc, c0, ncb, row0, \
+                                  st);
+    BGW_PX(1)
+    BGW_PX(2)
+    BGW_PX(4)
+    BGW_PX(6)
+    BGW_PX(8)
+    BGW_PX(12)
+    BGW_PX(16)
+    BGW_PX(24)
+    BGW_PX(32)
+#undef BGW_PX
+    return BGW_ERR_UNSUPPORTED;
+}
+
+// Returns BGW_ERR_UNSUPPORTED (without launching) when no fast path applies.
+int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
+                     const AxisPlan &py, const AxisPlan &pz, const int *ge_code2, const int *ge_out, int ng, int rey,
+                     int rez, double2 *M, long long row0, hipStream_t st) {
+    if (py.n != pz.n) return BGW_ERR_UNSUPPORTED;
+    const int n = pz.n;
+    const int per = (ng + 255) / 256;
+    switch (n) {
+        case 16: return launch_pair2_n<16, 1, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 24: return launch_pair2_n<8, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 32: return launch_pair2_n<16, 2, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 48: return launch_pair2_n<16, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 64: return launch_pair2_n<16, 4, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 96: return launch_pair2_n<16, 6, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        case 128: return launch_pair2_n<16, 8, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
+        default: return BGW_ERR_UNSUPPORTED;
+    }
+}
+
+namespace {
+template <int Z1, int Z2>
+int launch_band3_t(const double2 *C, int nbands, int ngw, const AxisPlan &px, const AxisPlan &py,
+                   const AxisPlan &pz, const SphereMaps &sm, int rwy, double2 *grids, hipStream_t st) {
+    constexpr int PS = plane_stride<Z1, Z2>();
+    if (sm.nstick > 4 * 256 || px.n > 128) return BGW_ERR_UNSUPPORTED;
+    const int bwy = 2 * rwy + 1;
+    const size_t fixed = sizeof(double2) * ((size_t)px.n + py.n + pz.n + (size_t)bwy * sm.bwz + (size_t)py.n * sm.bwz) +
+                         sizeof(int) * (size_t)ngw;
+    // aim at two workgroups per CU (<= 78 KB) with the coefficients cached
+    int cache_c = 1;
+    int lc = py.n;
+    auto bytes = [&](int l, int cc) { return fixed + sizeof(double2) * ((size_t)l * PS + (cc ? (size_t)ngw : 0)); };
+    while (lc > 8 && bytes(lc, 1) > 78 * 1024) lc = (lc + 1) / 2;
+    if (bytes(lc, 1) > 78 * 1024) {
+        cache_c = 0;
+        lc = py.n;
+        while (lc > 4 && bytes(lc, 0) > 78 * 1024) lc = (lc + 1) / 2;
+    }
+    const size_t lds = bytes(lc, cache_c);
+    if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
+#define BGW_B3(SPT)                                                                                              \
+    {                                                                                                            \
+        auto kern = k_band_to_real3<Z1, Z2, 256, SPT>;                                                           \
+        BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));  \
+        hipLaunchKernelGGL(kern, dim3(nbands), dim3(256), lds, st, C, ngw, px.n, py.n, px.tw, py.tw, pz.tw, sm, \
+                           rwy, lc, cache_c, grids);                                                              \
+    }
+    if (sm.nstick <= 256)
+        BGW_B3(1)
+    else if (sm.nstick <= 512)
+        BGW_B3(2)
+    else
+        BGW_B3(4)
+#undef BGW_B3
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+}  // namespace
+
 int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &px, const AxisPlan &py,
                          const AxisPlan &pz, const SphereMaps &sm, int rwy, double2 *grids, hipStream_t st) {
     if (nbands <= 0) return BGW_OK;
+    switch (pz.n) {
+        case 16: return launch_band3_t<16, 1>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 24: return launch_band3_t<8, 3>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 32: return launch_band3_t<16, 2>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 48: return launch_band3_t<16, 3>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 64: return launch_band3_t<16, 4>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 96: return launch_band3_t<16, 6>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        case 128: return launch_band3_t<16, 8>(C, nbands, ngw, px, py, pz, sm, rwy, grids, st);
+        default: break;
+    }
     const int bwy = 2 * rwy + 1;
     if (sm.bwz > 32 || pz.n > 256) return BGW_ERR_UNSUPPORTED;
     const size_t lds = sizeof(double2) * ((size_t)px.n + py.n + (size_t)bwy * sm.bwz + (size_t)py.n * sm.bwz);

@@ -65,6 +65,19 @@ def test_pair_desc_validation_codes():
     assert "duplicate" in bgw.lib().bgw_last_error().decode() or True
 
 
+def test_transform_box_is_minimal_alias_free():
+    """The library transforms on the smallest 2^a 3^b box with
+    b_i > 2 max|gw_i| + max|ge_i| (at most the caller's grid)."""
+    for name, expect in (("tiny-static-16", 16), ("silicon-like-48", 24), ("supercell-96", 48),
+                         ("imag-freq-64", 32)):
+        wl = synth.WORKLOADS[name]
+        gw, ge = synth.gvector_list(wl.ngw), synth.gvector_list(wl.ng)
+        box = bgw.pair_transform_box(wl.n, gw, ge)
+        assert box == (expect,) * 3, (name, box)
+        need = 2 * np.abs(gw).max(axis=0) + np.abs(ge).max(axis=0)
+        assert all(b > m for b, m in zip(box, need))
+
+
 def test_null_arguments_rejected_without_gpu():
     L = bgw.lib()
     assert L.bgw_pair_desc_check(None) == bgw.BGW_ERR_ARG

@@ -84,11 +84,13 @@ def test_pair_density_tiny_full(tiny):
         assert rel(tiny["M"][t], ref[t]) <= 10 * TOL
 
 
-def test_pair_density_ragged_noncubic_multik(torch_dev, handle):
-    """Non-cubic grid (12 x 18 x 16), ng = 51 (not a tile multiple), nk = 3."""
+@pytest.mark.parametrize("grid", [(12, 18, 16), (16, 18, 18), (27, 12, 36)])
+def test_pair_density_ragged_noncubic_multik(torch_dev, handle, grid):
+    """Non-cubic grids (fast and direct band kernels, generic pair kernel),
+    ng = 51 (not a tile multiple), nk = 3."""
     s = synth.small_system(n=16, ngw=123, ng=51, nv=3, nc=5, nk=3, seed=21)
     q = s["qs"][0]
-    M = gpu_M(handle, torch_dev, s, n=(12, 18, 16)).cpu().numpy()
+    M = gpu_M(handle, torch_dev, s, n=grid).cpu().numpy()
     ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
     assert rel(M, ref) <= TOL
 
@@ -110,22 +112,48 @@ def test_pair_density_kbatch_bitwise(torch_dev, handle):
     assert rel(full, oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])) <= TOL
 
 
-@pytest.mark.parametrize("n", [16, 24, 32, 48, 64])
+@pytest.mark.parametrize("n", [16, 24, 32, 48, 64, 96])
 def test_pair_density_fast_and_generic_kernels(torch_dev, handle, n):
     """Both transform paths (compile-time-size kernels and the generic
     any-length kernels) against the oracle on every fast grid length."""
-    ngw = {16: 181, 24: 411, 32: 411, 48: 881, 64: 881}[n]
+    ngw = {16: 181, 24: 411, 32: 411, 48: 881, 64: 881, 96: 1201}[n]
     s = synth.small_system(n=n, ngw=ngw, ng=113, nv=2, nc=3, nk=2, seed=n)
     q = s["qs"][0]
     ref = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
-    fast = gpu_M(handle, torch_dev, s).cpu().numpy()
-    os.environ["BGW_GENERIC_FFT"] = "1"
-    try:
-        generic = gpu_M(handle, torch_dev, s).cpu().numpy()
-    finally:
-        del os.environ["BGW_GENERIC_FFT"]
+    fast = gpu_M(handle, torch_dev, s).cpu().numpy()  # minimal alias-free box
     assert rel(fast, ref) <= TOL
-    assert rel(generic, ref) <= TOL
+    # every selectable kernel path on the caller's full grid n: default two-pass,
+    # generic, single-pass fused, two-pass variants
+    os.environ["BGW_FFT_BOX"] = "full"
+    try:
+        for env in ((), ("BGW_GENERIC_FFT", "1"), ("BGW_PAIR_FUSED", "1"), ("BGW_PAIR_VARIANT", "1"),
+                    ("BGW_PAIR_VARIANT", "2"), ("BGW_PAIR_VARIANT", "3"), ("BGW_PAIR_VARIANT", "4"),
+                    ("BGW_PAIR_RADIX8", "1")):
+            if env:
+                os.environ[env[0]] = env[1]
+            try:
+                other = gpu_M(handle, torch_dev, s).cpu().numpy()
+            finally:
+                if env:
+                    del os.environ[env[0]]
+            assert rel(other, ref) <= TOL, env
+    finally:
+        del os.environ["BGW_FFT_BOX"]
+
+
+def test_pair_density_grid_independence(torch_dev, handle):
+    """The matrix element does not depend on the (alias-free) transform box:
+    the minimal box and the full 48^3 grid give the same M."""
+    s = synth.small_system(n=48, ngw=411, ng=123, nv=2, nc=5, nk=2, seed=17)
+    box = bgw.pair_transform_box(48, s["gw"], s["qs"][0]["ge"])
+    assert max(box) < 48
+    small = gpu_M(handle, torch_dev, s).cpu().numpy()
+    os.environ["BGW_FFT_BOX"] = "full"
+    try:
+        full = gpu_M(handle, torch_dev, s).cpu().numpy()
+    finally:
+        del os.environ["BGW_FFT_BOX"]
+    assert rel(small, full) <= 1e-13
 
 
 def test_pair_density_single_plane_waves(torch_dev, handle):
