@@ -53,7 +53,7 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
 int split_workspace_bytes(long long K, int ng, size_t *bytes);
 SplitLayout split_layout(long long K, int ng, void *ws);
 int launch_split_slices(const SplitLayout &, const double2 *M, long long K, int ng, const double *w, long long t0,
-                        int nch, hipStream_t);
+                        int nch, bool with_b, hipStream_t);
 int launch_split_gemm(const SplitLayout &, int ng, int nch, int add, int *used, hipStream_t);
 int launch_split_headwing(const SplitLayout &, const double2 *M, long long K, int ng, int head, const double *w,
                           double pf, double2 *chi, int accumulate, hipStream_t);
@@ -582,17 +582,21 @@ extern "C" int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
                 BGW_TRY(launch_chi_finalize(part, ns, q.ng, q.prefactor, chi, d->accumulate, st));
             } else {
                 const SplitLayout L = split_layout(K, q.ng, rest);
+                // The slices of the unweighted side do not depend on omega: with a
+                // single super-chunk they are made once per q.
+                const bool resident_b = L.sc_pairs >= K;
                 int nslots = 0;  // slots initialised by the first (largest) super-chunk
                 for (long long t0 = 0; t0 < K; t0 += L.sc_pairs) {
                     const long long kn = std::min<long long>(L.sc_pairs, K - t0);
                     const int nch = (int)((kn + 127) / 128);
                     {
                         Timed tm(h, BGW_KERNEL_SPLIT_SLICE, st);
-                        BGW_TRY(launch_split_slices(L, (const double2 *)q.M, K, q.ng, w, t0, nch, st));
+                        BGW_TRY(launch_split_slices(L, (const double2 *)q.M, K, q.ng, w, t0, nch,
+                                                    !(resident_b && iw > 0), st));
                     }
                     Timed tm(h, BGW_KERNEL_SPLIT_HERK, st);
                     int used = 0;
-                    BGW_TRY(launch_split_gemm(L, q.ng, nch, nslots ? 1 : 0, &used, st));
+                    BGW_TRY(launch_split_gemm(L, q.ng, nch, nslots, &used, st));
                     if (!nslots) nslots = used;
                 }
                 {

@@ -39,7 +39,6 @@ constexpr int KS = 32;       // real rows per MFMA k-step (16x16x32)
 constexpr int NKS = SK / KS; // k-steps per chunk
 constexpr int NSL = 5;       // stored slices
 constexpr int TT = 64;       // output tile (G and G')
-constexpr int ROWB = 80;     // LDS row stride in bytes (64 data + 16 pad: conflict-free 16-B reads)
 
 __device__ inline double pow2(int e) { return __longlong_as_double((long long)(e + 1023) << 52); }
 
@@ -50,73 +49,92 @@ __device__ inline unsigned short bf16_bits_exact(double v) {
 }
 }  // namespace
 
-// One thread per (chunk, column).  S: [NSL][nchunk][NKS][gpad][KS] bf16 bits;
-// E: [nchunk][gpad].  Rows t0 .. t0 + nchunk*128 of M (zero beyond K).
-__global__ void k_split_slice(const double2 *__restrict__ M, long long K, int ng, int gpad,
-                              const double *__restrict__ w, long long t0, int nchunk, unsigned short *__restrict__ S,
-                              int *__restrict__ E) {
-    const int G = blockIdx.x * blockDim.x + threadIdx.x;
+// Block = one chunk x 32 columns; thread (ks, cl) owns the 16 pairs of k-step
+// ks of column G = 32 * blockIdx.x + cl and keeps them in registers, so M is
+// read once for both sides.  Side A (X_w, weighted by w) and side B (X) are
+// written when their slice pointer is non-null.
+// S: [NSL][nchunk][NKS][gpad][KS] bf16 bits; E: [nchunk][gpad].
+// Rows t0 .. t0 + nchunk*128 of M (zero beyond K).
+__global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__ M, long long K, int ng, int gpad,
+                                                     const double *__restrict__ w, long long t0, int nchunk,
+                                                     unsigned short *__restrict__ SA, int *__restrict__ EA,
+                                                     unsigned short *__restrict__ SB, int *__restrict__ EB) {
+    __shared__ double red[2][NKS][32];
+    const int cl = threadIdx.x & 31, ks = threadIdx.x >> 5;
+    const int G = blockIdx.x * 32 + cl;
     const int chunk = blockIdx.y;
-    if (G >= gpad || chunk >= nchunk) return;
-    const long long tb = t0 + (long long)chunk * SKP;
+    const long long tb = t0 + (long long)chunk * SKP + ks * (KS / 2);
     const bool col = G < ng;
-    double mx = 0.0;
-    if (col)
-        for (int i = 0; i < SKP; ++i) {
-            const long long t = tb + i;
-            if (t >= K) break;
-            const double2 m = M[t * ng + G];
-            const double s = w ? w[t] : 1.0;
-            mx = fmax(mx, fmax(fabs(s * m.x), fabs(s * m.y)));
+    double2 m[KS / 2];
+    double s[KS / 2];
+    double mxa = 0.0, mxb = 0.0;
+#pragma unroll
+    for (int i = 0; i < KS / 2; ++i) {
+        const long long t = tb + i;
+        m[i] = make_double2(0.0, 0.0);
+        s[i] = 0.0;
+        if (t < K) {
+            s[i] = w ? w[t] : 1.0;
+            if (col) m[i] = M[t * ng + G];
         }
-    int e = 0;
-    if (mx > 0.0) (void)frexp(mx, &e);  // mx < 2^e
-    E[(size_t)chunk * gpad + G] = e;
-    const double up = pow2(8 - e);
+        mxa = fmax(mxa, fabs(s[i]) * fmax(fabs(m[i].x), fabs(m[i].y)));
+        mxb = fmax(mxb, fmax(fabs(m[i].x), fabs(m[i].y)));
+    }
+    red[0][ks][cl] = mxa;
+    red[1][ks][cl] = mxb;
+    __syncthreads();
+    mxa = 0.0;
+    mxb = 0.0;
+#pragma unroll
+    for (int k = 0; k < NKS; ++k) {
+        mxa = fmax(mxa, red[0][k][cl]);
+        mxb = fmax(mxb, red[1][k][cl]);
+    }
+    if (G >= gpad) return;
     const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
-    for (int i4 = 0; i4 < SKP; i4 += 4) {
-        // 4 pairs -> 8 consecutive k' values
-        unsigned short d[NSL][8];
+    const size_t dst0 = (((size_t)chunk * NKS + ks) * gpad + G) * KS;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long long t = tb + i4 + j;
-            double2 m = make_double2(0.0, 0.0);
-            double s = 0.0;
-            if (col && t < K) {
-                m = M[t * ng + G];
-                s = w ? w[t] : 1.0;
+    for (int side = 0; side < 2; ++side) {
+        unsigned short *S = side ? SB : SA;
+        int *E = side ? EB : EA;
+        if (!S) continue;
+        const double mx = side ? mxb : mxa;
+        int e = 0;
+        if (mx > 0.0) (void)frexp(mx, &e);  // mx < 2^e
+        if (ks == 0) E[(size_t)chunk * gpad + G] = e;
+        const double up = pow2(8 - e);
+#pragma unroll
+        for (int i4 = 0; i4 < KS / 2; i4 += 4) {
+            unsigned short d[NSL][8];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int part = 0; part < 2; ++part) {
+                    const double v = part ? m[i4 + j].y : m[i4 + j].x;
+                    const double y = (side ? v : s[i4 + j] * v) * up;
+                    const double d1 = rint(y);
+                    double r = (y - d1) * 256.0;
+                    const double d2 = rint(r);
+                    r = (r - d2) * 256.0;
+                    const double d3 = rint(r);
+                    r = (r - d3) * 256.0;
+                    const double d4 = rint(r);
+                    const int q = 2 * j + part;
+                    d[0][q] = bf16_bits_exact(d1);
+                    d[1][q] = bf16_bits_exact(d2);
+                    d[2][q] = bf16_bits_exact(d3);
+                    d[3][q] = bf16_bits_exact(d3 * 0.00390625);
+                    d[4][q] = bf16_bits_exact(d4 * 0.00390625);
+                }
+#pragma unroll
+            for (int sl = 0; sl < NSL; ++sl) {
+                uint4 pk;
+                pk.x = d[sl][0] | ((unsigned)d[sl][1] << 16);
+                pk.y = d[sl][2] | ((unsigned)d[sl][3] << 16);
+                pk.z = d[sl][4] | ((unsigned)d[sl][5] << 16);
+                pk.w = d[sl][6] | ((unsigned)d[sl][7] << 16);
+                *reinterpret_cast<uint4 *>(S + sl * slice_stride + dst0 + 2 * i4) = pk;
             }
-#pragma unroll
-            for (int part = 0; part < 2; ++part) {
-                const double x = s * (part ? m.y : m.x);
-                const double y = x * up;
-                const double d1 = rint(y);
-                double r = (y - d1) * 256.0;
-                const double d2 = rint(r);
-                r = (r - d2) * 256.0;
-                const double d3 = rint(r);
-                r = (r - d3) * 256.0;
-                const double d4 = rint(r);
-                const int q = 2 * j + part;
-                d[0][q] = bf16_bits_exact(d1);
-                d[1][q] = bf16_bits_exact(d2);
-                d[2][q] = bf16_bits_exact(d3);
-                d[3][q] = bf16_bits_exact(d3 * 0.00390625);
-                d[4][q] = bf16_bits_exact(d4 * 0.00390625);
-            }
-        }
-        const int kp = 2 * i4;  // first k' of the group
-        const int ks = kp / KS, kk = kp % KS;
-#pragma unroll
-        for (int sl = 0; sl < NSL; ++sl) {
-            uint4 pk;
-            pk.x = d[sl][0] | ((unsigned)d[sl][1] << 16);
-            pk.y = d[sl][2] | ((unsigned)d[sl][3] << 16);
-            pk.z = d[sl][4] | ((unsigned)d[sl][5] << 16);
-            pk.w = d[sl][6] | ((unsigned)d[sl][7] << 16);
-            unsigned short *dst =
-                S + sl * slice_stride + (((size_t)chunk * NKS + ks) * gpad + G) * KS + kk;
-            *reinterpret_cast<uint4 *>(dst) = pk;
         }
     }
 }
@@ -137,131 +155,220 @@ __device__ inline uint4 swap_neg(uint4 u) {
     return r;
 }
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16((a), (b), (c), 0, 0, 0)
-}  // namespace
 
-// grid.x: upper-triangle 64x64 tiles, grid.y: splits of the chunk range.
-// part[split][ng][ng] (+)= chunk sums in FP64 (no prefactor).
-__global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__restrict__ SA,
-                                                    const int *__restrict__ EA,
-                                                    const unsigned short *__restrict__ SB,
-                                                    const int *__restrict__ EB, int ng, int gpad, int nt,
-                                                    int nchunk, int chunks_per_split, double2 *__restrict__ part,
-                                                    int add) {
-    __shared__ __attribute__((aligned(16))) unsigned char As[NSL][TT][ROWB];
-    __shared__ __attribute__((aligned(16))) unsigned char Bs[NSL][TT][ROWB];
+// LDS stage: [side][slice][64 rows][64 B], the four 16-B segments of row r
+// stored in the order seg ^ (r & 3) (conflict-free 16-B fragment reads).
+constexpr int SLICE_LDS = TT * KS * 2;          // 4096 B
+constexpr int STAGE_LDS = 2 * NSL * SLICE_LDS;  // 40960 B
 
-    int u = blockIdx.x, ti = 0;
-    while (u >= nt - ti) {
-        u -= nt - ti;
-        ++ti;
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+struct HerkAcc {
+    double4_t re[2][2], im[2][2];
+    float4_t g[3][2][2][2];  // [group][re/im][a][b]
+};
+
+// Copy k-step `step` of the A (rows G0..) and B (rows H0..) slices into a
+// stage with direct global->LDS loads: wave w fills rows 16w..16w+15 of every
+// slice, lane L the 16 B of row 16w + L/4 at stored segment L%4.
+__device__ __forceinline__ void herk_issue(unsigned char *stage, const unsigned short *ga,
+                                           const unsigned short *gb, size_t slice_stride, long long step,
+                                           int gpad, int wave) {
+    const size_t off = (size_t)step * gpad * KS;
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl) {
+        __builtin_amdgcn_global_load_lds((const void *)(ga + sl * slice_stride + off),
+                                         (lds_void_t *)(stage + sl * SLICE_LDS + wave * 1024), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(gb + sl * slice_stride + off),
+                                         (lds_void_t *)(stage + (NSL + sl) * SLICE_LDS + wave * 1024), 16, 0, 0);
     }
-    const int tj = ti + u;
-    const int G0 = ti * TT, H0 = tj * TT;
-    const int c0 = blockIdx.y * chunks_per_split;
-    const int c1 = min(nchunk, c0 + chunks_per_split);
-    const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
+}
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int li = lane & 15, lq = lane >> 4;
+__device__ __forceinline__ uint4 frag(const unsigned char *slice, int row, int lq) {
+    return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
+}
 
-    double4_t are[2][2], aim[2][2];
+// Ten BF16 products per (Re, Im) for the wave's 32x32 block of one k-step.
+__device__ __forceinline__ void herk_compute(const unsigned char *stage, HerkAcc &acc, int wr, int wc, int li,
+                                             int lq) {
+    const unsigned char *As = stage, *Bs = stage + NSL * SLICE_LDS;
+    uint4 af[NSL][2];
+#pragma unroll
+    for (int sl = 0; sl < NSL; ++sl)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[sl][a] = frag(As + sl * SLICE_LDS, wr * 32 + 16 * a + li, lq);
+    // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d3', 4 = d4'
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        uint4 bf[NSL];
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) bf[sl] = frag(Bs + sl * SLICE_LDS, wc * 32 + 16 * b + li, lq);
+        const bf16x8_t b1 = as_bf16x8(bf[0]), b2 = as_bf16x8(bf[1]), b3 = as_bf16x8(bf[2]);
+        const bf16x8_t b3p = as_bf16x8(bf[3]), b4p = as_bf16x8(bf[4]);
+        const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0])), y2 = as_bf16x8(swap_neg(bf[1]));
+        const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2])), y3p = as_bf16x8(swap_neg(bf[3]));
+        const bf16x8_t y4p = as_bf16x8(swap_neg(bf[4]));
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const bf16x8_t a1 = as_bf16x8(af[0][a]), a2 = as_bf16x8(af[1][a]), a3 = as_bf16x8(af[2][a]);
+            const bf16x8_t a3p = as_bf16x8(af[3][a]), a4p = as_bf16x8(af[4][a]);
+            float4_t(&g0)[2][2][2] = acc.g[0];
+            float4_t(&g1)[2][2][2] = acc.g[1];
+            float4_t(&g2)[2][2][2] = acc.g[2];
+            g0[0][a][b] = MFMA(a1, b1, g0[0][a][b]);
+            g0[1][a][b] = MFMA(a1, y1, g0[1][a][b]);
+            g1[0][a][b] = MFMA(a1, b2, g1[0][a][b]);
+            g1[1][a][b] = MFMA(a1, y2, g1[1][a][b]);
+            g1[0][a][b] = MFMA(a2, b1, g1[0][a][b]);
+            g1[1][a][b] = MFMA(a2, y1, g1[1][a][b]);
+            g2[0][a][b] = MFMA(a1, b3, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a1, y3, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a2, b2, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a2, y2, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a3, b1, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a3, y1, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a1, b4p, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a1, y4p, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a2, b3p, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a2, y3p, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a3p, b2, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a3p, y2, g2[1][a][b]);
+            g2[0][a][b] = MFMA(a4p, b1, g2[0][a][b]);
+            g2[1][a][b] = MFMA(a4p, y1, g2[1][a][b]);
+        }
+    }
+}
+
+// Chunk end: combine the three FP32 groups in FP64 with the chunk-column
+// scales and clear them.  D layout of 16x16x32: lane l, register r -> row
+// 4 (l/16) + r, col l % 16.
+__device__ __forceinline__ void herk_flush(HerkAcc &acc, const int *__restrict__ EA, const int *__restrict__ EB,
+                                           long long ch, int gpad, int G0, int H0, int wr, int wc, int li, int lq) {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            are[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
-            aim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+            const int H = H0 + wc * 32 + 16 * b + li;
+            const int eb = EB[(size_t)ch * gpad + H];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
+                const double sc = pow2(EA[(size_t)ch * gpad + G] + eb - 16);
+                const double vre = (double)acc.g[0][0][a][b][r] + (double)acc.g[1][0][a][b][r] * 0.00390625 +
+                                   (double)acc.g[2][0][a][b][r] * 0.0000152587890625;
+                const double vim = (double)acc.g[0][1][a][b][r] + (double)acc.g[1][1][a][b][r] * 0.00390625 +
+                                   (double)acc.g[2][1][a][b][r] * 0.0000152587890625;
+                acc.re[a][b][r] += vre * sc;
+                acc.im[a][b][r] += vim * sc;
+            }
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
         }
+}
+}  // namespace
 
-    for (int ch = c0; ch < c1; ++ch) {
-        float4_t g[3][2][2][2];  // [group][re/im][a][b]
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) g[p][ri][a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
-
-        for (int ks = 0; ks < NKS; ++ks) {
-            __syncthreads();
-            // stage 5 slices x 64 rows x 64 B for A and B: 1280 16-byte pieces each
-            for (int e = tid; e < NSL * TT * 4; e += 256) {
-                const int sl = e / (TT * 4), rem = e % (TT * 4), row = rem >> 2, seg = rem & 3;
-                const size_t off = sl * slice_stride + (((size_t)ch * NKS + ks) * gpad) * KS;
-                const uint4 va = *reinterpret_cast<const uint4 *>(SA + off + (size_t)(G0 + row) * KS + seg * 8);
-                const uint4 vb = *reinterpret_cast<const uint4 *>(SB + off + (size_t)(H0 + row) * KS + seg * 8);
-                *reinterpret_cast<uint4 *>(&As[sl][row][seg * 16]) = va;
-                *reinterpret_cast<uint4 *>(&Bs[sl][row][seg * 16]) = vb;
-            }
-            __syncthreads();
-            uint4 af[NSL][2], bf[NSL][2];
-#pragma unroll
-            for (int sl = 0; sl < NSL; ++sl)
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    af[sl][a] = *reinterpret_cast<const uint4 *>(&As[sl][wr * 32 + 16 * a + li][lq * 16]);
-                    bf[sl][a] = *reinterpret_cast<const uint4 *>(&Bs[sl][wc * 32 + 16 * a + li][lq * 16]);
-                }
-            // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d3', 4 = d4'
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const bf16x8_t b1 = as_bf16x8(bf[0][b]), b2 = as_bf16x8(bf[1][b]), b3 = as_bf16x8(bf[2][b]);
-                const bf16x8_t b3p = as_bf16x8(bf[3][b]), b4p = as_bf16x8(bf[4][b]);
-                const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0][b])), y2 = as_bf16x8(swap_neg(bf[1][b]));
-                const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2][b])), y3p = as_bf16x8(swap_neg(bf[3][b]));
-                const bf16x8_t y4p = as_bf16x8(swap_neg(bf[4][b]));
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const bf16x8_t a1 = as_bf16x8(af[0][a]), a2 = as_bf16x8(af[1][a]), a3 = as_bf16x8(af[2][a]);
-                    const bf16x8_t a3p = as_bf16x8(af[3][a]), a4p = as_bf16x8(af[4][a]);
-                    g[0][0][a][b] = MFMA(a1, b1, g[0][0][a][b]);
-                    g[0][1][a][b] = MFMA(a1, y1, g[0][1][a][b]);
-                    g[1][0][a][b] = MFMA(a1, b2, g[1][0][a][b]);
-                    g[1][0][a][b] = MFMA(a2, b1, g[1][0][a][b]);
-                    g[1][1][a][b] = MFMA(a1, y2, g[1][1][a][b]);
-                    g[1][1][a][b] = MFMA(a2, y1, g[1][1][a][b]);
-                    g[2][0][a][b] = MFMA(a1, b3, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a2, b2, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a3, b1, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a1, b4p, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a2, b3p, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a3p, b2, g[2][0][a][b]);
-                    g[2][0][a][b] = MFMA(a4p, b1, g[2][0][a][b]);
-                    g[2][1][a][b] = MFMA(a1, y3, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a2, y2, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a3, y1, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a1, y4p, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a2, y3p, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a3p, y2, g[2][1][a][b]);
-                    g[2][1][a][b] = MFMA(a4p, y1, g[2][1][a][b]);
-                }
-            }
-        }
-        // flush the chunk in FP64 with the chunk-column scales
-        // D layout of 16x16x32: lane l, register r -> row 4 (l/16) + r, col l % 16
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int H = H0 + wc * 32 + 16 * b + li;
-                const int eb = EB[(size_t)ch * gpad + H];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
-                    const double sc = pow2(EA[(size_t)ch * gpad + G] + eb - 16);
-                    const double vre = (double)g[0][0][a][b][r] + (double)g[1][0][a][b][r] * 0.00390625 +
-                                       (double)g[2][0][a][b][r] * 0.0000152587890625;
-                    const double vim = (double)g[0][1][a][b][r] + (double)g[1][1][a][b][r] * 0.00390625 +
-                                       (double)g[2][1][a][b][r] * 0.0000152587890625;
-                    are[a][b][r] += vre * sc;
-                    aim[a][b][r] += vim * sc;
-                }
-            }
+// Upper-triangle tile number u -> (ti, tj) in grouped order: bands of four
+// tile rows, each band walked column by column.  Consecutive tiles then
+// share a few A row blocks and B column blocks, which is what the blocks
+// co-resident on one XCD read at the same time.
+__device__ inline void grouped_tile(int u, int nt, int &ti, int &tj) {
+    constexpr int R = 4;
+    int r0 = 0;
+    for (;; r0 += R) {
+        const int r1 = min(r0 + R - 1, nt - 1);
+        int cnt = 0;
+        for (int c = r0; c < nt; ++c) cnt += min(c, r1) - r0 + 1;
+        if (u < cnt || r1 == nt - 1) break;
+        u -= cnt;
     }
-    double2 *o = part + (size_t)blockIdx.y * ng * ng;
+    const int r1 = min(r0 + R - 1, nt - 1);
+    for (int c = r0;; ++c) {
+        const int rows = min(c, r1) - r0 + 1;
+        if (u < rows || c == nt - 1) {
+            ti = r0 + u;
+            tj = c;
+            return;
+        }
+        u -= rows;
+    }
+}
+
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// With nsplit a multiple of 8, XCD x works through splits x, x + 8, ... one
+// after another, and within a split through the tiles in grouped order, so
+// the blocks resident on an XCD stream one range of chunks through its L2
+// and share most of their rows.  Otherwise block b takes split b % nsplit and
+// grouped tile b / nsplit.
+__global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__restrict__ SA,
+                                                    const int *__restrict__ EA,
+                                                    const unsigned short *__restrict__ SB,
+                                                    const int *__restrict__ EB, int ng, int gpad, int nt,
+                                                    int nchunk, int nsplit, int chunks_per_split,
+                                                    double2 *__restrict__ part, int add) {
+    __shared__ __attribute__((aligned(1024))) unsigned char stage0[STAGE_LDS];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage1[STAGE_LDS];
+
+    const int ntiles = nt * (nt + 1) / 2;
+    int split, u;
+    if (nsplit % 8 == 0) {
+        const int x = blockIdx.x % 8, j = blockIdx.x / 8;
+        split = x + 8 * (j / ntiles);
+        u = j % ntiles;
+    } else {
+        split = blockIdx.x % nsplit;
+        u = blockIdx.x / nsplit;
+    }
+    int ti, tj;
+    grouped_tile(u, nt, ti, tj);
+    const int G0 = ti * TT, H0 = tj * TT;
+    const int c0 = split * chunks_per_split;
+    const int c1 = min(nchunk, c0 + chunks_per_split);
+    const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wr = wave >> 1, wc = wave & 1;
+    const int li = lane & 15, lq = lane >> 4;
+
+    // loader source of this lane: row 16*wave + lane/4, logical segment (lane%4) ^ (row%4)
+    const int lrow = 16 * wave + (lane >> 2);
+    const int lseg = (lane & 3) ^ (lrow & 3);
+    const unsigned short *ga = SA + (size_t)(G0 + lrow) * KS + lseg * 8;
+    const unsigned short *gb = SB + (size_t)(H0 + lrow) * KS + lseg * 8;
+
+    HerkAcc acc;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            acc.re[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+            acc.im[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
+        }
+
+    const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;  // s1 - s0 is a multiple of NKS (even)
+    herk_issue(stage0, ga, gb, slice_stride, s0, gpad, wave);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (long long s = s0; s < s1; s += 2) {
+        herk_issue(stage1, ga, gb, slice_stride, s + 1, gpad, wave);
+        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs they overlap
+        herk_compute(stage0, acc, wr, wc, li, lq);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (s + 2 < s1) herk_issue(stage0, ga, gb, slice_stride, s + 2, gpad, wave);
+        __builtin_amdgcn_sched_barrier(0);
+        herk_compute(stage1, acc, wr, wc, li, lq);
+        if (((s + 1) % NKS) == NKS - 1) herk_flush(acc, EA, EB, (s + 1) / NKS, gpad, G0, H0, wr, wc, li, lq);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    double2 *o = part + (size_t)split * ng * ng;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -271,7 +378,7 @@ __global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__rest
                 const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
                 const int H = H0 + wc * 32 + 16 * b + li;
                 if (G < ng && H < ng) {
-                    double2 v = make_double2(are[a][b][r], aim[a][b][r]);
+                    double2 v = make_double2(acc.re[a][b][r], acc.im[a][b][r]);
                     if (add) v = cadd(v, o[(size_t)G * ng + H]);
                     o[(size_t)G * ng + H] = v;
                 }
@@ -325,6 +432,43 @@ struct SplitPlan {
     size_t slice_bytes;  // one side, one super-chunk
 };
 
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+// Splits of the chunk range: a multiple of the XCD count (8) when there are
+// enough chunks, chosen so that tiles * nsplit fills whole waves of one block
+// per CU as evenly as possible.
+int choose_nsplit(long long tiles, long long nch) {
+    const long long cus = device_cus();
+    if (nch < 8) return (int)std::max<long long>(1, nch);
+    int best = 8;
+    double best_eff = 0.0;
+    for (int ns = 8; ns <= 64 && ns <= nch; ns += 8) {
+        const long long cps = (nch + ns - 1) / ns;
+        const long long used = (nch + cps - 1) / cps;
+        if (used != ns) continue;  // keep the XCD-aligned mapping
+        const long long blocks = tiles * used;
+        const long long rounds = (blocks + cus - 1) / cus;
+        // useful chunk-steps over issued block-rounds of the longest block
+        const double eff = (double)(tiles * nch) / (double)(rounds * cus * cps);
+        if (eff > best_eff * 1.02) {
+            best = ns;
+            best_eff = eff;
+        }
+    }
+    return best;
+}
+
 SplitPlan make_plan(long long K, int ng) {
     SplitPlan p;
     p.gpad = (ng + TT - 1) / TT * TT;
@@ -338,9 +482,7 @@ SplitPlan make_plan(long long K, int ng) {
     long long nch = std::max<long long>(1, std::min<long long>(nch_total, cap / per_chunk));
     p.sc_pairs = nch * SKP;
     p.slice_bytes = per_chunk * nch;
-    long long want = (2048 + p.tiles - 1) / p.tiles;
-    want = std::min<long long>(want, nch);
-    p.nsplit = (int)std::max<long long>(1, std::min<long long>(want, 64));
+    p.nsplit = choose_nsplit(p.tiles, nch);
     return p;
 }
 
@@ -382,22 +524,24 @@ SplitLayout split_layout(long long K, int ng, void *ws) {
 }
 
 int launch_split_slices(const SplitLayout &L, const double2 *M, long long K, int ng, const double *w, long long t0,
-                        int nch, hipStream_t st) {
-    dim3 sg((L.gpad + 255) / 256, nch);
-    hipLaunchKernelGGL(k_split_slice, sg, dim3(256), 0, st, M, K, ng, L.gpad, w, t0, nch, L.SA, L.EA);
-    hipLaunchKernelGGL(k_split_slice, sg, dim3(256), 0, st, M, K, ng, L.gpad, (const double *)nullptr, t0, nch, L.SB,
-                       L.EB);
+                        int nch, bool with_b, hipStream_t st) {
+    dim3 sg(L.gpad / 32, nch);
+    hipLaunchKernelGGL(k_split_slice, sg, dim3(256), 0, st, M, K, ng, L.gpad, w, t0, nch, L.SA, L.EA,
+                       with_b ? L.SB : (unsigned short *)nullptr, with_b ? L.EB : (int *)nullptr);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
 
-// Returns the number of split slots written in *used.
+// Writes split slots [0, *used).  With add != 0 the slots [0, add) hold the
+// sums of earlier super-chunks and at most that many are used.
 int launch_split_gemm(const SplitLayout &L, int ng, int nch, int add, int *used, hipStream_t st) {
-    const int ns = std::min(L.nsplit, nch);
+    int ns = std::min(L.nsplit, nch);
+    if (nch < L.sc_pairs / SKP) ns = choose_nsplit(L.tiles, nch);  // short last super-chunk
+    ns = std::min(ns, add > 0 ? add : L.nsplit);
     const int cps = (nch + ns - 1) / ns;
     const int nsplit_used = (nch + cps - 1) / cps;
-    hipLaunchKernelGGL(k_herk_split, dim3((unsigned)L.tiles, nsplit_used), dim3(256), 0, st, L.SA, L.EA, L.SB, L.EB,
-                       ng, L.gpad, L.nt, nch, cps, L.part, add);
+    hipLaunchKernelGGL(k_herk_split, dim3((unsigned)(L.tiles * nsplit_used)), dim3(256), 0, st, L.SA, L.EA,
+                       L.SB, L.EB, ng, L.gpad, L.nt, nch, nsplit_used, cps, L.part, add > 0 ? 1 : 0);
     BGW_HIP(hipGetLastError());
     *used = nsplit_used;
     return BGW_OK;
