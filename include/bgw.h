@@ -144,9 +144,35 @@ typedef struct {
     const double *omega; /* HOST f64 [nw], imaginary-axis |omega| in eV, >= 0 */
     int precision;       /* BGW_FP64 or BGW_SPLIT_BF16 */
     int accumulate;      /* 0: chi = result; 1: chi += result (K-chunked sums) */
+    int use_graph;       /* 1: capture the call's launch sequence into a HIP graph the first
+                            time this exact descriptor (same pointers, sizes, frequencies) is
+                            seen, and replay the graph on later calls; 0: launch directly */
 } bgw_chi_desc;
 
+/* All q entries and all frequencies form one batch of (q, omega) problems.
+ * FP64: one launch for the weights, one persistent rank-K-update launch over
+ * every (problem, output tile, K range) work item, one finalize launch.
+ * Split: weights in one launch, then slicing, BF16 GEMM, finalize and FP64
+ * head row per problem.  Output tiles and K-split counts per size class
+ * (ng rounded up to 512, ceil(log2 K)) come from bgw_autotune when it has
+ * run, from fixed rules otherwise.  Work is ordered on `stream`; calls on one
+ * handle must not run concurrently (they share its workspace). */
 int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
+
+/* Autotuner.  For every size class present in d (precision taken from d),
+ * times the candidate configurations (FP64: output tile 32 or 64 and the
+ * K-split density; split: the GEMM's K-split count) on the class's first q
+ * and first frequency, with K cut to at most 2^17 pairs, and keeps the
+ * fastest in the handle.  Synchronises `stream`.  Overwrites chi[0] of the q
+ * entries it times (an output buffer).  When the environment variable
+ * BGW_TUNE_CACHE names a file, the choices are appended to it as JSON lines
+ * and read back by later handles of the same device type. */
+int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
+
+/* Configuration bgw_chi0 uses for one size class: cfg[0] FP64 output tile,
+ * cfg[1] FP64 target work items per compute unit, cfg[2] split GEMM K-split
+ * count (0 = rule), cfg[3] 1 if it comes from the autotuner. */
+int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cfg);
 
 /* ------------------------------------------------------------------------
  * Dielectric matrix and its inverse

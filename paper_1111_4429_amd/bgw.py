@@ -32,7 +32,8 @@ SPLIT_BF16 = 1
 EXPORTS = [
     "bgw_version", "bgw_create", "bgw_destroy", "bgw_last_error", "bgw_workspace_bytes",
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
-    "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box",
+    "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
+    "bgw_tuned_config",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -83,6 +84,7 @@ class ChiDesc(ctypes.Structure):
         ("omega", ctypes.POINTER(ctypes.c_double)),
         ("precision", ctypes.c_int),
         ("accumulate", ctypes.c_int),
+        ("use_graph", ctypes.c_int),
     ]
 
 
@@ -112,9 +114,11 @@ def lib():
         L.bgw_get_timing.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
         L.bgw_reset_timing.argtypes = [P]
         L.bgw_pair_transform_box.argtypes = [ctypes.POINTER(PairDesc), ctypes.POINTER(ctypes.c_int)]
+        L.bgw_autotune.argtypes = [P, ctypes.POINTER(ChiDesc), P]
+        L.bgw_tuned_config.argtypes = [P, I, I, ctypes.c_longlong, ctypes.POINTER(ctypes.c_int)]
         for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
-                  "bgw_pair_transform_box"):
+                  "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -243,15 +247,13 @@ class Handle:
         return M
 
     # ---------------------------------------------------------------- chi0
-    def chi0(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64, accumulate: bool = False,
-             chis: Optional[List] = None):
-        """qs: list of dicts {M, ev, ec, nk, nv, nc, head, prefactor} (device tensors).
-        Returns the list of chi tensors [nw][ng][ng] (complex128)."""
+    def _chi_desc(self, qs: Sequence[dict], omega: Sequence[float], precision: int, accumulate: bool,
+                  chis: Optional[List], use_graph: bool):
         import torch
         om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1)
         arr = (ChiQ * len(qs))()
         outs = []
-        keep = []
+        keep = [om, arr]
         for i, q in enumerate(qs):
             M = q["M"]
             ng = int(M.shape[1])
@@ -282,8 +284,33 @@ class Handle:
         d.omega = om.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         d.precision = int(precision)
         d.accumulate = 1 if accumulate else 0
+        d.use_graph = 1 if use_graph else 0
+        return d, outs, keep
+
+    def chi0(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64, accumulate: bool = False,
+             chis: Optional[List] = None, use_graph: bool = False):
+        """qs: list of dicts {M, ev, ec, nk, nv, nc, head, prefactor} (device tensors); all q and all
+        frequencies form one batch.  Returns the list of chi tensors [nw][ng][ng] (complex128).
+        use_graph: capture the call into a HIP graph on first use of this exact descriptor and
+        replay it afterwards (the tensors' addresses are part of the descriptor)."""
+        d, outs, keep = self._chi_desc(qs, omega, precision, accumulate, chis, use_graph)
         _check(lib().bgw_chi0(self._h, ctypes.byref(d), _stream()))
+        del keep
         return outs
+
+    def autotune(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64,
+                 chis: Optional[List] = None):
+        """Time the chi-sum candidates for every size class in qs and keep the fastest
+        (overwrites chis[i][0] of the timed q)."""
+        d, outs, keep = self._chi_desc(qs, omega, precision, False, chis, False)
+        _check(lib().bgw_autotune(self._h, ctypes.byref(d), _stream()))
+        del keep
+        return outs
+
+    def tuned_config(self, precision: int, ng: int, K: int) -> dict:
+        cfg = (ctypes.c_int * 4)()
+        _check(lib().bgw_tuned_config(self._h, int(precision), int(ng), int(K), cfg))
+        return {"tile": cfg[0], "items_per_cu": cfg[1], "split_nsplit": cfg[2], "tuned": bool(cfg[3])}
 
     # ---------------------------------------------------------------- eps^-1
     def eps_inv(self, vcoul, chi, epsinv=None, info=None):

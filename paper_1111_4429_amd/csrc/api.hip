@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "handle.h"
 
 namespace bgw {
 
@@ -38,45 +38,28 @@ int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int re
                   hipStream_t st);
 int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &, const AxisPlan &,
                          const AxisPlan &, const SphereMaps &, int rwy, double2 *grids, hipStream_t);
-int launch_weights(const double *ev, const double *ec, int nk, int nv, int nc, double omega_ev, double *w,
-                   hipStream_t);
-int herk_f64_splits(long long K, int ng);
-int launch_herk_f64(const double2 *M, long long K, int ng, const double *w, int nsplit, double2 *part,
-                    hipStream_t);
-int launch_chi_finalize(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
-                        hipStream_t);
 int launch_eps_build(const double2 *chi, const double *v, int ng, int nw, double2 *eps, hipStream_t);
 size_t gje_workspace_bytes(int n, int nmat, int R);
 int gje_rows_per_wg(int n);
 int gje_max_group(int n);
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t);
-int split_workspace_bytes(long long K, int ng, size_t *bytes);
-SplitLayout split_layout(long long K, int ng, void *ws);
-int launch_split_slices(const SplitLayout &, const double2 *M, long long K, int ng, const double *w, long long t0,
-                        int nch, bool with_b, hipStream_t);
-int launch_split_gemm(const SplitLayout &, int ng, int nch, int add, int *used, hipStream_t);
-int launch_split_headwing(const SplitLayout &, const double2 *M, long long K, int ng, int head, const double *w,
-                          double pf, double2 *chi, int accumulate, hipStream_t);
-int launch_chi_finalize_skip(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
-                             int skip, hipStream_t);
 
 namespace {
 thread_local std::string g_err;
-constexpr int kMaxNg = 8192;
 constexpr size_t kLdsBudget = 150 * 1024;
 }  // namespace
 
 void set_error(const std::string &msg) { g_err = msg; }
 void clear_error() { g_err.clear(); }
 
-static int fail(int code, const std::string &msg) {
+int fail(int code, const std::string &msg) {
     set_error(msg);
     return code;
 }
 
 // ---------------------------------------------------------------- validation (host only)
 
-static bool is_2a3b(int n) {
+bool is_2a3b(int n) {
     if (n < 1) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
@@ -152,44 +135,6 @@ extern "C" const char *bgw_last_error(void) { return g_err.c_str(); }
 
 namespace bgw {
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-};
-
-struct FFTPlan {
-    int box[3];  // transform box actually used (see transform_box)
-    AxisPlan ax[3];
-    SphereMaps sm;
-    std::vector<std::unique_ptr<DevBuf>> bufs;
-};
-
-}  // namespace bgw
-
-struct bgw_handle_s {
-    int device = 0;
-    DevBuf ws;
-    std::map<std::string, std::unique_ptr<bgw::FFTPlan>> plans;
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-    double total_ms[BGW_KERNEL_COUNT] = {};
-    long long launches[BGW_KERNEL_COUNT] = {};
-    ~bgw_handle_s() {
-        for (auto &p : pending) {
-            pool.push_back(p.second.first);
-            pool.push_back(p.second.second);
-        }
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    }
-};
-
-namespace bgw {
-
 static int upload(FFTPlan &pl, const void *host, size_t bytes, const void **dev) {
     auto b = std::make_unique<DevBuf>();
     BGW_HIP(hipMalloc(&b->p, std::max<size_t>(bytes, 16)));
@@ -214,7 +159,7 @@ static size_t env_limit() {
     return (size_t)std::strtoull(s, nullptr, 10);
 }
 
-static int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st) {
+int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st) {
     if (h->ws.bytes >= bytes) return BGW_OK;
     if (bytes > env_limit()) return fail(BGW_ERR_NOMEM, "workspace request exceeds BGW_WORKSPACE_LIMIT");
     BGW_HIP(hipStreamSynchronize(st));
@@ -374,42 +319,13 @@ static int pick_lc(int n2, int n3, size_t fixed_bytes) {
     return lc;
 }
 
-static hipEvent_t take_event(bgw_handle_t h) {
-    if (!h->pool.empty()) {
-        hipEvent_t e = h->pool.back();
-        h->pool.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    return e;
-}
-
-// Records a start event on construction and an end event on destruction.
-struct Timed {
-    bgw_handle_t h;
-    int id;
-    hipStream_t st;
-    hipEvent_t a = nullptr;
-    Timed(bgw_handle_t h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
-        if (h->timing && (a = take_event(h)) != nullptr) (void)hipEventRecord(a, st);
-    }
-    ~Timed() {
-        if (!a) return;
-        hipEvent_t b = take_event(h);
-        if (!b) return;
-        (void)hipEventRecord(b, st);
-        h->pending.push_back({id, {a, b}});
-    }
-};
-
 // BGW_GENERIC_FFT=1 forces the generic (any 2^a 3^b length) transform kernels.
 static bool generic_fft() {
     const char *s = std::getenv("BGW_GENERIC_FFT");
     return s && *s == '1';
 }
 
-static int set_device(bgw_handle_t h) {
+int set_device(bgw_handle_t h) {
     BGW_HIP(hipSetDevice(h->device));
     return BGW_OK;
 }
@@ -522,98 +438,6 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
     return BGW_OK;
 }
 
-static int check_chi_desc(const bgw_chi_desc *d) {
-    if (!d || d->nq < 1 || !d->q || d->nw < 1 || !d->omega) return fail(BGW_ERR_ARG, "bad chi descriptor");
-    if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16)
-        return fail(BGW_ERR_ARG, "unknown precision");
-    for (int i = 0; i < d->nw; ++i)
-        if (!(d->omega[i] >= 0.0)) return fail(BGW_ERR_ARG, "frequencies must be >= 0");
-    for (int i = 0; i < d->nq; ++i) {
-        const bgw_chi_q &q = d->q[i];
-        if (q.ng < 1 || q.nk < 1 || q.nv < 1 || q.nc < 1) return fail(BGW_ERR_ARG, "chi q entry: sizes must be >= 1");
-        if (q.ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "chi q entry: ng > 8192");
-        if (!q.M || !q.ev || !q.ec || !q.chi) return fail(BGW_ERR_ARG, "chi q entry: null pointer");
-        if (q.head < -1 || q.head >= q.ng) return fail(BGW_ERR_ARG, "chi q entry: head index out of range");
-    }
-    return BGW_OK;
-}
-
-extern "C" int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
-    clear_error();
-    BGW_TRY(check_chi_desc(d));
-    if (!h) return fail(BGW_ERR_ARG, "null handle");
-    BGW_TRY(set_device(h));
-    hipStream_t st = (hipStream_t)stream;
-    // workspace: weights [K] + partial sums
-    size_t need = 0;
-    for (int i = 0; i < d->nq; ++i) {
-        const bgw_chi_q &q = d->q[i];
-        const long long K = (long long)q.nk * q.nv * q.nc;
-        size_t b = 0;
-        if (d->precision == BGW_FP64) {
-            const int ns = herk_f64_splits(K, q.ng);
-            b = 256 + sizeof(double) * K + sizeof(double2) * (size_t)ns * q.ng * q.ng;
-        } else {
-            BGW_TRY(split_workspace_bytes(K, q.ng, &b));
-            b += 256 + sizeof(double) * K;
-        }
-        need = std::max(need, b);
-    }
-    BGW_TRY(ensure_ws(h, need, st));
-    for (int i = 0; i < d->nq; ++i) {
-        const bgw_chi_q &q = d->q[i];
-        const long long K = (long long)q.nk * q.nv * q.nc;
-        double *w = (double *)h->ws.p;
-        void *rest = (char *)h->ws.p + ((sizeof(double) * K + 255) / 256) * 256;
-        for (int iw = 0; iw < d->nw; ++iw) {
-            double2 *chi = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
-            {
-                Timed tm(h, BGW_KERNEL_WEIGHTS, st);
-                BGW_TRY(launch_weights(q.ev, q.ec, q.nk, q.nv, q.nc, d->omega[iw], w, st));
-            }
-            if (d->precision == BGW_FP64) {
-                const int ns = herk_f64_splits(K, q.ng);
-                double2 *part = (double2 *)rest;
-                {
-                    Timed tm(h, BGW_KERNEL_HERK, st);
-                    BGW_TRY(launch_herk_f64((const double2 *)q.M, K, q.ng, w, ns, part, st));
-                }
-                Timed tm(h, BGW_KERNEL_FINALIZE, st);
-                BGW_TRY(launch_chi_finalize(part, ns, q.ng, q.prefactor, chi, d->accumulate, st));
-            } else {
-                const SplitLayout L = split_layout(K, q.ng, rest);
-                // The slices of the unweighted side do not depend on omega: with a
-                // single super-chunk they are made once per q.
-                const bool resident_b = L.sc_pairs >= K;
-                int nslots = 0;  // slots initialised by the first (largest) super-chunk
-                for (long long t0 = 0; t0 < K; t0 += L.sc_pairs) {
-                    const long long kn = std::min<long long>(L.sc_pairs, K - t0);
-                    const int nch = (int)((kn + 127) / 128);
-                    {
-                        Timed tm(h, BGW_KERNEL_SPLIT_SLICE, st);
-                        BGW_TRY(launch_split_slices(L, (const double2 *)q.M, K, q.ng, w, t0, nch,
-                                                    !(resident_b && iw > 0), st));
-                    }
-                    Timed tm(h, BGW_KERNEL_SPLIT_HERK, st);
-                    int used = 0;
-                    BGW_TRY(launch_split_gemm(L, q.ng, nch, nslots, &used, st));
-                    if (!nslots) nslots = used;
-                }
-                {
-                    Timed tm(h, BGW_KERNEL_FINALIZE, st);
-                    BGW_TRY(launch_chi_finalize_skip(L.part, nslots, q.ng, q.prefactor, chi, d->accumulate, q.head,
-                                                     st));
-                }
-                if (q.head >= 0) {
-                    Timed tm(h, BGW_KERNEL_HEADWING, st);
-                    BGW_TRY(launch_split_headwing(L, (const double2 *)q.M, K, q.ng, q.head, w, q.prefactor, chi,
-                                                  d->accumulate, st));
-                }
-            }
-        }
-    }
-    return BGW_OK;
-}
 
 extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi, double *epsinv,
                            int *info, void *stream) {

@@ -1,6 +1,7 @@
 // The chi sum (epsilon section, static chi equation and its compact matrix
 // form): chi(omega) = pf * M^H diag(w(omega)) M over the composite pair index
-// t = (k*nv + v)*nc + c, on FP64 MFMA.
+// t = (k*nv + v)*nc + c, on FP64 MFMA, for a whole batch of (q, omega)
+// problems in one persistent launch.
 //
 // Complex arithmetic uses a real embedding along the contraction index: with
 // M = A + iB and X = [A; B] interleaved per pair (k = 2t + part, which is the
@@ -9,6 +10,8 @@
 // Only tiles on or above the diagonal are computed; the finalize kernel
 // reduces the K-splits in a fixed order (bitwise reproducible), applies the
 // prefactor and mirrors the lower triangle as the conjugate transpose.
+#include <algorithm>
+
 #include "common.h"
 
 namespace bgw {
@@ -16,63 +19,53 @@ namespace bgw {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // w[t] = Delta_t / (Delta_t^2 + omega^2), Delta_t = (E_v,k+q - E_c,k) / Ha  (omega in Ha)
-__global__ void k_weights(const double *__restrict__ ev, const double *__restrict__ ec, int nk, int nv, int nc,
-                          double omega_ha, double *__restrict__ w) {
-    const long long K = (long long)nk * nv * nc;
+// grid.y: problem; every block strides over that problem's pairs.
+__global__ void k_weights(const WProb *__restrict__ probs) {
+    const WProb P = probs[blockIdx.y];
+    const long long K = (long long)P.nk * P.nv * P.nc;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < K;
          t += (long long)gridDim.x * blockDim.x) {
-        const long long c = t % nc, kv = t / nc;
-        const long long k = kv / nv;
-        const double d = (ev[kv] - ec[k * nc + c]) / kHartreeEv;
-        w[t] = d / (d * d + omega_ha * omega_ha);
+        const long long c = t % P.nc, kv = t / P.nc;
+        const long long k = kv / P.nv;
+        const double d = (P.ev[kv] - P.ec[k * P.nc + c]) / kHartreeEv;
+        P.w[t] = d / (d * d + P.omega_ha * P.omega_ha);
     }
 }
 
 namespace {
-constexpr int TM = 64;       // tile rows (G)
-constexpr int TN = 64;       // tile cols (G')
 constexpr int KC = 16;       // complex pairs per LDS stage
 constexpr int KR = 2 * KC;   // real contraction rows per stage
-constexpr int LDA = TM + 16; // padded LDS row: 640 B = 128 B mod 256 B, so the two half-waves of a
-                             // 64-bit MFMA operand read hit disjoint bank halves
-}  // namespace
+constexpr int LDA = 64 + 16; // padded LDS row (doubles): the two half-waves of a 64-bit MFMA operand
+                             // read hit disjoint bank halves
 
-// grid.x: upper-triangle tiles (ti <= tj) of an nt x nt tile grid, grid.y: K splits.
-// out: [split][ng][ng] partial sums (no prefactor).
-__global__ __launch_bounds__(256) void k_herk_f64(const double2 *__restrict__ M, long long K, int ng, int nt,
-                                                  const double *__restrict__ w, long long kper,
-                                                  double2 *__restrict__ out) {
-    __shared__ double As[KR][LDA];
-    __shared__ double Bs[KR][LDA];
-
-    int u = blockIdx.x, ti = 0;
-    while (u >= nt - ti) {
-        u -= nt - ti;
-        ++ti;
-    }
-    const int tj = ti + u;
-    const int G0 = ti * TM, H0 = tj * TN;
-    const long long k0 = blockIdx.y * kper;
-    const long long k1 = min(K, k0 + kper);
-
+// One T x T output tile over pairs [k0, k1): 4 waves in a 2 x 2 layout, each
+// owning a (T/2) x (T/2) block of 16 x 16 MFMA tiles.  Raw sums (no prefactor)
+// are stored to o (tile rows/cols beyond ng are dropped).
+template <int T>
+__device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng, const double *__restrict__ w,
+                                          int G0, int H0, long long k0, long long k1, double2 *__restrict__ o,
+                                          double (*As)[LDA], double (*Bs)[LDA]) {
+    constexpr int NB = T / 32;    // MFMA tiles per wave side
+    constexpr int WT = T / 2;     // wave block edge
+    constexpr int LR = 256 / T;   // loader rows per sweep
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
 
-    double4_t cre[2][2], cim[2][2];
+    double4_t cre[NB][NB], cim[NB][NB];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < NB; ++b) {
             cre[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
             cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
         }
 
-    const int lcol = tid & 63, lrow = tid >> 6;  // loader: 4 rows x 64 cols per sweep
+    const int lcol = tid % T, lrow = tid / T;
     for (long long kk = k0; kk < k1; kk += KC) {
 #pragma unroll
-        for (int s = 0; s < KC / 4; ++s) {
-            const int r = lrow + 4 * s;
+        for (int s = 0; s < KC / LR; ++s) {
+            const int r = lrow + LR * s;
             const long long t = kk + r;
             double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
             double wt = 0.0;
@@ -90,19 +83,19 @@ __global__ __launch_bounds__(256) void k_herk_f64(const double2 *__restrict__ M,
 #pragma unroll
         for (int s = 0; s < KR / 4; ++s) {
             const int kr = 4 * s + lk;
-            double av[2], bre[2], bim[2];
+            double av[NB], bre[NB], bim[NB];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[kr][wr * 32 + 16 * a + li];
+            for (int a = 0; a < NB; ++a) av[a] = As[kr][wr * WT + 16 * a + li];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                const int col = wc * 32 + 16 * b + li;
+            for (int b = 0; b < NB; ++b) {
+                const int col = wc * WT + 16 * b + li;
                 bre[b] = Bs[kr][col];
                 bim[b] = (kr & 1) ? -Bs[kr - 1][col] : Bs[kr + 1][col];
             }
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < NB; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
+                for (int b = 0; b < NB; ++b) {
                     cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
                     cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
                 }
@@ -110,83 +103,126 @@ __global__ __launch_bounds__(256) void k_herk_f64(const double2 *__restrict__ M,
         __syncthreads();
     }
     // D layout of v_mfma_f64_16x16x4: lane l, register r -> row 4r + l/16, col l%16
-    double2 *o = out + (size_t)blockIdx.y * ng * ng;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int G = G0 + wr * 32 + 16 * a + 4 * r + lk;
-                const int H = H0 + wc * 32 + 16 * b + li;
+                const int G = G0 + wr * WT + 16 * a + 4 * r + lk;
+                const int H = H0 + wc * WT + 16 * b + li;
                 if (G < ng && H < ng) o[(size_t)G * ng + H] = make_double2(cre[a][b][r], cim[a][b][r]);
             }
 }
+}  // namespace
+
+// Persistent batched rank-K update for one output-tile size T.  Work item i
+// of problem p (items p.item0 .. p.item0 + tiles*ns) is K split s = i % ns of
+// upper-triangle tile i / ns; blocks stride over the items [i0, i1) of the
+// whole batch, so uneven problems (many q with different ng, many omega)
+// share one launch per tile size.
+template <int T>
+__global__ __launch_bounds__(256) void k_herk_f64(const HerkProb *__restrict__ probs, int nprob, long long i0,
+                                                  long long i1) {
+    __shared__ double As[KR][LDA];
+    __shared__ double Bs[KR][LDA];
+    for (long long item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
+        int lo = 0, hi = nprob - 1;  // last problem with item0 <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (probs[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const HerkProb &P = probs[lo];
+        const long long local = item - P.item0;
+        const int split = (int)(local % P.ns);
+        int u = (int)(local / P.ns), ti = 0;
+        const int nt = P.nt;
+        while (u >= nt - ti) {
+            u -= nt - ti;
+            ++ti;
+        }
+        const int tj = ti + u;
+        const long long k0 = split * P.kper;
+        const long long k1 = min(P.K, k0 + P.kper);
+        herk_tile<T>(P.M, P.ng, P.w, ti * T, tj * T, k0, k1, P.out + (size_t)split * P.ng * P.ng, As, Bs);
+    }
+}
 
 // chi[G][H] (+)= pf * sum_s part[s][G][H] for G <= H, conjugate mirror below the
-// diagonal, diagonal made exactly real.  The split sum runs in fixed order.
-// Row and column `skip` (>= 0) are left untouched (written by the FP64 head kernel).
-__global__ void k_chi_finalize(const double2 *__restrict__ part, int nsplit, int ng, double pf,
-                               double2 *__restrict__ chi, int accumulate, int skip) {
+// diagonal, diagonal made exactly real; the split sum runs in fixed order.
+// In place (ns == 1): chi's upper triangle holds the raw sums and each
+// thread reads (G, H), G <= H, and writes (G, H) and (H, G).  Row and column
+// `skip` (>= 0) are left untouched (written by the FP64 head kernel).
+// grid.y: problem.
+__global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
+    const FinProb P = probs[blockIdx.y];
+    const int ng = P.ng;
     const size_t total = (size_t)ng * ng;
-    const size_t pstride = total;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
         const int G = (int)(e / ng), H = (int)(e % ng);
-        if (G == skip || H == skip) continue;
+        if (G == P.skip || H == P.skip) continue;
+        if (P.inplace) {
+            if (G > H) continue;
+            const double2 s = P.chi[e];
+            double2 val = make_double2(P.pf * s.x, P.pf * s.y);
+            if (G == H) {
+                val.y = 0.0;
+                P.chi[e] = val;
+            } else {
+                P.chi[e] = val;
+                P.chi[(size_t)H * ng + G] = make_double2(val.x, -val.y);
+            }
+            continue;
+        }
         const bool up = G <= H;
         const size_t src = up ? e : (size_t)H * ng + G;
         double2 s = make_double2(0.0, 0.0);
-        for (int p = 0; p < nsplit; ++p) s = cadd(s, part[p * pstride + src]);
-        double2 val = make_double2(pf * s.x, up ? pf * s.y : -pf * s.y);
+        for (int p = 0; p < P.ns; ++p) s = cadd(s, P.part[p * total + src]);
+        double2 val = make_double2(P.pf * s.x, up ? P.pf * s.y : -P.pf * s.y);
         if (G == H) val.y = 0.0;
-        if (accumulate) val = cadd(chi[e], val);
-        chi[e] = val;
+        if (P.accumulate) val = cadd(P.chi[e], val);
+        P.chi[e] = val;
     }
 }
 
 // ---------------------------------------------------------------- launchers
 
-int launch_weights(const double *ev, const double *ec, int nk, int nv, int nc, double omega_ev, double *w,
-                   hipStream_t st) {
-    const long long K = (long long)nk * nv * nc;
-    const int blocks = (int)std::min<long long>((K + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_weights, dim3(blocks), dim3(256), 0, st, ev, ec, nk, nv, nc, omega_ev / kHartreeEv, w);
+int launch_weights_batch(const WProb *probs, int nprob, long long maxK, hipStream_t st) {
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((maxK + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_weights, dim3(blocks, nprob), dim3(256), 0, st, probs);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
 
-int herk_f64_splits(long long K, int ng) {
-    const int nt = (ng + TM - 1) / TM;
-    const long long tiles = (long long)nt * (nt + 1) / 2;
-    long long want = (2048 + tiles - 1) / tiles;
-    const long long maxs = std::max<long long>(1, K / (8 * KC));
-    want = std::min(want, maxs);
-    return (int)std::max<long long>(1, std::min<long long>(want, 64));
+int herk_blocks_per_cu() {
+    static int n = 0;
+    if (!n) {
+        int a = 0, b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_herk_f64<64>, 256, 0) != hipSuccess || a < 1) a = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_herk_f64<32>, 256, 0) != hipSuccess || b < 1) b = 1;
+        n = std::min(a, b);
+    }
+    return n;
 }
 
-int launch_herk_f64(const double2 *M, long long K, int ng, const double *w, int nsplit, double2 *part,
-                    hipStream_t st) {
-    const int nt = (ng + TM - 1) / TM;
-    const long long tiles = (long long)nt * (nt + 1) / 2;
-    long long kper = (K + nsplit - 1) / nsplit;
-    kper = (kper + KC - 1) / KC * KC;
-    hipLaunchKernelGGL(k_herk_f64, dim3((unsigned)tiles, nsplit), dim3(256), 0, st, M, K, ng, nt, w, kper, part);
+// Items [i0, i1) all have output tile `tile`.
+int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long i1, int tile, int grid,
+                      hipStream_t st) {
+    if (i1 <= i0) return BGW_OK;
+    const long long g = std::max<long long>(1, std::min<long long>(i1 - i0, grid));
+    if (tile == 64) hipLaunchKernelGGL(k_herk_f64<64>, dim3((unsigned)g), dim3(256), 0, st, probs, nprob, i0, i1);
+    else hipLaunchKernelGGL(k_herk_f64<32>, dim3((unsigned)g), dim3(256), 0, st, probs, nprob, i0, i1);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
 
-int launch_chi_finalize_skip(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
-                             int skip, hipStream_t st) {
-    const size_t total = (size_t)ng * ng;
-    const int blocks = (int)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_chi_finalize, dim3(blocks), dim3(256), 0, st, part, nsplit, ng, pf, chi, accumulate, skip);
+int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_t st) {
+    const size_t total = (size_t)maxng * maxng;
+    const int blocks = (int)std::max<size_t>(1, std::min<size_t>((total + 255) / 256, 16384 / std::max(1, nprob) + 1));
+    hipLaunchKernelGGL(k_chi_finalize, dim3(blocks, nprob), dim3(256), 0, st, probs);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
-}
-
-int launch_chi_finalize(const double2 *part, int nsplit, int ng, double pf, double2 *chi, int accumulate,
-                        hipStream_t st) {
-    return launch_chi_finalize_skip(part, nsplit, ng, pf, chi, accumulate, -1, st);
 }
 
 }  // namespace bgw

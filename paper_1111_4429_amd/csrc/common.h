@@ -90,4 +90,39 @@ struct SplitLayout {
     double2 *hw;             // FP64 head-row partials
 };
 
+// ---------------------------------------------------------------- batched chi sum
+// One (q, omega) problem of a batched chi0 call.  Plain data: the tables are
+// copied to device memory and read by the persistent kernels.
+struct HerkProb {
+    const double2 *M;  // [K][ng]
+    const double *w;   // [K] weights of this omega
+    double2 *out;      // [ns][ng][ng] raw upper-tile sums (or chi itself, ns == 1, in place)
+    long long K;
+    long long kper;    // pairs per work item (K split into ns ranges)
+    long long item0;   // first work item of this problem in the batch
+    int ng;
+    int tile;          // output tile edge: 64 or 32
+    int nt;            // tiles per side
+    int ns;            // K splits
+};
+
+struct FinProb {
+    const double2 *part;  // [ns][ng][ng] raw sums (unused in place)
+    double2 *chi;         // [ng][ng]
+    double pf;
+    int ns, ng;
+    int accumulate;
+    int skip;      // row/column left untouched (FP64 head row written separately), -1 for none
+    int inplace;   // raw upper-triangle sums already sit in chi (ns == 1, no accumulation)
+    int pad;
+};
+
+struct WProb {
+    const double *ev;  // [nk][nv] eV
+    const double *ec;  // [nk][nc] eV
+    double *w;         // [K]
+    double omega_ha;
+    int nk, nv, nc, pad;
+};
+
 }  // namespace bgw

@@ -1,0 +1,116 @@
+// Host-side state of a library handle and the helpers the entry points share
+// (error reporting, workspace, per-kernel timing, the kernels' launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace bgw {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct FFTPlan {
+    int box[3];  // transform box actually used (see transform_box)
+    AxisPlan ax[3];
+    SphereMaps sm;
+    std::vector<std::unique_ptr<DevBuf>> bufs;
+};
+
+struct ChiState;                 // chi0 batching: tables, tuned configurations, captured graphs
+void chi_state_free(ChiState *);
+
+}  // namespace bgw
+
+struct bgw_handle_s {
+    int device = 0;
+    bgw::DevBuf ws;
+    std::map<std::string, std::unique_ptr<bgw::FFTPlan>> plans;
+    bgw::ChiState *chi = nullptr;
+    bool capturing = false;  // a chi0 call is being captured into a HIP graph
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double total_ms[BGW_KERNEL_COUNT] = {};
+    long long launches[BGW_KERNEL_COUNT] = {};
+    ~bgw_handle_s() {
+        bgw::chi_state_free(chi);
+        for (auto &p : pending) {
+            pool.push_back(p.second.first);
+            pool.push_back(p.second.second);
+        }
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+namespace bgw {
+
+constexpr int kMaxNg = 8192;
+
+int fail(int code, const std::string &msg);
+bool is_2a3b(int n);
+int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st);
+int set_device(bgw_handle_t h);
+
+inline hipEvent_t take_event(bgw_handle_t h) {
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records a start event on construction and an end event on destruction
+// (nothing while a graph is being captured).
+struct Timed {
+    bgw_handle_t h;
+    int id;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(bgw_handle_t h_, int id_, hipStream_t st_) : h(h_), id(id_), st(st_) {
+        if (h->timing && !h->capturing && (a = take_event(h)) != nullptr) (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a) return;
+        hipEvent_t b = take_event(h);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        h->pending.push_back({id, {a, b}});
+    }
+};
+
+// ---- chi-sum launchers (chi.hip)
+int launch_weights_batch(const WProb *probs, int nprob, long long maxK, hipStream_t);
+int herk_blocks_per_cu();
+int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long i1, int tile, int grid,
+                      hipStream_t);
+int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_t);
+
+// ---- split-precision launchers (split.hip)
+int split_workspace_bytes(long long K, int ng, int nsplit_override, size_t *bytes);
+SplitLayout split_layout(long long K, int ng, int nsplit_override, void *ws);
+int launch_split_slices(const SplitLayout &, const double2 *M, long long K, int ng, const double *w, long long t0,
+                        int nch, bool with_b, hipStream_t);
+int launch_split_gemm(const SplitLayout &, int ng, int nch, int add, int *used, hipStream_t);
+int launch_split_headwing(const SplitLayout &, const double2 *M, long long K, int ng, int head, const double *w,
+                          double pf, double2 *chi, int accumulate, hipStream_t);
+
+int device_cus();
+
+}  // namespace bgw

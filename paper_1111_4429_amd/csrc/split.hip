@@ -22,6 +22,7 @@
 //
 // The head row/column (G = 0) is recomputed in FP64 from M (k_headwing)
 // because v(q+G) ~ 1/q^2 amplifies it in epsilon.
+#include <algorithm>
 #include <cstdlib>
 
 #include "common.h"
@@ -423,15 +424,6 @@ __global__ void k_headwing_write(const double2 *__restrict__ hw, int nsplit, int
 
 // ---------------------------------------------------------------- host side
 
-namespace {
-struct SplitPlan {
-    int gpad, nt;
-    long long tiles;
-    long long sc_pairs;  // pairs per super-chunk (multiple of 128)
-    int nsplit;
-    size_t slice_bytes;  // one side, one super-chunk
-};
-
 int device_cus() {
     static int cus = 0;
     if (!cus) {
@@ -444,6 +436,15 @@ int device_cus() {
     }
     return cus;
 }
+
+namespace {
+struct SplitPlan {
+    int gpad, nt;
+    long long tiles;
+    long long sc_pairs;  // pairs per super-chunk (multiple of 128)
+    int nsplit;
+    size_t slice_bytes;  // one side, one super-chunk
+};
 
 // Splits of the chunk range: a multiple of the XCD count (8) when there are
 // enough chunks, chosen so that tiles * nsplit fills whole waves of one block
@@ -469,7 +470,7 @@ int choose_nsplit(long long tiles, long long nch) {
     return best;
 }
 
-SplitPlan make_plan(long long K, int ng) {
+SplitPlan make_plan(long long K, int ng, int nsplit_override) {
     SplitPlan p;
     p.gpad = (ng + TT - 1) / TT * TT;
     p.nt = p.gpad / TT;
@@ -482,7 +483,7 @@ SplitPlan make_plan(long long K, int ng) {
     long long nch = std::max<long long>(1, std::min<long long>(nch_total, cap / per_chunk));
     p.sc_pairs = nch * SKP;
     p.slice_bytes = per_chunk * nch;
-    p.nsplit = choose_nsplit(p.tiles, nch);
+    p.nsplit = nsplit_override > 0 ? (int)std::min<long long>(nsplit_override, nch) : choose_nsplit(p.tiles, nch);
     return p;
 }
 
@@ -491,8 +492,8 @@ constexpr int kHeadSplits = 64;
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
 }  // namespace
 
-int split_workspace_bytes(long long K, int ng, size_t *bytes) {
-    const SplitPlan p = make_plan(K, ng);
+int split_workspace_bytes(long long K, int ng, int nsplit_override, size_t *bytes) {
+    const SplitPlan p = make_plan(K, ng, nsplit_override);
     const long long nch = p.sc_pairs / SKP;
     size_t b = 0;
     b += 2 * al(p.slice_bytes);                                     // SA, SB
@@ -504,8 +505,8 @@ int split_workspace_bytes(long long K, int ng, size_t *bytes) {
 }
 
 // Phase launchers used by the API (each phase is timed separately there).
-SplitLayout split_layout(long long K, int ng, void *ws) {
-    const SplitPlan p = make_plan(K, ng);
+SplitLayout split_layout(long long K, int ng, int nsplit_override, void *ws) {
+    const SplitPlan p = make_plan(K, ng, nsplit_override);
     SplitLayout L;
     L.gpad = p.gpad;
     L.nt = p.nt;
