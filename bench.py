@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the chi0 / eps^-1 hot path on one MI355X.
 
-One step = one pass of the whole path over one q of the silicon-like bulk
-workload (48^3 grid, Ng = 1500, Nv = 4, Nc = 400, Nk = 64, static, FP64):
-pair densities by FFT -> energy weights + chi-sum -> epsilon and its
-inverse.  Inputs are generated once (seeded, synthetic) and are resident in
-HBM before the timed region; W untimed warm-up steps, then exactly K timed
-steps bracketed by torch.cuda.synchronize().
+One step = one pass of the whole path over the workload's q points: pair
+densities by FFT for every q -> energy weights + chi-sum for all q and all
+frequencies in one batched call -> epsilon and its inverse per q.  The
+default workload is the silicon-like bulk one (48^3 grid, Ng = 1500, Nv = 4,
+Nc = 400, Nk = 64, static, FP64); the other workloads (supercell-96,
+imag-freq-64, uneven-q-48 with a --q-subset) run in their own precision.
+Inputs are generated once (seeded, synthetic) and are resident in HBM before
+the timed region; W untimed warm-up steps, then exactly K timed steps
+bracketed by torch.cuda.synchronize().
 
 Prints ONE JSON line.  `value` is the chi-sum algorithmic rate of the whole
-step: 4 Ng^2 K Nw flops / step time (TFLOP/s, FP64-equivalent).  Per-kernel
-times come from HIP events the library records on the launch stream during
-the timed steps; the roofline entry is for the kernel that dominates the
-step.  `cpu_baseline` times the oracle on a bounded sample of the same
-workload and extrapolates linearly in pairs.
+step: sum over q of 4 Ng^2 K Nw flops / step time (TFLOP/s, FP64-equivalent).
+Per-kernel times come from HIP events the library records on the launch
+stream during the timed steps; the roofline entry is for the kernel that
+dominates the step.  `cpu_baseline` times the oracle on a bounded sample of
+the same workload and extrapolates linearly in pairs (and in Ng^3 for the
+inversion when Ng is large).
 """
 
 from __future__ import annotations
@@ -46,6 +50,11 @@ def parse():
     ap.add_argument("--split-reps", type=int, default=3)
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-full-grid", action="store_true")
+    ap.add_argument("--q-subset", default="spread4",
+                    help="uneven-q workloads: comma-separated q indices, or spreadN (N q spanning the Ng range)")
+    ap.add_argument("--precision", choices=["fp64", "split"], default=None,
+                    help="chi-sum precision of the step (default: the workload's)")
+    ap.add_argument("--graph", action="store_true", help="chi0 through HIP-graph replay")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC byte-counter calibration)")
     return ap.parse_args()
@@ -72,19 +81,23 @@ def load_traffic(kernel: str, src_files):
 
 
 def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
+    """The oracle on a bounded sample: M by convolution for a sample of pairs
+    of the first q, chi of those pairs over all Ng x Ng entries and all
+    frequencies, one inversion; extrapolated linearly in pairs and q (and in
+    Ng^3 for inversions of Ng > 2000, timed on a 1500 x 1500 block)."""
     import oracle
 
     q = s["qs"][0]
     K = s["nk"] * s["nv"] * s["nc"]
     ng = q["ng"]
+    nw = len(s["omega"])
+    # keep the oracle's chi sample near 2e11 flops
+    pairs_sample = int(max(16, min(pairs_sample, K, 2e11 / (8.0 * ng * ng * nw))))
     rng = np.random.default_rng(123)
     pairs = np.sort(rng.choice(K, size=pairs_sample, replace=False))
     t0 = time.perf_counter()
     Ms = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
     t_m = time.perf_counter() - t0
-    kk = pairs // (s["nv"] * s["nc"])
-    vv = (pairs // s["nc"]) % s["nv"]
-    cc = pairs % s["nc"]
     w_all = oracle.weights(q["ev"], s["ec"], s["omega"])
     w = w_all[:, pairs]
     pf = 1.0 / (s["nk"] * s["vol"])
@@ -92,20 +105,25 @@ def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
     chi_s = oracle.chi(Ms, w, pf)
     t_c = time.perf_counter() - t0
     v = oracle.vcoul(s["bmat"], q["q"], q["ge"])
+    ni = min(ng, 1500) if ng > 2000 else ng
     t0 = time.perf_counter()
-    oracle.eps_inv(v, chi_s)
-    t_i = time.perf_counter() - t0
+    oracle.eps_inv(v[:ni], np.ascontiguousarray(chi_s[:1, :ni, :ni]))
+    t_i = (time.perf_counter() - t0) * (ng / ni) ** 3 * nw
     scale = K / pairs_sample
-    t_step = (t_m + t_c) * scale + t_i
-    del kk, vv, cc
+    nq = len(s["qs"])
+    sum_ng2 = sum(float(x["ng"]) ** 2 for x in s["qs"])
+    sum_ng3 = sum(float(x["ng"]) ** 3 for x in s["qs"])
+    t_step = t_m * scale * nq + t_c * scale * sum_ng2 / (ng * ng) + t_i * sum_ng3 / ng ** 3
     return {
         "value": chi_flops_step / t_step / 1e12,
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"oracle on {pairs_sample} of {K} pairs: M by convolution ({t_m:.2f} s) and chi over all "
-                   f"{ng}x{ng} entries ({t_c:.2f} s), extrapolated x{scale:.0f}; plus one full {ng}x{ng} "
-                   f"inversion ({t_i:.2f} s); extrapolated step {t_step:.1f} s"),
+        "sample": (f"oracle on {pairs_sample} of {K} pairs of q0: M by convolution ({t_m:.2f} s) and chi over all "
+                   f"{ng}x{ng} entries and {nw} frequencies ({t_c:.2f} s), extrapolated x{scale:.0f} and over "
+                   f"{nq} q by Ng^2; inversions {t_i:.2f} s for q0"
+                   + (f" (timed at {ni}x{ni}, scaled by Ng^3)" if ni != ng else "")
+                   + f"; extrapolated step {t_step:.1f} s"),
         "cpu": _cpu_model(),
     }
 
@@ -136,14 +154,14 @@ def full_grid_pairs(torch, bgw, n, s, q, cv, cc, M, fft_bytes_nominal, reps=2):
             "rel_diff_vs_minimal_box": diff}
 
 
-def split_vs_fp64(torch, h, bgw, qd, omega, chi64, ng, K, reps):
-    """Split-BF16 vs FP64 chi-sum on the same resident M (whole chi0 calls,
-    HIP events on the launch stream), with the relative Frobenius error of
-    the split result against the FP64 one."""
-    chisp = torch.empty_like(chi64)
+def split_vs_fp64(torch, h, bgw, ents, omega, chis64, reps):
+    """Split-BF16 vs FP64 chi-sum over the same resident M (whole batched chi0
+    calls, HIP events on the launch stream), with the relative Frobenius error
+    of every split (q, omega) result against the FP64 one (worst reported)."""
+    chissp = [torch.empty_like(c) for c in chis64]
     res = {}
-    for name, prec, buf in (("fp64", bgw.FP64, chi64), ("split", bgw.SPLIT_BF16, chisp)):
-        h.chi0([qd], omega, precision=prec, chis=[buf])  # warm-up
+    for name, prec, bufs in (("fp64", bgw.FP64, chis64), ("split", bgw.SPLIT_BF16, chissp)):
+        h.chi0(ents, omega, precision=prec, chis=bufs)  # warm-up
         torch.cuda.synchronize()
         h.reset_timing()
         h.set_timing(True)
@@ -151,19 +169,27 @@ def split_vs_fp64(torch, h, bgw, qd, omega, chi64, ng, K, reps):
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            h.chi0([qd], omega, precision=prec, chis=[buf])
+            h.chi0(ents, omega, precision=prec, chis=bufs)
         e1.record()
         torch.cuda.synchronize()
         h.set_timing(False)
         res[name] = (e0.elapsed_time(e1) / reps, h.timing())
-    err = float(torch.linalg.vector_norm(chisp - chi64) / torch.linalg.vector_norm(chi64))
-    head_err = float(torch.linalg.vector_norm(chisp[:, 0] - chi64[:, 0]) / torch.linalg.vector_norm(chi64[:, 0]))
-    nw = chi64.shape[0]
-    flops = 4.0 * ng * ng * K * nw
-    gpad = (ng + 63) // 64 * 64
-    tiles = (gpad // 64) * (gpad // 64 + 1) // 2
-    nchunk = (K + 127) // 128
-    issued = tiles * 64.0 * 64.0 * nchunk * 256 * 2 * 20 * nw
+    err = head_err = 0.0
+    for c64, csp in zip(chis64, chissp):
+        for iw in range(c64.shape[0]):
+            a, b = csp[iw], c64[iw]
+            err = max(err, float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
+            head_err = max(head_err, float(torch.linalg.vector_norm(a[0] - b[0]) / torch.linalg.vector_norm(b[0])))
+    nw = len(omega)
+    flops = issued = 0.0
+    for e in ents:
+        ng = int(e["M"].shape[1])
+        K = int(e["M"].shape[0])
+        flops += 4.0 * ng * ng * K * nw
+        gpad = (ng + 63) // 64 * 64
+        tiles = (gpad // 64) * (gpad // 64 + 1) // 2
+        nchunk = (K + 127) // 128
+        issued += tiles * 64.0 * 64.0 * nchunk * 256 * 2 * 20 * nw
     tsp = res["split"][1]
     herk_ms = tsp["split_herk"][0] / reps
     t64 = res["fp64"][0]
@@ -180,10 +206,26 @@ def split_vs_fp64(torch, h, bgw, qd, omega, chi64, ng, K, reps):
         "split_herk_ms": herk_ms,
         "split_headwing_ms": tsp["headwing"][0] / reps,
         "split_finalize_ms": tsp["finalize"][0] / reps,
+        "fp64_herk_ms": res["fp64"][1]["herk"][0] / reps,
         "split_chi_TFLOPs_fp64_equiv": flops / (tspl * 1e-3) / 1e12,
+        "fp64_chi_TFLOPs": flops / (t64 * 1e-3) / 1e12,
         "split_herk_bf16_issued_TFLOPs": issued / (herk_ms * 1e-3) / 1e12,
         "split_herk_frac_bf16_peak": issued / (herk_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
     }
+
+
+def graph_vs_eager(torch, h, bgw, ents, omega, chis, precision, reps=3):
+    """The same chi0 call launched directly and replayed from its HIP graph."""
+    out = {}
+    for name, g in (("eager_ms", False), ("graph_ms", True)):
+        h.chi0(ents, omega, precision=precision, chis=chis, use_graph=g)  # warm-up / capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            h.chi0(ents, omega, precision=precision, chis=chis, use_graph=g)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3 / reps
+    return out
 
 
 def _cpu_model():
@@ -219,31 +261,47 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
         return
     wl = synth.WORKLOADS[args.workload]
-    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
-    s = synth.make_system(wl)
-    q = s["qs"][0]
-    n, ng, nk, nv, nc = s["n"], q["ng"], s["nk"], s["nv"], s["nc"]
+    q_subset = None
+    if wl.nq > 1:
+        if args.q_subset.startswith("spread"):
+            cnt = int(args.q_subset[len("spread"):] or 4)
+            sizes = synth.uneven_q_sizes(wl)
+            order = np.argsort(sizes, kind="stable")
+            q_subset = sorted({int(order[round(i * (len(order) - 1) / max(1, cnt - 1))]) for i in range(cnt)})
+        else:
+            q_subset = [int(x) for x in args.q_subset.split(",")]
+    print(f"[bench] generating {wl.name}" + (f" q {q_subset}" if q_subset else ""), file=sys.stderr, flush=True)
+    s = synth.make_system(wl, q_subset=q_subset)
+    prec_name = args.precision or wl.precision
+    precision = bgw.FP64 if prec_name == "fp64" else bgw.SPLIT_BF16
+    n, nk, nv, nc = s["n"], s["nk"], s["nv"], s["nc"]
     K = nk * nv * nc
     N = n ** 3
     nw = len(s["omega"])
     pf = 1.0 / (nk * s["vol"])
+    omega = s["omega"]
 
-    cv = torch.from_numpy(q["cv"]).to(dev)
-    cc = torch.from_numpy(s["cc"]).to(dev)
-    ev = torch.from_numpy(q["ev"]).to(dev)
-    ec = torch.from_numpy(s["ec"]).to(dev)
-    v = torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev)
-    M = torch.empty((K, ng), dtype=torch.complex128, device=dev)
-    chi = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
-    einv = torch.empty_like(chi)
-    info = torch.empty(nw, dtype=torch.int32, device=dev)
     h = bgw.Handle(0)
-    qd = dict(M=M, ev=ev, ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf)
+    cc = torch.from_numpy(s["cc"]).to(dev)
+    ec = torch.from_numpy(s["ec"]).to(dev)
+    Q = []
+    for q in s["qs"]:
+        ng = q["ng"]
+        Q.append(dict(q=q, ng=ng, cv=torch.from_numpy(q["cv"]).to(dev), ev=torch.from_numpy(q["ev"]).to(dev),
+                      v=torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev),
+                      M=torch.empty((K, ng), dtype=torch.complex128, device=dev),
+                      chi=torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev),
+                      einv=torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev),
+                      info=torch.empty(nw, dtype=torch.int32, device=dev)))
+    ents = [dict(M=x["M"], ev=x["ev"], ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf) for x in Q]
+    chis = [x["chi"] for x in Q]
 
     def step():
-        h.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
-        h.chi0([qd], s["omega"], precision=bgw.FP64, chis=[chi])
-        h.eps_inv(v, chi, epsinv=einv, info=info)
+        for x in Q:
+            h.pair_density(n, s["gw"], x["q"]["ge"], x["cv"], cc, M=x["M"])
+        h.chi0(ents, omega, precision=precision, chis=chis, use_graph=args.graph)
+        for x in Q:
+            h.eps_inv(x["v"], x["chi"], epsinv=x["einv"], info=x["info"])
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -260,73 +318,81 @@ def main():
     elapsed = time.perf_counter() - t0
     h.set_timing(False)
     tm = h.timing()
-    assert int(info.cpu().max()) == 0 and int(info.cpu().min()) == 0
+    for x in Q:
+        assert int(x["info"].cpu().max()) == 0 and int(x["info"].cpu().min()) == 0
 
     ms_step = elapsed * 1e3 / args.steps
-    box = bgw.pair_transform_box(n, s["gw"], q["ge"])
-    Nb = box[0] * box[1] * box[2]
-    chi_flops = 4.0 * ng * ng * K * nw
+    q0 = Q[0]["q"]
+    box = bgw.pair_transform_box(n, s["gw"], q0["ge"])
+    boxes = [bgw.pair_transform_box(n, s["gw"], x["q"]["ge"]) for x in Q]
+    ngs = [x["ng"] for x in Q]
+    chi_flops = sum(4.0 * g * g * K * nw for g in ngs)
     # algorithmic bytes of the pair transform on the box actually transformed
-    fft_bytes = K * 16.0 * (Nb + ng)
-    fft_bytes_nominal = K * 16.0 * (N + ng)
-    lu_flops = 8.0 * ng ** 3 * nw
+    fft_bytes = sum(K * 16.0 * (b[0] * b[1] * b[2] + g) for b, g in zip(boxes, ngs))
+    fft_bytes_nominal = sum(K * 16.0 * (N + g) for g in ngs)
+    lu_flops = sum(8.0 * g ** 3 * nw for g in ngs)
 
-    def avg(name):
-        ms, cnt = tm[name]
-        return (ms / cnt if cnt else float("nan")), cnt
-
-    pair_ms, pair_n = avg("pair")
-    herk_ms, herk_n = avg("herk")
     per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
     launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
-    herk_per_step = launches.get("herk", 1)
-    box_bytes = 16.0 * Nb
-    nbox = None
+    pair_t = per_step.get("pair", 0) + per_step.get("pair_x", 0)
+    herk_key = "herk" if precision == bgw.FP64 else "split_herk"
+    chi_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize", "split_slice", "split_herk",
+                                               "headwing"))
     stages = {
-        "pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
+        "pair_density_ms": per_step.get("band", 0) + pair_t,
         "band_ms": per_step.get("band", 0),
         "pair_fft_ms": per_step.get("pair", 0),
         "pair_x_ms": per_step.get("pair_x", 0),
-        "chi_ms": per_step.get("weights", 0) + per_step.get("herk", 0) + per_step.get("finalize", 0),
-        "herk_ms": per_step.get("herk", 0),
+        "chi_ms": chi_ms,
+        "herk_ms": per_step.get(herk_key, 0),
         "eps_inv_ms": per_step.get("eps_build", 0) + per_step.get("invert", 0),
-        "chi_sum_TFLOPs": chi_flops / (per_step["herk"] * 1e-3) / 1e12,
-        "chi_sum_frac_fp64_peak": chi_flops / (per_step["herk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "pair_fft_GBs_algorithmic": fft_bytes / ((per_step.get("pair", 0) + per_step.get("pair_x", 0)) * 1e-3) / 1e9,
-        "pair_fft_nominal_TFLOPs": 5.0 * Nb * np.log2(Nb) * K
-        / ((per_step.get("pair", 0) + per_step.get("pair_x", 0)) * 1e-3) / 1e12,
+        "chi_sum_TFLOPs": chi_flops / (chi_ms * 1e-3) / 1e12,
+        "pair_fft_GBs_algorithmic": fft_bytes / (pair_t * 1e-3) / 1e9,
+        "pair_fft_nominal_TFLOPs": sum(5.0 * b[0] * b[1] * b[2] * np.log2(b[0] * b[1] * b[2]) * K for b in boxes)
+        / (pair_t * 1e-3) / 1e12,
         "eps_inv_TFLOPs": lu_flops / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
     }
+    if precision == bgw.FP64:
+        stages["chi_sum_frac_fp64_peak"] = chi_flops / (per_step["herk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
     kernel_share = {k: per_step[k] / ms_step for k in per_step}
-    # work per launch of each timed kernel group (algorithmic)
-    rey = int(np.abs(q["ge"][:, 1]).max())
-    rez = int(np.abs(q["ge"][:, 2]).max())
-    nbox = (2 * rey + 1) * (2 * rez + 1)
-    t_bytes = K * 16.0 * box[0] * nbox
+    # algorithmic work per step of each timed kernel group
+    t_bytes = 0.0
+    for x, b in zip(Q, boxes):
+        rey = int(np.abs(x["q"]["ge"][:, 1]).max())
+        rez = int(np.abs(x["q"]["ge"][:, 2]).max())
+        t_bytes += K * 16.0 * b[0] * (2 * rey + 1) * (2 * rez + 1)
+    box_bytes = sum(16.0 * b[0] * b[1] * b[2] for b in boxes)
+    split_issued = 0.0
+    for g in ngs:
+        gpad = (g + 63) // 64 * 64
+        split_issued += (gpad // 64) * (gpad // 64 + 1) // 2 * 64.0 * 64.0 * ((K + 127) // 128) * 256 * 2 * 20 * nw
     work = {
-        "pair": ("k_pair_yz (product + z/y FFT)", "hbm", (K * box_bytes + t_bytes), "GB/s"),
-        "pair_x": ("k_pair_x (x transform + sphere gather)", "hbm", (t_bytes + K * 16.0 * ng), "GB/s"),
-        "band": ("k_band_to_real3", "hbm", (nk * (nv + nc)) * box_bytes, "GB/s"),
-        "herk": ("k_herk_f64", "mfma", chi_flops, "TFLOP/s"),
-        "invert": ("Gauss-Jordan inversion (k_gje_*)", "mfma", lu_flops, "TFLOP/s"),
+        "pair": ("k_pair_yz (product + z/y FFT)", "hbm", K * box_bytes + t_bytes, "GB/s", HBM_PEAK_GBS),
+        "pair_x": ("k_pair_x (x transform + sphere gather)", "hbm", t_bytes + K * 16.0 * sum(ngs), "GB/s",
+                   HBM_PEAK_GBS),
+        "band": ("k_band_to_real3", "hbm", (nk * (nv + nc)) * box_bytes, "GB/s", HBM_PEAK_GBS),
+        "herk": ("k_herk_f64", "mfma", chi_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
+        "split_herk": ("k_herk_split (BF16 MFMA issued)", "mfma", split_issued, "TFLOP/s", BF16_PEAK_TFLOPS),
+        "invert": ("Gauss-Jordan inversion (k_gje_*)", "mfma", lu_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
     }
     dominant = max(work, key=lambda k: per_step.get(k, 0))
-    name, bound, per_step_work, unit = work[dominant]
+    name, bound, per_step_work, unit, peak = work[dominant]
     nl = launches.get(dominant, 1)
     avg_ms = per_step[dominant] / nl
     per_launch = per_step_work / nl
-    if unit == "GB/s":
-        ach = per_launch / (avg_ms * 1e-3) / 1e9
-        peak = HBM_PEAK_GBS
-    else:
-        ach = per_launch / (avg_ms * 1e-3) / 1e12
-        peak = FP64_PEAK_TFLOPS
-    fft_src = ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"]
-    tr = load_traffic(dominant, fft_src if dominant in ("pair", "pair_x", "band") else
-                      ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/eps.hip"])
+    ach = per_launch / (avg_ms * 1e-3) / (1e9 if unit == "GB/s" else 1e12)
+    src = {"pair": ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"],
+           "pair_x": ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"],
+           "band": ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"],
+           "herk": ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/common.h"],
+           "split_herk": ["paper_1111_4429_amd/csrc/split.hip", "paper_1111_4429_amd/csrc/common.h"],
+           "invert": ["paper_1111_4429_amd/csrc/eps.hip", "paper_1111_4429_amd/csrc/common.h"]}[dominant]
+    tr = load_traffic(f"{dominant}_{wl.name}", src)
     roof = {"kernel": name, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
             "traffic": None if tr is None else tr["bytes_per_launch"],
             "algorithmic_per_launch": per_launch, "avg_launch_ms": avg_ms, "launches_per_step": nl}
+    if tr is not None:
+        roof["traffic_source"] = tr.get("profile")
 
     out = {
         "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
@@ -339,21 +405,29 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == bgw.FP64 else "bf16-split/f32-acc/f64-recombined",
         "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies)",
-        "config": {"workload": wl.name, "grid": f"{n}^3", "transform_box": "x".join(map(str, box)), "ng": ng,
-                   "ngw": len(s["gw"]), "nv": nv, "nc": nc,
-                   "nk": nk, "npairs": K, "nw": nw, "precision": "fp64", "q": list(map(float, q["q"]))},
+        "config": {"workload": wl.name, "grid": f"{n}^3", "transform_box": "x".join(map(str, box)),
+                   "ng": ngs[0] if len(ngs) == 1 else ngs, "ngw": len(s["gw"]), "nv": nv, "nc": nc, "nk": nk,
+                   "npairs": K, "nw": nw, "nq": len(Q), "precision": prec_name,
+                   "q": [list(map(float, x["q"]["q"])) for x in Q] if len(Q) > 1 else list(map(float, q0["q"])),
+                   "q_index": [int(x["q"]["iq"]) for x in Q] if len(Q) > 1 else 0, "graph": bool(args.graph)},
         "stages": stages,
         "kernel_share": kernel_share,
         "roofline": roof,
         "split": None,
         "cpu_baseline": None,
     }
-    if not args.no_full_grid:
-        out["full_grid_pair_density"] = full_grid_pairs(torch, bgw, n, s, q, cv, cc, M, fft_bytes_nominal)
+    if not args.no_full_grid and len(Q) == 1 and tuple(box) != (n, n, n):
+        x = Q[0]
+        out["full_grid_pair_density"] = full_grid_pairs(torch, bgw, n, s, x["q"], x["cv"], cc, x["M"],
+                                                        fft_bytes_nominal)
     if not args.no_split:
-        out["split"] = split_vs_fp64(torch, h, bgw, qd, s["omega"], chi, ng, K, args.split_reps)
+        print("[bench] split vs fp64", file=sys.stderr, flush=True)
+        out["split"] = split_vs_fp64(torch, h, bgw, ents, omega, [torch.empty_like(c) for c in chis],
+                                     args.split_reps)
+    if (len(Q) > 1 or nw > 1) and chi_ms < 1000.0:
+        out["batch_graph"] = graph_vs_eager(torch, h, bgw, ents, omega, chis, precision, reps=2)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_pairs, chi_flops)

@@ -81,9 +81,12 @@ size_t bgw_workspace_bytes(bgw_handle_t h);
  * This equals the matrix element exactly when no axis aliases, i.e.
  * n_i > 2 max|gw_i| + max|ge_i| for i = 1..3 (else BGW_ERR_ALIAS).
  * Because the result does not depend on the grid once it is alias-free, the
- * transforms run on the smallest alias-free box: b_i = the least 2^a 3^b
- * length >= 2 max|gw_i| + max|ge_i| + 1 (at most n_i); setting the
- * environment variable BGW_FFT_BOX=full makes the library use n itself.
+ * transforms run on a small alias-free box b (each b_i >= 2 max|gw_i| +
+ * max|ge_i| + 1, b_i <= n_i): the least lengths of {16, 24, 32, 48, 64, 96,
+ * 128} (equal along y and z) when they fit in n, which have register-resident
+ * kernels, else the least 2^a 3^b length per axis.  Setting the environment
+ * variable BGW_FFT_BOX=full makes the library use n itself;
+ * bgw_pair_transform_box reports the box.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int n[3];          /* FFT grid; each n_i = 2^a 3^b with 4 <= n_i <= 128 */

@@ -181,7 +181,9 @@ int ensure_ws(bgw_handle_t h, size_t bytes, hipStream_t st) {
 // equation, and the discrete transform reproduces it exactly on any box whose
 // every axis satisfies b_i > 2 max|gw_i| + max|ge_i| (no aliasing of the
 // product's Fourier components onto the dielectric sphere).  The smallest such
-// 2^a 3^b length (at most the caller's n_i) is used; BGW_FFT_BOX=full forces
+// length among those with register-resident kernels (16 .. 128, y and z
+// equal) is used when one fits in the caller's grid, else the smallest
+// 2^a 3^b length per axis (at most the caller's n_i); BGW_FFT_BOX=full forces
 // the caller's grid.
 static void transform_box(const bgw_pair_desc *d, int box[3]) {
     const char *env = std::getenv("BGW_FFT_BOX");
@@ -191,12 +193,28 @@ static void transform_box(const bgw_pair_desc *d, int box[3]) {
         for (int a = 0; a < 3; ++a) mw[a] = std::max(mw[a], std::abs(d->gw[3 * g + a]));
     for (int g = 0; g < d->ng; ++g)
         for (int a = 0; a < 3; ++a) me[a] = std::max(me[a], std::abs(d->ge[3 * g + a]));
+    if (full) {
+        for (int a = 0; a < 3; ++a) box[a] = d->n[a];
+        return;
+    }
+    int need[3];
+    for (int a = 0; a < 3; ++a) need[a] = std::max(4, 2 * mw[a] + me[a] + 1);
+    // lengths with register-resident transform kernels (equal y and z for the two-pass pair transform)
+    static const int kFast[] = {16, 24, 32, 48, 64, 96, 128};
+    auto fast_at_least = [](int lo, int hi) {
+        for (int f : kFast)
+            if (f >= lo && f <= hi) return f;
+        return 0;
+    };
+    const int fx = fast_at_least(need[0], d->n[0]);
+    const int fyz = fast_at_least(std::max(need[1], need[2]), std::min(d->n[1], d->n[2]));
+    if (fx && fyz) {
+        box[0] = fx;
+        box[1] = box[2] = fyz;
+        return;
+    }
     for (int a = 0; a < 3; ++a) {
-        if (full) {
-            box[a] = d->n[a];
-            continue;
-        }
-        int b = std::max(4, 2 * mw[a] + me[a] + 1);
+        int b = need[a];
         while (!is_2a3b(b)) ++b;
         box[a] = std::min(b, d->n[a]);
     }

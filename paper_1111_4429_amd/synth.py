@@ -195,6 +195,23 @@ def make_system(wl: Workload, seed: int = 0, q_subset: Optional[Sequence[int]] =
                 omega=frequencies(wl), cc=cc, ec=ec, qs=qs)
 
 
+def uneven_q_sizes(wl: Workload, seed: int = 0) -> np.ndarray:
+    """Ng_q of every q of an uneven-q workload, as make_system draws them
+    (the earlier draws are replayed in chunks, nothing is kept)."""
+    assert wl.nq > 1 and wl.ng_range is not None
+    rng = np.random.default_rng(seed)
+    ngw = wl.ngw
+    for _ in range(wl.nk * (wl.nv + wl.nc)):   # C, one band at a time
+        rng.standard_normal((1, ngw, 2))
+    for _ in range(wl.nk * wl.nv):             # xi
+        rng.standard_normal((1, ngw, 2))
+    rng.uniform(-10.0, 0.0, size=(wl.nk, wl.nv))
+    rng.uniform(1.0, 20.0, size=(wl.nk, wl.nc))
+    lo, hi = wl.ng_range
+    ngq = rng.integers(lo, hi + 1, size=wl.nq)
+    return np.minimum(ngq, ngw)
+
+
 def small_system(n: int, ngw: int, ng: int, nv: int, nc: int, nk: int = 1, seed: int = 0,
                  q=Q0_CRYSTAL, nw: int = 1, freq: str = "static") -> dict:
     """A system of arbitrary (small) size drawn by the same recipe."""
