@@ -29,6 +29,7 @@ namespace bgw {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kPanelMax = 32;
+constexpr int kGjeMaxR = 32;                // workgroups per matrix (n <= 8192, 256 rows each)
 constexpr int kInfoBarrierTimeout = -1000;  // info value when a grid barrier wait gave up
 
 struct GjeScratch {
@@ -69,23 +70,24 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 }
 
 // grid barrier among the R workgroups of one matrix; `target` = R * (number of
-// barriers passed including this one)
+// barriers passed including this one).  One release (the arrival) and one
+// acquire fence after the wait: the spin itself uses relaxed loads, since an
+// acquire load per iteration would invalidate the XCD's L2 every time.
 __device__ inline void matrix_barrier(unsigned int *bar, unsigned int target, int *info) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
         __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         unsigned long long spins = 0;
-        while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > (1ull << 24)) {  // bounded wait: report and give up
                 atomicExch(info, kInfoBarrierTimeout);
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    // thread 0's acquire invalidated this CU's stale cache lines; the exchanged
-    // values are then read with device-scope atomic loads
+    // the exchanged values are then read with device-scope atomic loads
     __syncthreads();
 }
 
@@ -101,21 +103,36 @@ __device__ inline void st_agent(double2 *p, double2 v) {
     __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Largest |Re|+|Im| over a wavefront, first row on ties; every lane gets the result.
+__device__ inline void wave_argmax(double &v, int &row) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(v, off);
+        const int orow = __shfl_xor(row, off);
+        if (ov > v || (ov == v && orow < row)) {
+            v = ov;
+            row = orow;
+        }
+    }
+}
+
 // A: matrices of a group, [nmat][n][n]; each matrix is factored by R
-// consecutive workgroups, workgroup r owning rows [r*rows, min(n, (r+1)*rows)).
-__global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int n, int k, int nb, int rows, int R,
+// consecutive workgroups, workgroup r owning rows [r*rows, min(n, (r+1)*rows))
+// (rows <= blockDim.x: one row per thread).  NB: panel width known at compile
+// time (0: the runtime nb, for the last, narrower panel).
+template <int NB>
+__global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int n, int k, int nb_rt, int rows, int R,
                                                    int *__restrict__ ipiv, int *__restrict__ info, GjeScratch sc,
                                                    unsigned int bar_done) {
     extern __shared__ double2 lds[];
-    const int ps = nb + 1;                   // padded row stride of the panel in LDS
-    double2 *P = lds;                        // [rows][ps]
+    const int nb = NB ? NB : nb_rt;
+    const int ps = nb + 1;                       // padded row stride of the panel in LDS
+    double2 *P = lds;                            // [rows][ps]
     double2 *prow = P + rows * (kPanelMax + 1);  // scaled pivot row [nb]
-    double2 *prow_raw = prow + kPanelMax;    // pivot row before scaling [nb]
-    double2 *oldrow = prow_raw + kPanelMax;  // row k+j before the swap [nb]
-    __shared__ double red_val[256];
-    __shared__ int red_row[256];
-    __shared__ int red_win[256];
-    __shared__ int s_p, s_win;
+    double2 *oldrow = prow + kPanelMax;          // row k+j before the swap [nb]
+    double2 *cand = oldrow + kPanelMax;          // candidate rows of all workgroups [R][nb]
+    __shared__ double wv[4], cv_s[kGjeMaxR];
+    __shared__ int wrow[4], cr_s[kGjeMaxR];
 
     const int mat = blockIdx.x / R, r = blockIdx.x % R;
     double2 *Am = A + (size_t)mat * n * n;
@@ -127,8 +144,12 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
     double2 *crows = sc.cand_rows + (size_t)mat * 2 * R * nb;
     double2 *rbuf = sc.rowbuf + (size_t)mat * 2 * nb;
     unsigned int *bar = sc.bar + mat;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int gi = row0 + tid;  // this thread's row
+    const bool mine = tid < nloc;
+    double2 *pr = P + tid * ps;
 
-    for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
+    for (int e = tid; e < nloc * nb; e += blockDim.x) {
         const int i = e / nb, c = e % nb;
         P[i * ps + c] = Am[(size_t)(row0 + i) * n + k + c];
     }
@@ -140,116 +161,88 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
         // local pivot candidate among rows >= col
         double best = -1.0;
         int brow = 0x7fffffff;
-        for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-            const int gi = row0 + i;
-            if (gi >= col) {
-                const double a = cabs1(P[i * ps + j]);
-                if (a > best || (a == best && gi < brow)) {
-                    best = a;
-                    brow = gi;
-                }
-            }
+        if (mine && gi >= col) {
+            best = cabs1(pr[j]);
+            brow = gi;
         }
-        red_val[threadIdx.x] = best;
-        red_row[threadIdx.x] = brow;
+        wave_argmax(best, brow);
+        if (lane == 0) {
+            wv[wave] = best;
+            wrow[wave] = brow;
+        }
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) {
-                const double ov = red_val[threadIdx.x + s];
-                const int orow = red_row[threadIdx.x + s];
-                if (ov > red_val[threadIdx.x] || (ov == red_val[threadIdx.x] && orow < red_row[threadIdx.x])) {
-                    red_val[threadIdx.x] = ov;
-                    red_row[threadIdx.x] = orow;
-                }
+        best = wv[0];
+        brow = wrow[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (wv[w] > best || (wv[w] == best && wrow[w] < brow)) {
+                best = wv[w];
+                brow = wrow[w];
             }
-            __syncthreads();
+        // publish the candidate (value, row, row contents) and, from the owner, row col
+        if (tid == 0) {
+            __hip_atomic_store(&cval[slot * R + r], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&crow[slot * R + r], brow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const double lbest = red_val[0];
-        const int lrow = red_row[0];
-        if (threadIdx.x == 0) {
-            __hip_atomic_store(&cval[slot * R + r], lbest, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&crow[slot * R + r], lrow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lbest >= 0.0)
-            for (int c = threadIdx.x; c < nb; c += blockDim.x)
-                st_agent(&crows[((size_t)slot * R + r) * nb + c], P[(lrow - row0) * ps + c]);
-        if (col >= row0 && col < row0 + nloc)
-            for (int c = threadIdx.x; c < nb; c += blockDim.x) st_agent(&rbuf[slot * nb + c], P[(col - row0) * ps + c]);
+        if (tid < nb)
+            st_agent(&crows[((size_t)slot * R + r) * nb + tid],
+                     best >= 0.0 ? P[(brow - row0) * ps + tid] : make_double2(0.0, 0.0));
+        if (col >= row0 && col < row0 + nloc && tid < nb) st_agent(&rbuf[slot * nb + tid], P[(col - row0) * ps + tid]);
 
         matrix_barrier(bar, (bar_done + j + 1) * (unsigned)R, info + mat);
 
-        // global pivot: every thread reads some of the R candidates, then a block reduction
-        {
-            double bv = -1.0;
-            int bp = 0x7fffffff, bw = 0;
-            for (int q = threadIdx.x; q < R; q += blockDim.x) {
-                const double v = __hip_atomic_load(&cval[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int rr = __hip_atomic_load(&crow[slot * R + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (v > bv || (v == bv && rr < bp)) {
-                    bv = v;
-                    bp = rr;
-                    bw = q;
-                }
-            }
-            red_val[threadIdx.x] = bv;
-            red_row[threadIdx.x] = bp;
-            red_win[threadIdx.x] = bw;
-            __syncthreads();
-            for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
-                if (threadIdx.x < s2) {
-                    const double ov = red_val[threadIdx.x + s2];
-                    const int orow = red_row[threadIdx.x + s2];
-                    if (ov > red_val[threadIdx.x] || (ov == red_val[threadIdx.x] && orow < red_row[threadIdx.x])) {
-                        red_val[threadIdx.x] = ov;
-                        red_row[threadIdx.x] = orow;
-                        red_win[threadIdx.x] = red_win[threadIdx.x + s2];
-                    }
-                }
-                __syncthreads();
-            }
-            if (threadIdx.x == 0) {
-                s_p = red_row[0];
-                s_win = red_win[0];
-                if (red_val[0] <= 0.0 && r == 0) atomicCAS(info + mat, 0, col + 1);
-                if (r == 0) ip[col] = red_row[0];
-            }
-            __syncthreads();
+        // every workgroup fetches all candidates (values, rows, row contents) and row col in one round
+        for (int e = tid; e < R * nb; e += blockDim.x) cand[e] = ld_agent(&crows[(size_t)slot * R * nb + e]);
+        if (tid < R) {
+            cv_s[tid] = __hip_atomic_load(&cval[slot * R + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            cr_s[tid] = __hip_atomic_load(&crow[slot * R + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const int p = s_p, win = s_win;
-        for (int c = threadIdx.x; c < nb; c += blockDim.x) {
-            prow_raw[c] = ld_agent(&crows[((size_t)slot * R + win) * nb + c]);
-            oldrow[c] = ld_agent(&rbuf[slot * nb + c]);
-        }
+        if (tid >= 64 && tid < 64 + nb) oldrow[tid - 64] = ld_agent(&rbuf[slot * nb + tid - 64]);
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double2 piv = prow_raw[j];
-            if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
-            const double2 one = make_double2(1.0, 0.0);
-            const double2 ipv = cdiv(one, piv);
-            for (int c = 0; c < nb; ++c) prow[c] = (c == j) ? ipv : cmul(prow_raw[c], ipv);
+        // global pivot (every thread, same order): largest |Re|+|Im|, first row on ties
+        double bv = cv_s[0];
+        int p = cr_s[0], win = 0;
+        for (int q = 1; q < R; ++q)
+            if (cv_s[q] > bv || (cv_s[q] == bv && cr_s[q] < p)) {
+                bv = cv_s[q];
+                p = cr_s[q];
+                win = q;
+            }
+        if (tid == 0 && r == 0) {
+            if (bv <= 0.0) atomicCAS(info + mat, 0, col + 1);
+            ip[col] = p;
         }
-        // row interchange col <-> p inside the panel
-        if (p != col) {
-            if (p >= row0 && p < row0 + nloc)
-                for (int c = threadIdx.x; c < nb; c += blockDim.x) P[(p - row0) * ps + c] = oldrow[c];
+        const double2 *praw = cand + win * nb;
+        if (tid < nb) {
+            double2 piv = praw[j];
+            if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
+            const double2 ipv = cdiv(make_double2(1.0, 0.0), piv);
+            prow[tid] = tid == j ? ipv : cmul(praw[tid], ipv);
+            // row interchange col <-> p inside the panel
+            if (p != col && p >= row0 && p < row0 + nloc) P[(p - row0) * ps + tid] = oldrow[tid];
         }
         __syncthreads();
         // eliminate: every row except col; row col becomes the scaled pivot row
-        for (int i = threadIdx.x; i < nloc; i += blockDim.x) {
-            const int gi = row0 + i;
-            double2 *pr = P + i * ps;
+        if (mine) {
             if (gi == col) {
-                for (int c = 0; c < nb; ++c) pr[c] = prow[c];
+#pragma unroll
+                for (int c = 0; c < (NB ? NB : kPanelMax); ++c)
+                    if (NB || c < nb) pr[c] = prow[c];
             } else {
                 const double2 f = pr[j];
-                for (int c = 0; c < nb; ++c)
-                    pr[c] = (c == j) ? make_double2(-(f.x * prow[j].x - f.y * prow[j].y), -(f.x * prow[j].y + f.y * prow[j].x))
-                                     : csub(pr[c], cmul(f, prow[c]));
+                const double2 pj = prow[j];
+#pragma unroll
+                for (int c = 0; c < (NB ? NB : kPanelMax); ++c)
+                    if (NB || c < nb) {
+                        const double2 pc = prow[c];
+                        const double2 x = pr[c];
+                        pr[c] = (c == j) ? make_double2(-(f.x * pj.x - f.y * pj.y), -(f.x * pj.y + f.y * pj.x))
+                                         : csub(x, cmul(f, pc));
+                    }
             }
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < nloc * nb; e += blockDim.x) {
+    for (int e = tid; e < nloc * nb; e += blockDim.x) {
         const int i = e / nb, c = e % nb;
         Am[(size_t)(row0 + i) * n + k + c] = P[i * ps + c];
     }
@@ -366,19 +359,26 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
 }
 
 // Column index map of the final column interchanges: start from the identity
-// and swap entries j <-> ipiv[j] for j = n-1 down to 0.  One thread per matrix.
-__global__ void k_gje_perm(const int *__restrict__ ipiv, int n, int nmat, int *__restrict__ idx) {
-    const int mat = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mat >= nmat) return;
-    int *id = idx + (size_t)mat * n;
-    const int *ip = ipiv + (size_t)mat * n;
-    for (int j = 0; j < n; ++j) id[j] = j;
-    for (int j = n - 1; j >= 0; --j) {
-        const int p = ip[j];
-        const int t = id[j];
-        id[j] = id[p];
-        id[p] = t;
+// and swap entries j <-> ipiv[j] for j = n-1 down to 0.  One workgroup per
+// matrix; the sequential swap chain runs on one thread over LDS copies.
+__global__ void k_gje_perm(const int *__restrict__ ipiv, int n, int *__restrict__ idx) {
+    extern __shared__ int perm_lds[];
+    int *id = perm_lds, *ip = perm_lds + n;
+    const int mat = blockIdx.x;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        id[j] = j;
+        ip[j] = ipiv[(size_t)mat * n + j];
     }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int j = n - 1; j >= 0; --j) {
+            const int p = ip[j];
+            const int t = id[j];
+            id[j] = id[p];
+            id[p] = t;
+        }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) idx[(size_t)mat * n + j] = id[j];
 }
 
 // out[i][c] = A[i][idx[c]], one workgroup per row, row staged in LDS (in place).
@@ -421,9 +421,13 @@ size_t gje_workspace_bytes(int n, int nmat, int R) {
            sizeof(int) * (size_t)nmat * n * 2 + 512;
 }
 
-// rows of the panel held by one workgroup: few workgroups per matrix keep the
-// per-column grid barrier cheap
-int gje_rows_per_wg(int n) { return std::min(256, std::max(64, (n + 15) / 16)); }
+static size_t gje_panel_lds(int rows, int R) {
+    return sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 2 * kPanelMax + (size_t)R * kPanelMax);
+}
+
+// rows of the panel held by one workgroup (one per thread): few workgroups per
+// matrix keep the per-column grid barrier cheap
+int gje_rows_per_wg(int n) { return std::min(256, n); }
 
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t st) {
     const int rows = gje_rows_per_wg(n);
@@ -443,13 +447,17 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (unsigned int *)info, (size_t)nmat, 0u);
     BGW_HIP(hipGetLastError());
 
-    const size_t lds = sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 3 * kPanelMax);
-    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (R > kGjeMaxR) return BGW_ERR_UNSUPPORTED;
+    const size_t lds = gje_panel_lds(rows, R);
+    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<kPanelMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     unsigned int bar_done = 0;
     for (int k = 0; k < n; k += kPanelMax) {
         const int nb = std::min(kPanelMax, n - k);
         void *args[] = {&A, (void *)&n, &k, (void *)&nb, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
-        BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel, dim3(R * nmat), dim3(256), args, lds, st));
+        const void *kern = nb == kPanelMax ? (const void *)k_gje_panel<kPanelMax> : (const void *)k_gje_panel<0>;
+        BGW_HIP(hipLaunchCooperativeKernel(kern, dim3(R * nmat), dim3(256), args, lds, st));
         bar_done += nb;
         const int m = n - nb;
         if (m > 0) {
@@ -459,7 +467,9 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
             BGW_HIP(hipGetLastError());
         }
     }
-    hipLaunchKernelGGL(k_gje_perm, dim3((nmat + 63) / 64), dim3(64), 0, st, ipiv, n, nmat, idx);
+    const size_t plds = sizeof(int) * 2 * (size_t)n;
+    BGW_HIP(hipFuncSetAttribute((const void *)k_gje_perm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
+    hipLaunchKernelGGL(k_gje_perm, dim3(nmat), dim3(256), plds, st, ipiv, n, idx);
     const size_t rlds = sizeof(double2) * (size_t)n;
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_colperm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
     hipLaunchKernelGGL(k_gje_colperm, dim3(n, nmat), dim3(256), rlds, st, A, n, idx);
@@ -471,12 +481,13 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
 int gje_max_group(int n) {
     const int rows = gje_rows_per_wg(n);
     const int R = (n + rows - 1) / rows;
-    const size_t lds = sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 3 * kPanelMax);
+    const size_t lds = gje_panel_lds(rows, R);
     int per_cu = 0;
-    if (hipFuncSetAttribute((const void *)k_gje_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
+    if (hipFuncSetAttribute((const void *)k_gje_panel<kPanelMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds) != hipSuccess)
         return 1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gje_panel, 256, lds) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gje_panel<kPanelMax>, 256, lds) !=
+            hipSuccess ||
         per_cu <= 0)
         return 1;
     int dev = 0, cus = 0;
