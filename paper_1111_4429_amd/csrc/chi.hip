@@ -116,11 +116,15 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
 }
 }  // namespace
 
-// Persistent batched rank-K update for one output-tile size T.  Work item i
-// of problem p (items p.item0 .. p.item0 + tiles*ns) is K split s = i % ns of
-// upper-triangle tile i / ns; blocks stride over the items [i0, i1) of the
-// whole batch, so uneven problems (many q with different ng, many omega)
-// share one launch per tile size.
+// Persistent batched rank-K update for one output-tile size T.  Problem p
+// owns the items p.item0 .. p.item0 + p.nitems (a multiple of 8).  Blocks
+// stride over the items of the whole batch with a grid that is a multiple of
+// 8, so item i always runs on XCD i % 8 (workgroups are dealt to the XCDs
+// round-robin).  Within a problem, XCD x takes the x-th contiguous eighth of
+// the (K split, tile) sequence, split-major with tiles in grouped order:
+// the blocks resident on one XCD then stream the same K range of nearby row
+// and column blocks of M through its L2.  Uneven problems (many q with
+// different ng, many omega) share one launch per tile size.
 template <int T>
 __global__ __launch_bounds__(256) void k_herk_f64(const HerkProb *__restrict__ probs, int nprob, long long i0,
                                                   long long i1) {
@@ -135,14 +139,13 @@ __global__ __launch_bounds__(256) void k_herk_f64(const HerkProb *__restrict__ p
         }
         const HerkProb &P = probs[lo];
         const long long local = item - P.item0;
-        const int split = (int)(local % P.ns);
-        int u = (int)(local / P.ns), ti = 0;
-        const int nt = P.nt;
-        while (u >= nt - ti) {
-            u -= nt - ti;
-            ++ti;
-        }
-        const int tj = ti + u;
+        const long long chunk = P.nitems / 8;  // items per XCD
+        const long long u = (local % 8) * chunk + local / 8;
+        const long long ntile = (long long)P.nt * (P.nt + 1) / 2;
+        if (u >= ntile * P.ns) continue;  // padding item
+        const int split = (int)(u / ntile);
+        int ti, tj;
+        grouped_tile((int)(u % ntile), P.nt, ti, tj);
         const long long k0 = split * P.kper;
         const long long k1 = min(P.K, k0 + P.kper);
         herk_tile<T>(P.M, P.ng, P.w, ti * T, tj * T, k0, k1, P.out + (size_t)split * P.ng * P.ng, As, Bs);

@@ -311,14 +311,15 @@ int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile,
             for (int p = 0; p < P.nprob; ++p) {
                 if (hps[p].tile != t) continue;
                 hps[p].item0 = item0;
-                item0 += (long long)hps[p].nt * (hps[p].nt + 1) / 2 * hps[p].ns;
+                hps[p].nitems = ((long long)hps[p].nt * (hps[p].nt + 1) / 2 * hps[p].ns + 7) / 8 * 8;
+                item0 += hps[p].nitems;
                 P.herk.push_back(hps[p]);
                 P.herk_prob.push_back(p);
             }
             if (t == 64) P.nitems64 = item0;
         }
         P.nitems = item0;
-        P.grid = (int)slots;
+        P.grid = (int)(slots / 8 * 8);  // a multiple of 8: item i stays on XCD i % 8
         P.off_split = off;
     } else {
         P.off_split = off;

@@ -90,6 +90,32 @@ struct SplitLayout {
     double2 *hw;             // FP64 head-row partials
 };
 
+// Upper-triangle tile number u -> (ti, tj) in grouped order: bands of four
+// tile rows, each band walked column by column.  Consecutive tiles then
+// share a few A row blocks and B column blocks, which is what the blocks
+// co-resident on one XCD read at the same time.
+__device__ inline void grouped_tile(int u, int nt, int &ti, int &tj) {
+    constexpr int R = 4;
+    int r0 = 0;
+    for (;; r0 += R) {
+        const int r1 = min(r0 + R - 1, nt - 1);
+        int cnt = 0;
+        for (int c = r0; c < nt; ++c) cnt += min(c, r1) - r0 + 1;
+        if (u < cnt || r1 == nt - 1) break;
+        u -= cnt;
+    }
+    const int r1 = min(r0 + R - 1, nt - 1);
+    for (int c = r0;; ++c) {
+        const int rows = min(c, r1) - r0 + 1;
+        if (u < rows || c == nt - 1) {
+            ti = r0 + u;
+            tj = c;
+            return;
+        }
+        u -= rows;
+    }
+}
+
 // ---------------------------------------------------------------- batched chi sum
 // One (q, omega) problem of a batched chi0 call.  Plain data: the tables are
 // copied to device memory and read by the persistent kernels.
@@ -100,6 +126,7 @@ struct HerkProb {
     long long K;
     long long kper;    // pairs per work item (K split into ns ranges)
     long long item0;   // first work item of this problem in the batch
+    long long nitems;  // work items of this problem: tiles * ns rounded up to a multiple of 8
     int ng;
     int tile;          // output tile edge: 64 or 32
     int nt;            // tiles per side

@@ -270,32 +270,6 @@ __device__ __forceinline__ void herk_flush(HerkAcc &acc, const int *__restrict__
 }
 }  // namespace
 
-// Upper-triangle tile number u -> (ti, tj) in grouped order: bands of four
-// tile rows, each band walked column by column.  Consecutive tiles then
-// share a few A row blocks and B column blocks, which is what the blocks
-// co-resident on one XCD read at the same time.
-__device__ inline void grouped_tile(int u, int nt, int &ti, int &tj) {
-    constexpr int R = 4;
-    int r0 = 0;
-    for (;; r0 += R) {
-        const int r1 = min(r0 + R - 1, nt - 1);
-        int cnt = 0;
-        for (int c = r0; c < nt; ++c) cnt += min(c, r1) - r0 + 1;
-        if (u < cnt || r1 == nt - 1) break;
-        u -= cnt;
-    }
-    const int r1 = min(r0 + R - 1, nt - 1);
-    for (int c = r0;; ++c) {
-        const int rows = min(c, r1) - r0 + 1;
-        if (u < rows || c == nt - 1) {
-            ti = r0 + u;
-            tj = c;
-            return;
-        }
-        u -= rows;
-    }
-}
-
 // Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
 // With nsplit a multiple of 8, XCD x works through splits x, x + 8, ... one
 // after another, and within a split through the tiles in grouped order, so
