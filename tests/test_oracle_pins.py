@@ -6,6 +6,8 @@ paper, and special cases that reduce to numpy library routines.  None of
 these tests call the GPU library.
 """
 
+import os
+
 import numpy as np
 import pytest
 
@@ -324,10 +326,23 @@ def test_eps_inverse_partial_pivoting_needed():
     assert np.allclose(X, np.linalg.inv(A), rtol=1e-14, atol=1e-14)
 
 
+def _golden_w_table():
+    """Powers of q of the q->0 limits, transcribed from the paper's table of
+    head/wing limits (semiconductor column) into tests/golden/."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "w_table_semiconductor.txt")
+    out = {}
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if line:
+            out[(line[0], line[1])] = int(line[4])
+    return out
+
+
 def test_head_wing_q_scaling():
-    """P-eps6, the paper's q->0 table (semiconductor, no truncation): the head
-    of eps^-1 stays constant, the wing eps^-1_{G0} scales as q and the wing'
-    eps^-1_{0G'} as 1/q."""
+    """P-eps6, the paper's q->0 table (semiconductor, no truncation): going
+    from q0 to q0/10 must scale the head, wing and wing' of eps^-1 and of
+    W = eps^-1 v by 10^(-power) with the powers the table prints."""
+    table = _golden_w_table()
     out = []
     for qx in (1e-3, 1e-4):
         s = synth.small_system(n=16, ngw=181, ng=51, nv=3, nc=12, seed=9, q=(qx, 0, 0))
@@ -338,10 +353,13 @@ def test_head_wing_q_scaling():
         v = oracle.vcoul(s["bmat"], q["q"], q["ge"])
         einv, info = oracle.eps_inv(v, chi)
         assert info[0] == 0
-        out.append(einv[0])
-    a, b = out
-    assert abs(a[0, 0] / b[0, 0] - 1) < 0.01
-    wing = np.abs(a[1:, 0]) / np.abs(b[1:, 0])
-    wingp = np.abs(a[0, 1:]) / np.abs(b[0, 1:])
-    assert np.median(wing) == pytest.approx(10.0, rel=0.02)
-    assert np.median(wingp) == pytest.approx(0.1, rel=0.02)
+        out.append((einv[0], einv[0] * v[None, :]))
+    for k, name in enumerate(("eps_inv", "W")):
+        a, b = out[0][k], out[1][k]
+        # ratio (q0) / (q0/10) = 10^power
+        head = abs(a[0, 0]) / abs(b[0, 0])
+        wing = np.median(np.abs(a[1:, 0]) / np.abs(b[1:, 0]))
+        wingp = np.median(np.abs(a[0, 1:]) / np.abs(b[0, 1:]))
+        assert head == pytest.approx(10.0 ** table[(name, "head")], rel=0.02)
+        assert wing == pytest.approx(10.0 ** table[(name, "wing")], rel=0.02)
+        assert wingp == pytest.approx(10.0 ** table[(name, "wingp")], rel=0.02)
