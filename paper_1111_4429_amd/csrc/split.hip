@@ -54,7 +54,8 @@ __device__ inline unsigned short bf16_bits_exact(double v) {
 // ks of column G = 32 * blockIdx.x + cl and keeps them in registers, so M is
 // read once for both sides.  Side A (X_w, weighted by w) and side B (X) are
 // written when their slice pointer is non-null.
-// S: [NSL][nchunk][NKS][gpad][KS] bf16 bits; E: [nchunk][gpad].
+// S: [NSL][nchunk][NKS][gpad][KS] bf16 bits, each group of 8 values holding four
+// pairs as (Re t0..t3, Im t0..t3); E: [nchunk][gpad].
 // Rows t0 .. t0 + nchunk*128 of M (zero beyond K).
 __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__ M, long long K, int ng, int gpad,
                                                      const double *__restrict__ w, long long t0, int nchunk,
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
                     const double d3 = rint(r);
                     r = (r - d3) * 256.0;
                     const double d4 = rint(r);
-                    const int q = 2 * j + part;
+                    const int q = 4 * part + j;  // real parts first, then imaginary parts
                     d[0][q] = bf16_bits_exact(d1);
                     d[1][q] = bf16_bits_exact(d2);
                     d[2][q] = bf16_bits_exact(d3);
@@ -146,13 +147,15 @@ __device__ inline bf16x8_t as_bf16x8(uint4 u) {
     __builtin_memcpy(&r, &u, 16);
     return r;
 }
-// (x[2m], x[2m+1]) -> (x[2m+1], -x[2m]) for the four pairs of a fragment
+// A fragment holds four pairs as (Re t0..t3, Im t0..t3); the Y operand of the
+// imaginary part is (Im t0..t3, -Re t0..t3): the two halves exchanged and the
+// moved real parts negated (sign bits of both BF16 halves of a dword).
 __device__ inline uint4 swap_neg(uint4 u) {
     uint4 r;
-    r.x = (u.x >> 16) | (((u.x & 0xffffu) ^ 0x8000u) << 16);
-    r.y = (u.y >> 16) | (((u.y & 0xffffu) ^ 0x8000u) << 16);
-    r.z = (u.z >> 16) | (((u.z & 0xffffu) ^ 0x8000u) << 16);
-    r.w = (u.w >> 16) | (((u.w & 0xffffu) ^ 0x8000u) << 16);
+    r.x = u.z;
+    r.y = u.w;
+    r.z = u.x ^ 0x80008000u;
+    r.w = u.y ^ 0x80008000u;
     return r;
 }
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16((a), (b), (c), 0, 0, 0)
@@ -164,24 +167,37 @@ constexpr int STAGE_LDS = 2 * NSL * SLICE_LDS;  // 40960 B
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
+// Block: 8 waves (512 threads) in a 2 x 4 layout over the 64 x 64 tile; wave
+// (wr, wc) owns rows wr*32 .. +32 (two 16-row MFMA blocks a) and columns
+// wc*16 .. +16.  Two waves per SIMD let one wave's LDS reads and VALU work
+// run under the other's MFMAs.
+constexpr int HT = 512;  // threads per block
+
 struct HerkAcc {
-    double4_t re[2][2], im[2][2];
-    float4_t g[3][2][2][2];  // [group][re/im][a][b]
+    float4_t g[3][2][2];  // [group][re/im][a]
 };
 
+// LDS address of this lane's accumulator for row block a, register r.
+__device__ __forceinline__ double2 *acc_at(double2 *accl, int wr, int wc, int li, int lq, int a, int r) {
+    return accl + (wr * 32 + 16 * a + 4 * lq + r) * TT + wc * 16 + li;
+}
+
 // Copy k-step `step` of the A (rows G0..) and B (rows H0..) slices into a
-// stage with direct global->LDS loads: wave w fills rows 16w..16w+15 of every
-// slice, lane L the 16 B of row 16w + L/4 at stored segment L%4.
-__device__ __forceinline__ void herk_issue(unsigned char *stage, const unsigned short *ga,
-                                           const unsigned short *gb, size_t slice_stride, long long step,
-                                           int gpad, int wave) {
-    const size_t off = (size_t)step * gpad * KS;
+// stage with direct global->LDS loads.  The stage is 40 pieces of 1 KB
+// (slice-side q/4, rows 16 (q%4) .. +16); wave w issues pieces 5w .. 5w+4,
+// lane L the 16 B of row 16 (q%4) + L/4 at stored segment L%4.  Addresses: a
+// wave-uniform base plus this lane's 32-bit byte offset.
+__device__ __forceinline__ void herk_issue(unsigned char *stage, const unsigned short *SA,
+                                           const unsigned short *SB, const unsigned (&off)[5],
+                                           size_t slice_stride, long long step, int gpad, int wave) {
+    const size_t so = (size_t)step * gpad * KS;
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl) {
-        __builtin_amdgcn_global_load_lds((const void *)(ga + sl * slice_stride + off),
-                                         (lds_void_t *)(stage + sl * SLICE_LDS + wave * 1024), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((const void *)(gb + sl * slice_stride + off),
-                                         (lds_void_t *)(stage + (NSL + sl) * SLICE_LDS + wave * 1024), 16, 0, 0);
+    for (int i = 0; i < 5; ++i) {
+        const int q = 5 * wave + i;
+        const int idx = q >> 2;  // 0..4: A slices, 5..9: B slices
+        const unsigned short *base = idx < NSL ? SA + idx * slice_stride : SB + (idx - NSL) * slice_stride;
+        __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const char *>(base + so) + off[i]),
+                                         (lds_void_t *)(stage + idx * SLICE_LDS + (q & 3) * 1024), 16, 0, 0);
     }
 }
 
@@ -189,84 +205,90 @@ __device__ __forceinline__ uint4 frag(const unsigned char *slice, int row, int l
     return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
 }
 
-// Ten BF16 products per (Re, Im) for the wave's 32x32 block of one k-step.
+// Ten BF16 products per (Re, Im) for the wave's 32 x 16 block of one k-step.
 __device__ __forceinline__ void herk_compute(const unsigned char *stage, HerkAcc &acc, int wr, int wc, int li,
                                              int lq) {
     const unsigned char *As = stage, *Bs = stage + NSL * SLICE_LDS;
-    uint4 af[NSL][2];
+    uint4 bf[NSL];
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) af[sl][a] = frag(As + sl * SLICE_LDS, wr * 32 + 16 * a + li, lq);
+    for (int sl = 0; sl < NSL; ++sl) bf[sl] = frag(Bs + sl * SLICE_LDS, wc * 16 + li, lq);
     // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d3', 4 = d4'
+    const bf16x8_t b1 = as_bf16x8(bf[0]), b2 = as_bf16x8(bf[1]), b3 = as_bf16x8(bf[2]);
+    const bf16x8_t b3p = as_bf16x8(bf[3]), b4p = as_bf16x8(bf[4]);
+    const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0])), y2 = as_bf16x8(swap_neg(bf[1]));
+    const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2])), y3p = as_bf16x8(swap_neg(bf[3]));
+    const bf16x8_t y4p = as_bf16x8(swap_neg(bf[4]));
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        uint4 bf[NSL];
-#pragma unroll
-        for (int sl = 0; sl < NSL; ++sl) bf[sl] = frag(Bs + sl * SLICE_LDS, wc * 32 + 16 * b + li, lq);
-        const bf16x8_t b1 = as_bf16x8(bf[0]), b2 = as_bf16x8(bf[1]), b3 = as_bf16x8(bf[2]);
-        const bf16x8_t b3p = as_bf16x8(bf[3]), b4p = as_bf16x8(bf[4]);
-        const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0])), y2 = as_bf16x8(swap_neg(bf[1]));
-        const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2])), y3p = as_bf16x8(swap_neg(bf[3]));
-        const bf16x8_t y4p = as_bf16x8(swap_neg(bf[4]));
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const bf16x8_t a1 = as_bf16x8(af[0][a]), a2 = as_bf16x8(af[1][a]), a3 = as_bf16x8(af[2][a]);
-            const bf16x8_t a3p = as_bf16x8(af[3][a]), a4p = as_bf16x8(af[4][a]);
-            float4_t(&g0)[2][2][2] = acc.g[0];
-            float4_t(&g1)[2][2][2] = acc.g[1];
-            float4_t(&g2)[2][2][2] = acc.g[2];
-            g0[0][a][b] = MFMA(a1, b1, g0[0][a][b]);
-            g0[1][a][b] = MFMA(a1, y1, g0[1][a][b]);
-            g1[0][a][b] = MFMA(a1, b2, g1[0][a][b]);
-            g1[1][a][b] = MFMA(a1, y2, g1[1][a][b]);
-            g1[0][a][b] = MFMA(a2, b1, g1[0][a][b]);
-            g1[1][a][b] = MFMA(a2, y1, g1[1][a][b]);
-            g2[0][a][b] = MFMA(a1, b3, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a1, y3, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a2, b2, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a2, y2, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a3, b1, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a3, y1, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a1, b4p, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a1, y4p, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a2, b3p, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a2, y3p, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a3p, b2, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a3p, y2, g2[1][a][b]);
-            g2[0][a][b] = MFMA(a4p, b1, g2[0][a][b]);
-            g2[1][a][b] = MFMA(a4p, y1, g2[1][a][b]);
-        }
+    for (int a = 0; a < 2; ++a) {
+        const int row = wr * 32 + 16 * a + li;
+        const bf16x8_t a1 = as_bf16x8(frag(As, row, lq)), a2 = as_bf16x8(frag(As + SLICE_LDS, row, lq));
+        const bf16x8_t a3 = as_bf16x8(frag(As + 2 * SLICE_LDS, row, lq));
+        const bf16x8_t a3p = as_bf16x8(frag(As + 3 * SLICE_LDS, row, lq));
+        const bf16x8_t a4p = as_bf16x8(frag(As + 4 * SLICE_LDS, row, lq));
+        float4_t(&g0)[2][2] = acc.g[0];
+        float4_t(&g1)[2][2] = acc.g[1];
+        float4_t(&g2)[2][2] = acc.g[2];
+        g0[0][a] = MFMA(a1, b1, g0[0][a]);
+        g0[1][a] = MFMA(a1, y1, g0[1][a]);
+        g1[0][a] = MFMA(a1, b2, g1[0][a]);
+        g1[1][a] = MFMA(a1, y2, g1[1][a]);
+        g1[0][a] = MFMA(a2, b1, g1[0][a]);
+        g1[1][a] = MFMA(a2, y1, g1[1][a]);
+        g2[0][a] = MFMA(a1, b3, g2[0][a]);
+        g2[1][a] = MFMA(a1, y3, g2[1][a]);
+        g2[0][a] = MFMA(a2, b2, g2[0][a]);
+        g2[1][a] = MFMA(a2, y2, g2[1][a]);
+        g2[0][a] = MFMA(a3, b1, g2[0][a]);
+        g2[1][a] = MFMA(a3, y1, g2[1][a]);
+        g2[0][a] = MFMA(a1, b4p, g2[0][a]);
+        g2[1][a] = MFMA(a1, y4p, g2[1][a]);
+        g2[0][a] = MFMA(a2, b3p, g2[0][a]);
+        g2[1][a] = MFMA(a2, y3p, g2[1][a]);
+        g2[0][a] = MFMA(a3p, b2, g2[0][a]);
+        g2[1][a] = MFMA(a3p, y2, g2[1][a]);
+        g2[0][a] = MFMA(a4p, b1, g2[0][a]);
+        g2[1][a] = MFMA(a4p, y1, g2[1][a]);
     }
 }
 
-// Chunk end: combine the three FP32 groups in FP64 with the chunk-column
-// scales and clear them.  D layout of 16x16x32: lane l, register r -> row
-// 4 (l/16) + r, col l % 16.
-__device__ __forceinline__ void herk_flush(HerkAcc &acc, const int *__restrict__ EA, const int *__restrict__ EB,
-                                           long long ch, int gpad, int G0, int H0, int wr, int wc, int li, int lq) {
+// Chunk-column exponents of this lane's output rows and column, loaded when
+// the chunk starts and used when it is flushed.
+struct ChunkExp {
+    int ea[2][4], eb;
+};
+
+__device__ __forceinline__ void herk_exp_load(ChunkExp &E, const int *__restrict__ EA, const int *__restrict__ EB,
+                                              long long ch, int gpad, int G0, int H0, int wr, int wc, int li, int lq) {
+    E.eb = EB[(size_t)ch * gpad + H0 + wc * 16 + li];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int H = H0 + wc * 32 + 16 * b + li;
-            const int eb = EB[(size_t)ch * gpad + H];
+        for (int r = 0; r < 4; ++r) E.ea[a][r] = EA[(size_t)ch * gpad + G0 + wr * 32 + 16 * a + 4 * lq + r];
+}
+
+// Chunk end: combine the three FP32 groups in FP64 with the chunk-column
+// scales into the LDS accumulators and clear them.  D layout of 16x16x32:
+// lane l, register r -> row 4 (l/16) + r, col l % 16.
+__device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E, double2 *accl, int wr, int wc, int li,
+                                           int lq) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
-                const double sc = pow2(EA[(size_t)ch * gpad + G] + eb - 16);
-                const double vre = (double)acc.g[0][0][a][b][r] + (double)acc.g[1][0][a][b][r] * 0.00390625 +
-                                   (double)acc.g[2][0][a][b][r] * 0.0000152587890625;
-                const double vim = (double)acc.g[0][1][a][b][r] + (double)acc.g[1][1][a][b][r] * 0.00390625 +
-                                   (double)acc.g[2][1][a][b][r] * 0.0000152587890625;
-                acc.re[a][b][r] += vre * sc;
-                acc.im[a][b][r] += vim * sc;
-            }
+    for (int a = 0; a < 2; ++a) {
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < 4; ++r) {
+            const double sc = pow2(E.ea[a][r] + E.eb - 16);
+            const double vre = (double)acc.g[0][0][a][r] + (double)acc.g[1][0][a][r] * 0.00390625 +
+                               (double)acc.g[2][0][a][r] * 0.0000152587890625;
+            const double vim = (double)acc.g[0][1][a][r] + (double)acc.g[1][1][a][r] * 0.00390625 +
+                               (double)acc.g[2][1][a][r] * 0.0000152587890625;
+            double2 *dst = acc_at(accl, wr, wc, li, lq, a, r);
+            const double2 old = *dst;
+            *dst = make_double2(old.x + vre * sc, old.y + vim * sc);
         }
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    }
 }
 }  // namespace
 
@@ -276,14 +298,18 @@ __device__ __forceinline__ void herk_flush(HerkAcc &acc, const int *__restrict__
 // the blocks resident on an XCD stream one range of chunks through its L2
 // and share most of their rows.  Otherwise block b takes split b % nsplit and
 // grouped tile b / nsplit.
-__global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__restrict__ SA,
-                                                    const int *__restrict__ EA,
-                                                    const unsigned short *__restrict__ SB,
-                                                    const int *__restrict__ EB, int ng, int gpad, int nt,
-                                                    int nchunk, int nsplit, int chunks_per_split,
-                                                    double2 *__restrict__ part, int add) {
+// The k-steps run through two LDS stages filled by direct global->LDS loads:
+// the next step's slices stream in while the current one feeds the MFMAs.
+// part[split][ng][ng] (+)= chunk sums in FP64 (no prefactor).
+__global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restrict__ SA,
+                                                   const int *__restrict__ EA,
+                                                   const unsigned short *__restrict__ SB,
+                                                   const int *__restrict__ EB, int ng, int gpad, int nt,
+                                                   int nchunk, int nsplit, int chunks_per_split,
+                                                   double2 *__restrict__ part, int add) {
     __shared__ __attribute__((aligned(1024))) unsigned char stage0[STAGE_LDS];
     __shared__ __attribute__((aligned(1024))) unsigned char stage1[STAGE_LDS];
+    __shared__ __attribute__((aligned(16))) double2 accl[TT * TT];  // each lane owns its own entries
 
     const int ntiles = nt * (nt + 1) / 2;
     int split, u;
@@ -304,42 +330,46 @@ __global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__rest
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave >> 2, wc = wave & 3;
     const int li = lane & 15, lq = lane >> 4;
 
-    // loader source of this lane: row 16*wave + lane/4, logical segment (lane%4) ^ (row%4)
-    const int lrow = 16 * wave + (lane >> 2);
-    const int lseg = (lane & 3) ^ (lrow & 3);
-    const unsigned short *ga = SA + (size_t)(G0 + lrow) * KS + lseg * 8;
-    const unsigned short *gb = SB + (size_t)(H0 + lrow) * KS + lseg * 8;
+    // this lane's source offsets (bytes) for its five pieces of a stage
+    unsigned off[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int q = 5 * wave + i;
+        const int row = 16 * (q & 3) + (lane >> 2);
+        const int seg = (lane & 3) ^ (row & 3);
+        off[i] = (unsigned)((((q >> 2) < NSL ? G0 : H0) + row) * KS * 2 + seg * 16);
+    }
 
     HerkAcc acc;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            acc.re[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
-            acc.im[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int r = 0; r < 4; ++r) *acc_at(accl, wr, wc, li, lq, a, r) = make_double2(0.0, 0.0);
 #pragma unroll
-            for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < 3; ++p)
 #pragma unroll
-                for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a][b] = (float4_t){0.f, 0.f, 0.f, 0.f};
-        }
+            for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
+    }
 
     const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;  // s1 - s0 is a multiple of NKS (even)
-    herk_issue(stage0, ga, gb, slice_stride, s0, gpad, wave);
+    herk_issue(stage0, SA, SB, off, slice_stride, s0, gpad, wave);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    ChunkExp E;
     for (long long s = s0; s < s1; s += 2) {
-        herk_issue(stage1, ga, gb, slice_stride, s + 1, gpad, wave);
+        if (s % NKS == 0) herk_exp_load(E, EA, EB, s / NKS, gpad, G0, H0, wr, wc, li, lq);
+        herk_issue(stage1, SA, SB, off, slice_stride, s + 1, gpad, wave);
         __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs they overlap
         herk_compute(stage0, acc, wr, wc, li, lq);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (s + 2 < s1) herk_issue(stage0, ga, gb, slice_stride, s + 2, gpad, wave);
+        if (s + 2 < s1) herk_issue(stage0, SA, SB, off, slice_stride, s + 2, gpad, wave);
         __builtin_amdgcn_sched_barrier(0);
         herk_compute(stage1, acc, wr, wc, li, lq);
-        if (((s + 1) % NKS) == NKS - 1) herk_flush(acc, EA, EB, (s + 1) / NKS, gpad, G0, H0, wr, wc, li, lq);
+        if (((s + 1) % NKS) == NKS - 1) herk_flush(acc, E, accl, wr, wc, li, lq);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     }
@@ -347,17 +377,15 @@ __global__ __launch_bounds__(256) void k_herk_split(const unsigned short *__rest
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
-                const int H = H0 + wc * 32 + 16 * b + li;
-                if (G < ng && H < ng) {
-                    double2 v = make_double2(acc.re[a][b][r], acc.im[a][b][r]);
-                    if (add) v = cadd(v, o[(size_t)G * ng + H]);
-                    o[(size_t)G * ng + H] = v;
-                }
+        for (int r = 0; r < 4; ++r) {
+            const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
+            const int H = H0 + wc * 16 + li;
+            if (G < ng && H < ng) {
+                double2 v = *acc_at(accl, wr, wc, li, lq, a, r);
+                if (add) v = cadd(v, o[(size_t)G * ng + H]);
+                o[(size_t)G * ng + H] = v;
             }
+        }
 }
 
 // FP64 head row: hw[s][H] = sum_{t in split s} w_t conj(M_t(head)) M_t(H)
@@ -515,7 +543,7 @@ int launch_split_gemm(const SplitLayout &L, int ng, int nch, int add, int *used,
     ns = std::min(ns, add > 0 ? add : L.nsplit);
     const int cps = (nch + ns - 1) / ns;
     const int nsplit_used = (nch + cps - 1) / cps;
-    hipLaunchKernelGGL(k_herk_split, dim3((unsigned)(L.tiles * nsplit_used)), dim3(256), 0, st, L.SA, L.EA,
+    hipLaunchKernelGGL(k_herk_split, dim3((unsigned)(L.tiles * nsplit_used)), dim3(HT), 0, st, L.SA, L.EA,
                        L.SB, L.EB, ng, L.gpad, L.nt, nch, nsplit_used, cps, L.part, add > 0 ? 1 : 0);
     BGW_HIP(hipGetLastError());
     *used = nsplit_used;
