@@ -174,13 +174,20 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int HT = 512;  // threads per block
 
 struct HerkAcc {
-    float4_t g[3][2][2];  // [group][re/im][a]
+    float4_t g[3][2][2];        // [group][re/im][a]
+    double re[2][4], im[2][4];  // FP64 sums of the chunks done so far
 };
 
-// LDS address of this lane's accumulator for row block a, register r.
-__device__ __forceinline__ double2 *acc_at(double2 *accl, int wr, int wc, int li, int lq, int a, int r) {
-    return accl + (wr * 32 + 16 * a + 4 * lq + r) * TT + wc * 16 + li;
-}
+constexpr int NSTAGE = 4;  // LDS stages: k-steps are loaded NSTAGE - 1 ahead
+
+// vmcnt(n) alone (expcnt and lgkmcnt left at their maxima)
+#define BGW_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x0F70 | (n))
+
+// Workgroup barrier for the stage pipeline: the wave's LDS reads are complete
+// (lgkmcnt) and its direct-to-LDS loads have been waited for explicitly, so no
+// fence is needed; __syncthreads() would also wait for the loads still in
+// flight for later stages.
+__device__ __forceinline__ void stage_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Copy k-step `step` of the A (rows G0..) and B (rows H0..) slices into a
 // stage with direct global->LDS loads.  The stage is 40 pieces of 1 KB
@@ -205,26 +212,35 @@ __device__ __forceinline__ uint4 frag(const unsigned char *slice, int row, int l
     return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
 }
 
-// Ten BF16 products per (Re, Im) for the wave's 32 x 16 block of one k-step.
-__device__ __forceinline__ void herk_compute(const unsigned char *stage, HerkAcc &acc, int wr, int wc, int li,
-                                             int lq) {
+// The wave's fragments of one k-step: 5 slices of the B column block and of
+// the two A row blocks.
+struct HerkFrags {
+    uint4 b[NSL], a[2][NSL];
+};
+
+__device__ __forceinline__ void herk_frags(const unsigned char *stage, HerkFrags &f, int wr, int wc, int li,
+                                           int lq) {
     const unsigned char *As = stage, *Bs = stage + NSL * SLICE_LDS;
-    uint4 bf[NSL];
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl) bf[sl] = frag(Bs + sl * SLICE_LDS, wc * 16 + li, lq);
+    for (int sl = 0; sl < NSL; ++sl) f.b[sl] = frag(Bs + sl * SLICE_LDS, wc * 16 + li, lq);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) f.a[a][sl] = frag(As + sl * SLICE_LDS, wr * 32 + 16 * a + li, lq);
+}
+
+// Ten BF16 products per (Re, Im) for the wave's 32 x 16 block of one k-step.
+__device__ __forceinline__ void herk_mfma(const HerkFrags &f, HerkAcc &acc) {
     // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d3', 4 = d4'
-    const bf16x8_t b1 = as_bf16x8(bf[0]), b2 = as_bf16x8(bf[1]), b3 = as_bf16x8(bf[2]);
-    const bf16x8_t b3p = as_bf16x8(bf[3]), b4p = as_bf16x8(bf[4]);
-    const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0])), y2 = as_bf16x8(swap_neg(bf[1]));
-    const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2])), y3p = as_bf16x8(swap_neg(bf[3]));
-    const bf16x8_t y4p = as_bf16x8(swap_neg(bf[4]));
+    const bf16x8_t b1 = as_bf16x8(f.b[0]), b2 = as_bf16x8(f.b[1]), b3 = as_bf16x8(f.b[2]);
+    const bf16x8_t b3p = as_bf16x8(f.b[3]), b4p = as_bf16x8(f.b[4]);
+    const bf16x8_t y1 = as_bf16x8(swap_neg(f.b[0])), y2 = as_bf16x8(swap_neg(f.b[1]));
+    const bf16x8_t y3 = as_bf16x8(swap_neg(f.b[2])), y3p = as_bf16x8(swap_neg(f.b[3]));
+    const bf16x8_t y4p = as_bf16x8(swap_neg(f.b[4]));
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const int row = wr * 32 + 16 * a + li;
-        const bf16x8_t a1 = as_bf16x8(frag(As, row, lq)), a2 = as_bf16x8(frag(As + SLICE_LDS, row, lq));
-        const bf16x8_t a3 = as_bf16x8(frag(As + 2 * SLICE_LDS, row, lq));
-        const bf16x8_t a3p = as_bf16x8(frag(As + 3 * SLICE_LDS, row, lq));
-        const bf16x8_t a4p = as_bf16x8(frag(As + 4 * SLICE_LDS, row, lq));
+        const bf16x8_t a1 = as_bf16x8(f.a[a][0]), a2 = as_bf16x8(f.a[a][1]), a3 = as_bf16x8(f.a[a][2]);
+        const bf16x8_t a3p = as_bf16x8(f.a[a][3]), a4p = as_bf16x8(f.a[a][4]);
         float4_t(&g0)[2][2] = acc.g[0];
         float4_t(&g1)[2][2] = acc.g[1];
         float4_t(&g2)[2][2] = acc.g[2];
@@ -267,10 +283,9 @@ __device__ __forceinline__ void herk_exp_load(ChunkExp &E, const int *__restrict
 }
 
 // Chunk end: combine the three FP32 groups in FP64 with the chunk-column
-// scales into the LDS accumulators and clear them.  D layout of 16x16x32:
+// scales into the FP64 accumulators and clear them.  D layout of 16x16x32:
 // lane l, register r -> row 4 (l/16) + r, col l % 16.
-__device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E, double2 *accl, int wr, int wc, int li,
-                                           int lq) {
+__device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
@@ -280,15 +295,57 @@ __device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E, doub
                                (double)acc.g[2][0][a][r] * 0.0000152587890625;
             const double vim = (double)acc.g[0][1][a][r] + (double)acc.g[1][1][a][r] * 0.00390625 +
                                (double)acc.g[2][1][a][r] * 0.0000152587890625;
-            double2 *dst = acc_at(accl, wr, wc, li, lq, a, r);
-            const double2 old = *dst;
-            *dst = make_double2(old.x + vre * sc, old.y + vim * sc);
+            acc.re[a][r] += vre * sc;
+            acc.im[a][r] += vim * sc;
         }
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
             for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
     }
+}
+// The k-step loop over [s0, s1) (a whole number of chunks).  The four stages
+// are distinct restrict-qualified buffers, which tells the compiler that the
+// loads in flight into one stage do not alias the reads of another, so it
+// inserts no wait for them before those reads.
+__device__ __forceinline__ void herk_pipeline(unsigned char *__restrict__ stage0, unsigned char *__restrict__ stage1,
+                                              unsigned char *__restrict__ stage2, unsigned char *__restrict__ stage3,
+                                              const unsigned short *__restrict__ SA,
+                                              const unsigned short *__restrict__ SB, const int *__restrict__ EA,
+                                              const int *__restrict__ EB, const unsigned (&off)[5],
+                                              size_t slice_stride, long long s0, long long s1, int gpad, int G0,
+                                              int H0, int wave, int wr, int wc, int li, int lq, HerkAcc &acc) {
+    // Each issue is 5 loads per wave.  Before step x+1 is read, the loads of
+    // steps x+2 and x+3 (10, when both were issued) may still be in flight.
+    // The fragments of the current step are read before the loads into the
+    // free stage are issued, so no wait on those loads is needed for them.
+#define BGW_STEP(cur, nxt_stage, x)                                              \
+    {                                                                             \
+        HerkFrags f_;                                                             \
+        herk_frags(cur, f_, wr, wc, li, lq);                                      \
+        __builtin_amdgcn_sched_barrier(0);                                        \
+        if ((x) + 3 < s1) herk_issue(nxt_stage, SA, SB, off, slice_stride, (x) + 3, gpad, wave); \
+        __builtin_amdgcn_sched_barrier(0);                                        \
+        herk_mfma(f_, acc);                                                       \
+        if (((x) % NKS) == NKS - 1) herk_flush(acc, E);                           \
+        if ((x) + 3 < s1) BGW_WAIT_VM(10);                                        \
+        else BGW_WAIT_VM(0);                                                      \
+        stage_barrier();                                                          \
+    }
+    herk_issue(stage0, SA, SB, off, slice_stride, s0, gpad, wave);
+    herk_issue(stage1, SA, SB, off, slice_stride, s0 + 1, gpad, wave);
+    herk_issue(stage2, SA, SB, off, slice_stride, s0 + 2, gpad, wave);
+    BGW_WAIT_VM(10);
+    stage_barrier();
+    ChunkExp E;
+    for (long long s = s0; s < s1; s += NSTAGE) {
+        if (s % NKS == 0) herk_exp_load(E, EA, EB, s / NKS, gpad, G0, H0, wr, wc, li, lq);
+        BGW_STEP(stage0, stage3, s);
+        BGW_STEP(stage1, stage0, s + 1);
+        BGW_STEP(stage2, stage1, s + 2);
+        BGW_STEP(stage3, stage2, s + 3);
+    }
+#undef BGW_STEP
 }
 }  // namespace
 
@@ -298,8 +355,9 @@ __device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E, doub
 // the blocks resident on an XCD stream one range of chunks through its L2
 // and share most of their rows.  Otherwise block b takes split b % nsplit and
 // grouped tile b / nsplit.
-// The k-steps run through two LDS stages filled by direct global->LDS loads:
-// the next step's slices stream in while the current one feeds the MFMAs.
+// The k-steps run through four LDS stages filled by direct global->LDS
+// loads: the slices of the next three steps stream in while the current one
+// feeds the MFMAs.
 // part[split][ng][ng] (+)= chunk sums in FP64 (no prefactor).
 __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restrict__ SA,
                                                    const int *__restrict__ EA,
@@ -309,7 +367,8 @@ __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restr
                                                    double2 *__restrict__ part, int add) {
     __shared__ __attribute__((aligned(1024))) unsigned char stage0[STAGE_LDS];
     __shared__ __attribute__((aligned(1024))) unsigned char stage1[STAGE_LDS];
-    __shared__ __attribute__((aligned(16))) double2 accl[TT * TT];  // each lane owns its own entries
+    __shared__ __attribute__((aligned(1024))) unsigned char stage2[STAGE_LDS];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage3[STAGE_LDS];
 
     const int ntiles = nt * (nt + 1) / 2;
     int split, u;
@@ -347,32 +406,16 @@ __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restr
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) *acc_at(accl, wr, wc, li, lq, a, r) = make_double2(0.0, 0.0);
+        for (int r = 0; r < 4; ++r) acc.re[a][r] = acc.im[a][r] = 0.0;
 #pragma unroll
         for (int p = 0; p < 3; ++p)
 #pragma unroll
             for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
     }
 
-    const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;  // s1 - s0 is a multiple of NKS (even)
-    herk_issue(stage0, SA, SB, off, slice_stride, s0, gpad, wave);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    ChunkExp E;
-    for (long long s = s0; s < s1; s += 2) {
-        if (s % NKS == 0) herk_exp_load(E, EA, EB, s / NKS, gpad, G0, H0, wr, wc, li, lq);
-        herk_issue(stage1, SA, SB, off, slice_stride, s + 1, gpad, wave);
-        __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs they overlap
-        herk_compute(stage0, acc, wr, wc, li, lq);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (s + 2 < s1) herk_issue(stage0, SA, SB, off, slice_stride, s + 2, gpad, wave);
-        __builtin_amdgcn_sched_barrier(0);
-        herk_compute(stage1, acc, wr, wc, li, lq);
-        if (((s + 1) % NKS) == NKS - 1) herk_flush(acc, E, accl, wr, wc, li, lq);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
+    const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;  // s1 - s0: a multiple of NKS (8)
+    herk_pipeline(stage0, stage1, stage2, stage3, SA, SB, EA, EB, off, slice_stride, s0, s1, gpad, G0, H0, wave, wr,
+                  wc, li, lq, acc);
     double2 *o = part + (size_t)split * ng * ng;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -381,7 +424,7 @@ __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restr
             const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
             const int H = H0 + wc * 16 + li;
             if (G < ng && H < ng) {
-                double2 v = *acc_at(accl, wr, wc, li, lq, a, r);
+                double2 v = make_double2(acc.re[a][r], acc.im[a][r]);
                 if (add) v = cadd(v, o[(size_t)G * ng + H]);
                 o[(size_t)G * ng + H] = v;
             }
