@@ -248,6 +248,166 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
     }
 }
 
+// Full-width panels (kPanelMax columns): the same column steps as
+// k_gje_panel, with each thread's panel row held in registers.  The column
+// steps are instantiated per column index, so every row element has a fixed
+// register.  Every thread scales by the inverse pivot on the fly:
+// row i -= (f / p) * (pivot row) and row col = (pivot row) / p, so the only
+// shared data per column are the candidates fetched after the grid barrier.
+struct GjeRegCtx {
+    double2 *Am;
+    int *ip, *info, *crow;
+    double *cval;
+    double2 *crows, *rbuf, *oldrow, *cand;
+    unsigned int *bar;
+    double *wv, *cv_s;
+    int *wrow, *cr_s;
+    int k, R, r, row0, nloc, gi, lane, wave, tid, mat;
+    bool mine;
+    unsigned int bar_done;
+};
+
+template <int J>
+__device__ __forceinline__ void gje_reg_column(const GjeRegCtx &x, double2 (&rv)[kPanelMax]) {
+    constexpr int nb = kPanelMax;
+    const int col = x.k + J;
+    constexpr int slot = J & 1;
+    const int R = x.R;
+    // local pivot candidate among rows >= col
+    double best = -1.0;
+    int brow = 0x7fffffff;
+    if (x.mine && x.gi >= col) {
+        best = cabs1(rv[J]);
+        brow = x.gi;
+    }
+    wave_argmax(best, brow);
+    if (x.lane == 0) {
+        x.wv[x.wave] = best;
+        x.wrow[x.wave] = brow;
+    }
+    __syncthreads();
+    best = x.wv[0];
+    brow = x.wrow[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (x.wv[w] > best || (x.wv[w] == best && x.wrow[w] < brow)) {
+            best = x.wv[w];
+            brow = x.wrow[w];
+        }
+    // publish the candidate (value, row, row contents) and, from its owner, row col
+    if (x.tid == 0) {
+        __hip_atomic_store(&x.cval[slot * R + x.r], best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&x.crow[slot * R + x.r], brow, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (x.mine && x.gi == brow) {
+#pragma unroll
+        for (int c = 0; c < nb; ++c) st_agent(&x.crows[((size_t)slot * R + x.r) * nb + c], rv[c]);
+    }
+    if (x.mine && x.gi == col) {
+#pragma unroll
+        for (int c = 0; c < nb; ++c) st_agent(&x.rbuf[slot * nb + c], rv[c]);
+    }
+
+    matrix_barrier(x.bar, (x.bar_done + J + 1) * (unsigned)R, x.info + x.mat);
+
+    // every workgroup fetches all candidates and row col in one round
+    for (int e = x.tid; e < R * nb; e += blockDim.x) x.cand[e] = ld_agent(&x.crows[(size_t)slot * R * nb + e]);
+    if (x.tid < R) {
+        x.cv_s[x.tid] = __hip_atomic_load(&x.cval[slot * R + x.tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        x.cr_s[x.tid] = __hip_atomic_load(&x.crow[slot * R + x.tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (x.tid >= 64 && x.tid < 64 + nb) x.oldrow[x.tid - 64] = ld_agent(&x.rbuf[slot * nb + x.tid - 64]);
+    __syncthreads();
+    // global pivot (every thread, same order): largest |Re|+|Im|, first row on ties
+    double bv = x.cv_s[0];
+    int p = x.cr_s[0], win = 0;
+    for (int q = 1; q < R; ++q)
+        if (x.cv_s[q] > bv || (x.cv_s[q] == bv && x.cr_s[q] < p)) {
+            bv = x.cv_s[q];
+            p = x.cr_s[q];
+            win = q;
+        }
+    if (x.tid == 0 && x.r == 0) {
+        if (bv <= 0.0) atomicCAS(x.info + x.mat, 0, col + 1);
+        x.ip[col] = p;
+    }
+    const double2 *praw = x.cand + win * nb;
+    double2 piv = praw[J];
+    if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
+    const double2 ipv = cdiv(make_double2(1.0, 0.0), piv);
+    if (x.mine) {
+        if (x.gi == col) {
+            // row col becomes the scaled pivot row
+#pragma unroll
+            for (int c = 0; c < nb; ++c) rv[c] = c == J ? ipv : cmul(praw[c], ipv);
+        } else {
+            if (p != col && x.gi == p) {
+#pragma unroll
+                for (int c = 0; c < nb; ++c) rv[c] = x.oldrow[c];  // row p receives row col
+            }
+            const double2 fs = cmul(rv[J], ipv);
+#pragma unroll
+            for (int c = 0; c < nb; ++c)
+                rv[c] = c == J ? make_double2(-fs.x, -fs.y) : csub(rv[c], cmul(fs, praw[c]));
+        }
+    }
+}
+
+template <int J>
+struct GjeRegColumns {
+    __device__ __forceinline__ static void run(const GjeRegCtx &x, double2 (&rv)[kPanelMax]) {
+        gje_reg_column<J>(x, rv);
+        GjeRegColumns<J + 1>::run(x, rv);
+    }
+};
+template <>
+struct GjeRegColumns<kPanelMax> {
+    __device__ __forceinline__ static void run(const GjeRegCtx &, double2 (&)[kPanelMax]) {}
+};
+
+__global__ __launch_bounds__(256) void k_gje_panel_reg(double2 *__restrict__ A, int n, int k, int rows, int R,
+                                                       int *__restrict__ ipiv, int *__restrict__ info,
+                                                       GjeScratch sc, unsigned int bar_done) {
+    extern __shared__ double2 lds[];
+    __shared__ double wv[4], cv_s[kGjeMaxR];
+    __shared__ int wrow[4], cr_s[kGjeMaxR];
+    GjeRegCtx x;
+    x.mat = blockIdx.x / R;
+    x.r = blockIdx.x % R;
+    x.Am = A + (size_t)x.mat * n * n;
+    x.ip = ipiv + (size_t)x.mat * n;
+    x.info = info;
+    x.row0 = x.r * rows;
+    x.nloc = max(0, min(rows, n - x.row0));
+    x.cval = sc.cand_val + (size_t)x.mat * 2 * R;
+    x.crow = sc.cand_row + (size_t)x.mat * 2 * R;
+    x.crows = sc.cand_rows + (size_t)x.mat * 2 * R * kPanelMax;
+    x.rbuf = sc.rowbuf + (size_t)x.mat * 2 * kPanelMax;
+    x.bar = sc.bar + x.mat;
+    x.oldrow = lds;                  // row k+j before the swap [kPanelMax]
+    x.cand = lds + kPanelMax;        // candidate rows of all workgroups [R][kPanelMax]
+    x.wv = wv;
+    x.cv_s = cv_s;
+    x.wrow = wrow;
+    x.cr_s = cr_s;
+    x.k = k;
+    x.R = R;
+    x.tid = threadIdx.x;
+    x.lane = x.tid & 63;
+    x.wave = x.tid >> 6;
+    x.gi = x.row0 + x.tid;
+    x.mine = x.tid < x.nloc;
+    x.bar_done = bar_done;
+
+    double2 rv[kPanelMax];
+#pragma unroll
+    for (int c = 0; c < kPanelMax; ++c) rv[c] = x.mine ? x.Am[(size_t)x.gi * n + k + c] : make_double2(0.0, 0.0);
+    GjeRegColumns<0>::run(x, rv);
+    if (x.mine) {
+#pragma unroll
+        for (int c = 0; c < kPanelMax; ++c) x.Am[(size_t)x.gi * n + k + c] = rv[c];
+    }
+}
+
 // For every column outside the panel: apply the panel's row interchanges in
 // order, copy the panel rows to Rs [nb][n - nb] and zero them in A.
 __global__ void k_gje_swap_save(double2 *__restrict__ A, int n, int k, int nb, const int *__restrict__ ipiv,
@@ -425,6 +585,8 @@ static size_t gje_panel_lds(int rows, int R) {
     return sizeof(double2) * ((size_t)rows * (kPanelMax + 1) + 2 * kPanelMax + (size_t)R * kPanelMax);
 }
 
+static size_t gje_panel_reg_lds(int R) { return sizeof(double2) * (kPanelMax + (size_t)R * kPanelMax); }
+
 // rows of the panel held by one workgroup (one per thread): few workgroups per
 // matrix keep the per-column grid barrier cheap
 int gje_rows_per_wg(int n) { return std::min(256, n); }
@@ -452,12 +614,18 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<kPanelMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const size_t rlds_panel = gje_panel_reg_lds(R);
     unsigned int bar_done = 0;
     for (int k = 0; k < n; k += kPanelMax) {
         const int nb = std::min(kPanelMax, n - k);
         void *args[] = {&A, (void *)&n, &k, (void *)&nb, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
-        const void *kern = nb == kPanelMax ? (const void *)k_gje_panel<kPanelMax> : (const void *)k_gje_panel<0>;
-        BGW_HIP(hipLaunchCooperativeKernel(kern, dim3(R * nmat), dim3(256), args, lds, st));
+        if (nb == kPanelMax) {
+            void *rargs[] = {&A, (void *)&n, &k, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
+            BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel_reg, dim3(R * nmat), dim3(256), rargs,
+                                               rlds_panel, st));
+        } else {
+            BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel<0>, dim3(R * nmat), dim3(256), args, lds, st));
+        }
         bar_done += nb;
         const int m = n - nb;
         if (m > 0) {
