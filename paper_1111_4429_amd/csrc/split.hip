@@ -50,10 +50,12 @@ __device__ inline unsigned short bf16_bits_exact(double v) {
 }
 }  // namespace
 
-// Block = one chunk x 32 columns; thread (ks, cl) owns the 16 pairs of k-step
-// ks of column G = 32 * blockIdx.x + cl and keeps them in registers, so M is
-// read once for both sides.  Side A (X_w, weighted by w) and side B (X) are
-// written when their slice pointer is non-null.
+// Block = one chunk x 32 columns.  Thread t owns column G = 32 blockIdx.x +
+// (t/4) % 32 and, in each of the k-steps 4 (t/128) .. +3, the four pairs
+// 4 (t%4) .. +3; it keeps its 16 pairs in registers, so M is read once for
+// both sides.  With this assignment every 16-byte store instruction of a wave
+// writes 1 KB of contiguous slice memory.  Side A (X_w, weighted by w) and
+// side B (X) are written when their slice pointer is non-null.
 // S: [NSL][nchunk][NKS][gpad][KS] bf16 bits, each group of 8 values holding four
 // pairs as (Re t0..t3, Im t0..t3); E: [nchunk][gpad].
 // Rows t0 .. t0 + nchunk*128 of M (zero beyond K).
@@ -61,40 +63,41 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
                                                      const double *__restrict__ w, long long t0, int nchunk,
                                                      unsigned short *__restrict__ SA, int *__restrict__ EA,
                                                      unsigned short *__restrict__ SB, int *__restrict__ EB) {
-    __shared__ double red[2][NKS][32];
-    const int cl = threadIdx.x & 31, ks = threadIdx.x >> 5;
+    __shared__ double red[2][8][32];
+    const int q = threadIdx.x & 3, cl = (threadIdx.x >> 2) & 31, kh = threadIdx.x >> 7;
     const int G = blockIdx.x * 32 + cl;
     const int chunk = blockIdx.y;
-    const long long tb = t0 + (long long)chunk * SKP + ks * (KS / 2);
+    const long long tb = t0 + (long long)chunk * SKP;
     const bool col = G < ng;
-    double2 m[KS / 2];
-    double s[KS / 2];
+    double2 m[4][4];  // [k-step i][pair j]
+    double s[4][4];
     double mxa = 0.0, mxb = 0.0;
 #pragma unroll
-    for (int i = 0; i < KS / 2; ++i) {
-        const long long t = tb + i;
-        m[i] = make_double2(0.0, 0.0);
-        s[i] = 0.0;
-        if (t < K) {
-            s[i] = w ? w[t] : 1.0;
-            if (col) m[i] = M[t * ng + G];
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long t = tb + (4 * kh + i) * (KS / 2) + 4 * q + j;
+            m[i][j] = make_double2(0.0, 0.0);
+            s[i][j] = 0.0;
+            if (t < K) {
+                s[i][j] = w ? w[t] : 1.0;
+                if (col) m[i][j] = M[t * ng + G];
+            }
+            mxa = fmax(mxa, fabs(s[i][j]) * fmax(fabs(m[i][j].x), fabs(m[i][j].y)));
+            mxb = fmax(mxb, fmax(fabs(m[i][j].x), fabs(m[i][j].y)));
         }
-        mxa = fmax(mxa, fabs(s[i]) * fmax(fabs(m[i].x), fabs(m[i].y)));
-        mxb = fmax(mxb, fmax(fabs(m[i].x), fabs(m[i].y)));
-    }
-    red[0][ks][cl] = mxa;
-    red[1][ks][cl] = mxb;
+    red[0][4 * kh + q][cl] = mxa;
+    red[1][4 * kh + q][cl] = mxb;
     __syncthreads();
     mxa = 0.0;
     mxb = 0.0;
 #pragma unroll
-    for (int k = 0; k < NKS; ++k) {
+    for (int k = 0; k < 8; ++k) {
         mxa = fmax(mxa, red[0][k][cl]);
         mxb = fmax(mxb, red[1][k][cl]);
     }
     if (G >= gpad) return;
     const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
-    const size_t dst0 = (((size_t)chunk * NKS + ks) * gpad + G) * KS;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         unsigned short *S = side ? SB : SA;
@@ -103,17 +106,18 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
         const double mx = side ? mxb : mxa;
         int e = 0;
         if (mx > 0.0) (void)frexp(mx, &e);  // mx < 2^e
-        if (ks == 0) E[(size_t)chunk * gpad + G] = e;
+        if (q == 0 && kh == 0) E[(size_t)chunk * gpad + G] = e;
         const double up = pow2(8 - e);
 #pragma unroll
-        for (int i4 = 0; i4 < KS / 2; i4 += 4) {
+        for (int i = 0; i < 4; ++i) {
+            const int ks = 4 * kh + i;
             unsigned short d[NSL][8];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int part = 0; part < 2; ++part) {
-                    const double v = part ? m[i4 + j].y : m[i4 + j].x;
-                    const double y = (side ? v : s[i4 + j] * v) * up;
+                    const double v = part ? m[i][j].y : m[i][j].x;
+                    const double y = (side ? v : s[i][j] * v) * up;
                     const double d1 = rint(y);
                     double r = (y - d1) * 256.0;
                     const double d2 = rint(r);
@@ -121,13 +125,14 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
                     const double d3 = rint(r);
                     r = (r - d3) * 256.0;
                     const double d4 = rint(r);
-                    const int q = 4 * part + j;  // real parts first, then imaginary parts
-                    d[0][q] = bf16_bits_exact(d1);
-                    d[1][q] = bf16_bits_exact(d2);
-                    d[2][q] = bf16_bits_exact(d3);
-                    d[3][q] = bf16_bits_exact(d3 * 0.00390625);
-                    d[4][q] = bf16_bits_exact(d4 * 0.00390625);
+                    const int qq = 4 * part + j;  // real parts first, then imaginary parts
+                    d[0][qq] = bf16_bits_exact(d1);
+                    d[1][qq] = bf16_bits_exact(d2);
+                    d[2][qq] = bf16_bits_exact(d3);
+                    d[3][qq] = bf16_bits_exact(d3 * 0.00390625);
+                    d[4][qq] = bf16_bits_exact(d4 * 0.00390625);
                 }
+            const size_t dst = (((size_t)chunk * NKS + ks) * gpad + G) * KS + 8 * q;
 #pragma unroll
             for (int sl = 0; sl < NSL; ++sl) {
                 uint4 pk;
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
                 pk.y = d[sl][2] | ((unsigned)d[sl][3] << 16);
                 pk.z = d[sl][4] | ((unsigned)d[sl][5] << 16);
                 pk.w = d[sl][6] | ((unsigned)d[sl][7] << 16);
-                *reinterpret_cast<uint4 *>(S + sl * slice_stride + dst0 + 2 * i4) = pk;
+                *reinterpret_cast<uint4 *>(S + sl * slice_stride + dst) = pk;
             }
         }
     }
