@@ -33,9 +33,12 @@ bool pair_two_pass_supported(const AxisPlan &py, const AxisPlan &pz);
 int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
                    const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
                    hipStream_t st);
+int launch_pair_yzr(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                    const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                    hipStream_t st);
 int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int rey, int rez, const int *ge_code2,
                   const int *ge_out, int ng, double2 *M, int nv, int nc, int c0, int ncb, long long row0, size_t N,
-                  hipStream_t st);
+                  bool yfast, hipStream_t st);
 int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &, const AxisPlan &,
                          const AxisPlan &, const SphereMaps &, int rwy, double2 *grids, hipStream_t);
 int launch_eps_build(const double2 *chi, const double *v, int ng, int nw, double2 *eps, hipStream_t);
@@ -434,13 +437,19 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
         if (two_pass) {
             for (int c0 = 0; c0 < d->nc; c0 += ncb) {
                 const int cn = std::min(ncb, d->nc - c0);
+                bool yfast = true;
                 {
                     Timed tm(h, BGW_KERNEL_PAIR, st);
-                    BGW_TRY(launch_pair_yz(gv, gc, kn, d->nv, d->nc, c0, cn, px, py, pz, pl->sm.rey, pl->sm.rez, T, st));
+                    int rc = launch_pair_yzr(gv, gc, kn, d->nv, d->nc, c0, cn, px, py, pz, pl->sm.rey, pl->sm.rez, T, st);
+                    if (rc == BGW_ERR_UNSUPPORTED) {
+                        yfast = false;
+                        rc = launch_pair_yz(gv, gc, kn, d->nv, d->nc, c0, cn, px, py, pz, pl->sm.rey, pl->sm.rez, T, st);
+                    }
+                    BGW_TRY(rc);
                 }
                 Timed tm(h, BGW_KERNEL_PAIR_X, st);
                 BGW_TRY(launch_pair_x(T, (long long)kn * d->nv * cn, px, pl->sm.rey, pl->sm.rez, pl->sm.ge_code2,
-                                      pl->sm.ge_out, d->ng, (double2 *)M, d->nv, d->nc, c0, cn, row0, N, st));
+                                      pl->sm.ge_out, d->ng, (double2 *)M, d->nv, d->nc, c0, cn, row0, N, yfast, st));
             }
         } else {
             Timed tm(h, BGW_KERNEL_PAIR, st);

@@ -117,6 +117,93 @@ struct RegDFT<16> {
     }
 };
 
+template <>
+struct RegDFT<3> {
+    __device__ static void run(double2 *v) {
+        const double2 s = v[0], t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
+        const double2 m = make_double2(s.x - 0.5 * t1.x, s.y - 0.5 * t1.y);
+        const double2 is = make_double2(-kS60 * t2.y, kS60 * t2.x);
+        v[0] = cadd(s, t1);
+        v[1] = cadd(m, is);
+        v[2] = csub(m, is);
+    }
+};
+
+// cos(2 pi j / 96), j = 0..24, rounded to the nearest double; every twiddle
+// exp(2 pi i j / N) of the lengths 16, 24, 32, 48 and 96 is one of these
+// values up to sign (quarter-wave symmetry).
+constexpr double kCos96[25] = {1.0,
+                               0.9978589232386035,
+                               0.9914448613738104,
+                               0.9807852804032304,
+                               0.9659258262890683,
+                               0.9469301294951057,
+                               0.9238795325112867,
+                               0.8968727415326883,
+                               0.8660254037844386,
+                               0.8314696123025452,
+                               0.7933533402912352,
+                               0.7518398074789774,
+                               0.7071067811865476,
+                               0.6593458151000688,
+                               0.6087614290087207,
+                               0.5555702330196022,
+                               0.5,
+                               0.4422886902190013,
+                               0.3826834323650898,
+                               0.3214394653031616,
+                               0.25881904510252074,
+                               0.19509032201612828,
+                               0.1305261922200516,
+                               0.06540312923014306,
+                               0.0};
+__host__ __device__ constexpr double cos96(int j) {
+    j = ((j % 96) + 96) % 96;
+    return j <= 24 ? kCos96[j] : (j <= 48 ? -kCos96[48 - j] : (j <= 72 ? -kCos96[j - 48] : kCos96[96 - j]));
+}
+__host__ __device__ constexpr double sin96(int j) { return cos96(24 - j); }
+
+// Whole-line DFT in registers, kernel exp(+2 pi i j k / N), natural order in
+// and out, N = R1 * R2: R2 DFTs of length R1 over x[a + R2 b], twiddles
+// w_N^{a kb}, then R1 DFTs of length R2 (output kb + R1 ka).
+template <int R1, int R2>
+struct RegFFT2 {
+    static constexpr int N = R1 * R2;
+    __device__ static void run(double2 *v) {
+        double2 y[R2][R1];
+#pragma unroll
+        for (int a = 0; a < R2; ++a) {
+#pragma unroll
+            for (int b = 0; b < R1; ++b) y[a][b] = v[a + R2 * b];
+            RegDFT<R1>::run(y[a]);
+#pragma unroll
+            for (int kb = 1; kb < R1; ++kb)
+                if (a) y[a][kb] = cmul(y[a][kb], make_double2(cos96(a * kb * (96 / N)), sin96(a * kb * (96 / N))));
+            // one sub-transform at a time keeps the live registers near the line itself
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int kb = 0; kb < R1; ++kb) {
+            double2 z[R2];
+#pragma unroll
+            for (int a = 0; a < R2; ++a) z[a] = y[a][kb];
+            RegDFT<R2>::run(z);
+#pragma unroll
+            for (int ka = 0; ka < R2; ++ka) v[kb + R1 * ka] = z[ka];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+};
+
+template <int N>
+struct LineDFT;
+template <>
+struct LineDFT<16> : RegDFT<16> {};
+template <>
+struct LineDFT<24> : RegFFT2<8, 3> {};
+template <>
+struct LineDFT<32> : RegFFT2<8, 4> {};
+
 // n = R1 * R2; element z of a line at line[z * es].  Stage 1 (in place): for
 // each za < R2, Y_za = DFT_R1 over x[za + R2 zb], times w_n^{za kb}, stored at
 // position za + R2 kb.  Output k = kb + R1 ka is then
@@ -441,14 +528,126 @@ __global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict_
     }
 }
 
-// Pass B.  T: [npairs][n1][nbox]; sphere points in (mx, my, mz) order (ge_code2),
+// Pass A for y and z lengths N <= 32, one wavefront per workgroup and no
+// workgroup barriers.  Workgroup = (k, c, block of x-planes); it loops over
+// the valence bands and takes G x-planes of one pair per round:
+//   y: lane (plane p, z) reads the y-line of u_v and u_c at that z (at fixed y
+//      the lanes of one plane read N consecutive elements: coalesced),
+//      forms conj(u_v) u_c, does the whole N-point DFT in registers and
+//      stores the bey outputs of the dielectric box to Q[p][iy][z] in LDS;
+//   z: lane (plane p, iy) reads row Q[p][iy][.], does the N-point DFT in
+//      registers and writes the bez box outputs to T[t][x][iz][iy] (iy
+//      fastest, so the stores of a wave are contiguous runs).
+// The Q row stride N + 1 is odd in 16-byte units, so both the column writes
+// and the row reads are free of LDS bank conflicts.
+template <int N, int G, int MINW>
+__global__ __launch_bounds__(64, MINW) void k_pair_yzr(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
+                                                 int nv, int nc, int c0, int ncb, int n1, int rey, int rez, int xblk,
+                                                 double2 *__restrict__ T) {
+    constexpr int QS = N + 1;
+    extern __shared__ double2 Q[];  // [G][bey][QS]
+    const int lane = threadIdx.x;
+    const int bey = 2 * rey + 1, bez = 2 * rez + 1, nbox = bey * bez;
+    const int nxb = (n1 + xblk - 1) / xblk;
+    const int cl = blockIdx.x % ncb;
+    const int rest = blockIdx.x / ncb;
+    const int xb = rest % nxb;
+    const int k = rest / nxb;
+    const int x0 = xb * xblk, x1 = min(n1, x0 + xblk);
+    const size_t plane = (size_t)N * N;
+    const size_t NB = (size_t)n1 * plane;
+    const double2 *uc = gc + (size_t)(k * nc + c0 + cl) * NB;
+    const double2 *uvk = gv + (size_t)k * nv * NB;
+    const int py = lane / N, zl = lane - py * N;   // y-stage role
+    const int pz = lane / bey, iy = lane - pz * bey;  // z-stage role
+#pragma unroll 1
+    for (int v = 0; v < nv; ++v) {
+        const long long tl = ((long long)k * nv + v) * ncb + cl;
+#pragma unroll 1
+        for (int xg = x0; xg < x1; xg += G) {
+            {
+                const int x = xg + py;
+                const bool act = py < G && x < x1;
+                double2 d[N];
+                if (act) {
+                    // the u_c line first, then u_v in blocks of 8 with one block in
+                    // flight ahead of the products (bounded register footprint)
+                    const double2 *a = uvk + v * NB + x * plane + zl;
+                    const double2 *b = uc + x * plane + zl;
+#pragma unroll
+                    for (int y = 0; y < N; ++y) d[y] = b[y * N];
+                    double2 ra[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) ra[i] = a[i * N];
+#pragma unroll
+                    for (int y0 = 0; y0 < N; y0 += 8) {
+                        double2 na[8];
+                        if (y0 + 8 < N) {
+#pragma unroll
+                            for (int i = 0; i < 8; ++i) na[i] = a[(y0 + 8 + i) * N];
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) d[y0 + i] = cconjmul(ra[i], d[y0 + i]);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) ra[i] = na[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int y = 0; y < N; ++y) d[y] = make_double2(0.0, 0.0);
+                }
+                LineDFT<N>::run(d);
+                if (act) {
+                    double2 *q = Q + py * bey * QS + zl;
+#pragma unroll
+                    for (int ky = 0; ky < N; ++ky) {
+                        const int m = ky <= N / 2 ? ky : ky - N;
+                        if (m >= -rey && m <= rey) q[(m + rey) * QS] = d[ky];
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            {
+                const int x = xg + pz;
+                const bool act = pz < G && x < x1;
+                double2 e[N];
+                if (act) {
+                    const double2 *q = Q + (pz * bey + iy) * QS;
+#pragma unroll
+                    for (int z = 0; z < N; ++z) e[z] = q[z];
+                } else {
+#pragma unroll
+                    for (int z = 0; z < N; ++z) e[z] = make_double2(0.0, 0.0);
+                }
+                LineDFT<N>::run(e);
+                if (act) {
+                    double2 *o = T + ((size_t)tl * n1 + x) * nbox + iy;
+#pragma unroll
+                    for (int kz = 0; kz < N; ++kz) {
+                        const int m = kz <= N / 2 ? kz : kz - N;
+                        if (m >= -rez && m <= rez) o[(m + rez) * bey] = e[kz];
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+}
+
+// Pass B.  T: [npairs][n1][nbox], box point (iy, iz) at iy * ys + iz * zs;
+// sphere points in (mx, my, mz) order (ge_code2),
 // written back in the original order (ge_out).  XS planes staged per round.
 template <int ACC, int NT, int XS>
 __global__ __launch_bounds__(NT) void k_pair_x(const double2 *__restrict__ T, int n1, int nbox, int bez,
                                                const double2 *__restrict__ tw1g, const int *__restrict__ ge_code,
                                                const int *__restrict__ ge_out, int ng, double inv_n,
                                                double2 *__restrict__ M, int nv, int nc, int c0, int ncb,
-                                               long long m_row0) {
+                                               long long m_row0, int ys, int zs) {
     extern __shared__ double2 lds[];
     double2 *tw1 = lds, *Ts = tw1 + n1;  // [XS][nbox]
     for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
@@ -460,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_pair_x(const double2 *__restrict__ T, in
     for (int i = 0; i < ACC; ++i) {
         const int g = threadIdx.x + i * NT;
         const int cd = g < ng ? ge_code[g] : -1;
-        slot[i] = cd >= 0 ? ((cd >> 8) & 0xff) * bez + (cd >> 16) : -1;
+        slot[i] = cd >= 0 ? ((cd >> 8) & 0xff) * ys + (cd >> 16) * zs : -1;
         mxs[i] = cd >= 0 ? (cd & 0xff) : 0;
         ph[i] = 0;
         acc[i] = make_double2(0.0, 0.0);
@@ -750,14 +949,30 @@ int launch_pair_yz_t(const double2 *gv, const double2 *gc, int nkb, int nv, int 
 template <int ACC>
 int launch_pair_x_t(const double2 *T, long long npairs, const AxisPlan &px, int nbox, int bez, const int *ge_code2,
                     const int *ge_out, int ng, double inv_n, double2 *M, int nv, int nc, int c0, int ncb,
-                    long long row0, hipStream_t st) {
+                    long long row0, int ys, int zs, hipStream_t st) {
     constexpr int XS = 8;
     const size_t lds = sizeof(double2) * ((size_t)px.n + (size_t)XS * nbox);
     if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
     auto kern = k_pair_x<ACC, 256, XS>;
     BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)npairs), dim3(256), lds, st, T, px.n, nbox, bez, px.tw, ge_code2, ge_out,
-                       ng, inv_n, M, nv, nc, c0, ncb, row0);
+                       ng, inv_n, M, nv, nc, c0, ncb, row0, ys, zs);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+template <int N, int G, int MINW>
+int launch_pair_yzr_t(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb, int n1,
+                      int rey, int rez, double2 *T, hipStream_t st) {
+    const int bey = 2 * rey + 1;
+    if (bey > N || 2 * rez + 1 > N || G * bey > 64) return BGW_ERR_UNSUPPORTED;
+    const size_t lds = sizeof(double2) * (size_t)G * bey * (N + 1);
+    auto kern = k_pair_yzr<N, G, MINW>;
+    BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int xblk = std::max(G, std::min(n1, 4 * G));
+    const int nxb = (n1 + xblk - 1) / xblk;
+    const long long grid = (long long)nkb * nxb * ncb;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), lds, st, gv, gc, nv, nc, c0, ncb, n1, rey, rez, xblk, T);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
@@ -816,16 +1031,33 @@ int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc
     }
 }
 
+// Pass A with one lane per line (y and z lengths 16, 24 or 32).  T then holds
+// each x-plane's box with iy fastest.  BGW_ERR_UNSUPPORTED when it does not apply.
+int launch_pair_yzr(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
+                    const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
+                    hipStream_t st) {
+    const char *e = std::getenv("BGW_PAIR_YZ_LEGACY");
+    if ((e && *e == '1') || py.n != pz.n) return BGW_ERR_UNSUPPORTED;
+    switch (pz.n) {
+        case 16: return launch_pair_yzr_t<16, 4, 1>(gv, gc, nkb, nv, nc, c0, ncb, px.n, rey, rez, T, st);
+        case 24: return launch_pair_yzr_t<24, 2, 1>(gv, gc, nkb, nv, nc, c0, ncb, px.n, rey, rez, T, st);
+        case 32: return launch_pair_yzr_t<32, 2, 1>(gv, gc, nkb, nv, nc, c0, ncb, px.n, rey, rez, T, st);
+        default: return BGW_ERR_UNSUPPORTED;
+    }
+}
+
+// yfast: T box points stored iy fastest (lane-per-line pass A), else iz fastest.
 int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int rey, int rez, const int *ge_code2,
                   const int *ge_out, int ng, double2 *M, int nv, int nc, int c0, int ncb, long long row0, size_t N,
-                  hipStream_t st) {
-    const int bez = 2 * rez + 1, nbox = (2 * rey + 1) * bez;
+                  bool yfast, hipStream_t st) {
+    const int bez = 2 * rez + 1, bey = 2 * rey + 1, nbox = bey * bez;
+    const int ys = yfast ? 1 : bez, zs = yfast ? bey : 1;
     const double inv_n = 1.0 / (double)N;
     const int per = (ng + 255) / 256;
 #define BGW_PX(A)                                                                                               \
     if (per <= A)                                                                                               \
         return launch_pair_x_t<A>(T, npairs, px, nbox, bez, ge_code2, ge_out, ng, inv_n, M, nv, nc, c0, ncb, row0, \
-                                  st);
+                                  ys, zs, st);
     BGW_PX(1)
     BGW_PX(2)
     BGW_PX(4)
