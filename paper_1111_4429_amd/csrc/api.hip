@@ -29,6 +29,11 @@ int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int 
                      const AxisPlan &, const AxisPlan &, const int *ge_code2, const int *ge_out, int ng, int rey,
                      int rez, double2 *M, long long row0, hipStream_t);
 size_t pair_yz_bytes_per_pair(int n1, int rey, int rez);
+size_t band_lines_bytes(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm,
+                        int nbands);
+bool band_lines_supported(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm);
+int launch_band_lines(const double2 *C, int nbands, int ngw, const AxisPlan &px, const AxisPlan &py,
+                      const AxisPlan &pz, const SphereMaps &sm, double2 *W, double2 *grids, hipStream_t st);
 bool pair_two_pass_supported(const AxisPlan &py, const AxisPlan &pz);
 int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
                    const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
@@ -281,6 +286,30 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
         syz.push_back(mod(kv.first.first, n2) | ((kv.first.second + rwz) << 16));
         syz2.push_back((kv.first.first + rwy) | ((kv.first.second + rwz) << 16));
     }
+    // the same sticks with entries in ascending mx, and the (my, mz) box cells
+    const int bwy_ = 2 * rwy + 1, bwz_ = 2 * rwz + 1;
+    std::vector<int> cell((size_t)bwy_ * bwz_, -1), slo, sgs;
+    bool contiguous = true;
+    int rwx = 0;
+    {
+        int s = 0;
+        for (auto &kv : sticks) {
+            std::vector<std::pair<int, int>> e;
+            for (int g : kv.second) {
+                e.push_back({d->gw[3 * g], g});
+                rwx = std::max(rwx, std::abs(d->gw[3 * g]));
+            }
+            std::sort(e.begin(), e.end());
+            for (size_t i = 0; i < e.size(); ++i) {
+                if (i && e[i].first != e[i - 1].first + 1) contiguous = false;
+                sgs.push_back(e[i].second);
+            }
+            slo.push_back(e.front().first);
+            cell[(size_t)(kv.first.second + rwz) * bwy_ + (kv.first.first + rwy)] = s;
+            ++s;
+        }
+    }
+    if (2 * rwx + 1 > n1 || bwy_ > n2 || bwz_ > pl->box[2]) contiguous = false;
     SphereMaps &sm = pl->sm;
     sm.nstick = (int)syz.size();
     sm.rwz = rwz;
@@ -297,6 +326,14 @@ static int get_plan(bgw_handle_t h, const bgw_pair_desc *d, FFTPlan **out) {
     BGW_TRY(upload(*pl, syz2.data(), sizeof(int) * syz2.size(), &dp));
     sm.stick_yz2 = (const int *)dp;
     sm.rwy = rwy;
+    sm.ncell = bwy_ * bwz_;
+    sm.sticks_contiguous = contiguous;
+    BGW_TRY(upload(*pl, cell.data(), sizeof(int) * cell.size(), &dp));
+    sm.cell_stick = (const int *)dp;
+    BGW_TRY(upload(*pl, slo.data(), sizeof(int) * slo.size(), &dp));
+    sm.st_lo = (const int *)dp;
+    BGW_TRY(upload(*pl, sgs.data(), sizeof(int) * sgs.size(), &dp));
+    sm.st_gs = (const int *)dp;
     int rez = 0, rey = 0;
     for (int g = 0; g < d->ng; ++g) {
         rez = std::max(rez, std::abs(d->ge[3 * g + 2]));
@@ -409,13 +446,19 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
         ncb = (int)std::max<size_t>(1, std::min<size_t>((size_t)d->nc, t_cap / (t_per_pair * d->nv)));
     }
     const size_t t_bytes_for = two_pass ? t_per_pair * (size_t)d->nv * ncb : 0;  // per k in the batch
-    int kb = (int)std::min<size_t>((size_t)d->nk, budget / (per_k + t_bytes_for + 1));
+    // x-stick results of the lane-per-line band path, reused by the valence and conduction launches
+    const bool band_lines = !generic_fft() && band_lines_supported(px, py, pz, pl->sm);
+    const size_t w_per_k = band_lines ? band_lines_bytes(px, py, pz, pl->sm, std::max(d->nv, d->nc)) : 0;
+    int kb = (int)std::min<size_t>((size_t)d->nk, budget / (per_k + t_bytes_for + w_per_k + 1));
     if (kb < 1) return fail(BGW_ERR_NOMEM, "workspace for one k-point of band grids does not fit");
     if (two_pass) kb = (int)std::min<size_t>((size_t)kb, std::max<size_t>(1, t_cap / (t_per_pair * d->nv * ncb)));
     const size_t grid_bytes = per_k * kb;
-    BGW_TRY(ensure_ws(h, grid_bytes + (two_pass ? t_bytes_for * kb + 256 : 0), st));
+    const size_t t_off = ((grid_bytes + 255) / 256) * 256;
+    const size_t w_off = t_off + ((two_pass ? t_bytes_for * kb : 0) + 255) / 256 * 256;
+    BGW_TRY(ensure_ws(h, w_off + w_per_k * kb, st));
     double2 *gv = (double2 *)h->ws.p;
-    double2 *T = (double2 *)((char *)h->ws.p + ((grid_bytes + 255) / 256) * 256);
+    double2 *T = (double2 *)((char *)h->ws.p + t_off);
+    double2 *Wb = (double2 *)((char *)h->ws.p + w_off);
     const double2 *cv = (const double2 *)d->cv, *cc = (const double2 *)d->cc;
     for (int k0 = 0; k0 < d->nk; k0 += kb) {
         const int kn = std::min(kb, d->nk - k0);
@@ -423,14 +466,20 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
         {
             Timed tm(h, BGW_KERNEL_BAND, st);
             const double2 *cvk = cv + (size_t)k0 * d->nv * d->ngw, *cck = cc + (size_t)k0 * d->nc * d->ngw;
-            int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
-                                   : launch_band_to_real2(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gv, st);
-            if (rc == BGW_ERR_UNSUPPORTED) {
-                BGW_TRY(launch_band_to_real(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, lcb, gv, st));
-                BGW_TRY(launch_band_to_real(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, lcb, gc, st));
+            if (band_lines) {
+                BGW_TRY(launch_band_lines(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, Wb, gv, st));
+                BGW_TRY(launch_band_lines(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, Wb, gc, st));
             } else {
-                BGW_TRY(rc);
-                BGW_TRY(launch_band_to_real2(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gc, st));
+                int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
+                                       : launch_band_to_real2(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, pl->sm.rwy,
+                                                              gv, st);
+                if (rc == BGW_ERR_UNSUPPORTED) {
+                    BGW_TRY(launch_band_to_real(cvk, kn * d->nv, d->ngw, px, py, pz, pl->sm, lcb, gv, st));
+                    BGW_TRY(launch_band_to_real(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, lcb, gc, st));
+                } else {
+                    BGW_TRY(rc);
+                    BGW_TRY(launch_band_to_real2(cck, kn * d->nc, d->ngw, px, py, pz, pl->sm, pl->sm.rwy, gc, st));
+                }
             }
         }
         const long long row0 = (long long)k0 * d->nv * d->nc;

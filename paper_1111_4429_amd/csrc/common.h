@@ -76,6 +76,14 @@ struct SphereMaps {
     const int *ge_out;     // original index of the p-th point of that order
     int bez, rez;          // dielectric box extent along z, Rez
     int rey;               // dielectric box half-extent along y
+    // lane-per-line band path (x-sticks contiguous in mx): cell c = iz * bwy + iy
+    // of the (my, mz) box holds stick cell_stick[c] (-1: none); stick s has
+    // entries st_gs[stick_start[s] .. stick_start[s+1]) in ascending mx from st_lo[s]
+    int ncell;
+    const int *cell_stick;
+    const int *st_lo;
+    const int *st_gs;
+    bool sticks_contiguous;
 };
 
 // Workspace carve-up of the split-precision chi sum (split.hip).

@@ -869,6 +869,106 @@ __global__ __launch_bounds__(NT) void k_band_to_real3(const double2 *__restrict_
     }
 }
 
+// Two-pass band transform for cubic boxes of side N = 16, 24 or 32 (the
+// inverse direction of the pair passes).
+// Pass X (k_band_x): lane = (band, box cell (iy, iz)).  The cell's x-stick
+// holds consecutive mx; each is placed at register mx mod N (zero elsewhere)
+// and the whole N-point DFT along x runs in registers.  The N results go to
+// W[band][x][iz][iy] (iy fastest; cells without a stick get zeros).
+template <int N>
+__global__ __launch_bounds__(256) void k_band_x(const double2 *__restrict__ C, int ngw, SphereMaps sm,
+                                                double2 *__restrict__ W) {
+    const int cell = blockIdx.x * 256 + threadIdx.x;
+    const int band = blockIdx.y;
+    if (cell >= sm.ncell) return;
+    const int s = sm.cell_stick[cell];
+    int base = 0, cnt = 0, lo = 0;
+    if (s >= 0) {
+        base = sm.stick_start[s];
+        cnt = sm.stick_start[s + 1] - base;
+        lo = sm.st_lo[s];
+    }
+    const double2 *cb = C + (size_t)band * ngw;
+    double2 d[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const int j = (k <= N / 2 ? k : k - N) - lo;
+        d[k] = (j >= 0 && j < cnt) ? cb[sm.st_gs[base + j]] : make_double2(0.0, 0.0);
+    }
+    LineDFT<N>::run(d);
+    double2 *o = W + (size_t)band * N * sm.ncell + cell;
+#pragma unroll
+    for (int x = 0; x < N; ++x) o[(size_t)x * sm.ncell] = d[x];
+}
+
+// Pass YZ (k_band_yz): one wavefront per workgroup = (band, block of
+// x-planes), G planes per round.
+//   z: lane (plane p, iy) reads the bwz values W[band][x][.][iy] (coalesced
+//      over iy), places them at registers mz mod N, does the N-point DFT and
+//      stores the row to Q[p][iy][.] in LDS;
+//   y: lane (plane p, z) reads the bwy values Q[p][.][z], places them at my
+//      mod N, does the N-point DFT and stores u[band][x][y][z] for all y
+//      (coalesced over z).
+template <int N, int G>
+__global__ __launch_bounds__(64) void k_band_yz(const double2 *__restrict__ W, int ncell, int rwy, int rwz, int xblk,
+                                                double2 *__restrict__ grids) {
+    constexpr int QS = N + 1;
+    extern __shared__ double2 Q[];  // [G][bwy][QS]
+    const int lane = threadIdx.x;
+    const int bwy = 2 * rwy + 1;
+    const int nxb = (N + xblk - 1) / xblk;
+    const int band = blockIdx.x / nxb;
+    const int xb = blockIdx.x - band * nxb;
+    const int x0 = xb * xblk, x1 = min(N, x0 + xblk);
+    const double2 *wb = W + (size_t)band * N * ncell;
+    double2 *ob = grids + (size_t)band * N * N * N;
+    const int pz = lane / bwy, iy = lane - pz * bwy;  // z-stage role
+    const int py = lane / N, zl = lane - py * N;      // y-stage role
+#pragma unroll 1
+    for (int xg = x0; xg < x1; xg += G) {
+        {
+            const int x = xg + pz;
+            const bool act = pz < G && x < x1;
+            const double2 *w = wb + (size_t)x * ncell + iy;
+            double2 d[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int m = k <= N / 2 ? k : k - N;
+                d[k] = (act && m >= -rwz && m <= rwz) ? w[(m + rwz) * bwy] : make_double2(0.0, 0.0);
+            }
+            LineDFT<N>::run(d);
+            if (act) {
+                double2 *q = Q + (pz * bwy + iy) * QS;
+#pragma unroll
+                for (int z = 0; z < N; ++z) q[z] = d[z];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        {
+            const int x = xg + py;
+            const bool act = py < G && x < x1;
+            const double2 *q = Q + py * bwy * QS + zl;
+            double2 e[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int m = k <= N / 2 ? k : k - N;
+                e[k] = (act && m >= -rwy && m <= rwy) ? q[(m + rwy) * QS] : make_double2(0.0, 0.0);
+            }
+            LineDFT<N>::run(e);
+            if (act) {
+                double2 *o = ob + (size_t)x * N * N + zl;
+#pragma unroll
+                for (int y = 0; y < N; ++y) o[y * N] = e[y];
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // ------------------------------------------------------------------ host side
 
 namespace {
@@ -1160,6 +1260,55 @@ int launch_band_to_real2(const double2 *C, int nbands, int ngw, const AxisPlan &
     }
     BGW_HIP(hipGetLastError());
     return BGW_OK;
+}
+
+// Band transform by the two lane-per-line passes when the box is a cube of
+// side 16, 24 or 32 and every x-stick is contiguous in mx; W must hold
+// sizeof(double2) * nbands * N * ncell bytes.  BGW_ERR_UNSUPPORTED (nothing
+// launched) otherwise.
+size_t band_lines_bytes(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm,
+                        int nbands) {
+    return sizeof(double2) * (size_t)nbands * px.n * sm.ncell;
+}
+
+bool band_lines_supported(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm) {
+    const char *e = std::getenv("BGW_BAND_LEGACY");
+    if (e && *e == '1') return false;
+    if (px.n != py.n || py.n != pz.n || !sm.sticks_contiguous) return false;
+    const int n = pz.n, G = n == 16 ? 4 : 2;
+    return (n == 16 || n == 24 || n == 32) && G * (2 * sm.rwy + 1) <= 64;
+}
+
+namespace {
+template <int N, int G>
+int launch_band_lines_t(const double2 *C, int nbands, int ngw, const SphereMaps &sm, double2 *W, double2 *grids,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_band_x<N>, dim3((unsigned)((sm.ncell + 255) / 256), (unsigned)nbands), dim3(256), 0, st, C,
+                       ngw, sm, W);
+    BGW_HIP(hipGetLastError());
+    const int bwy = 2 * sm.rwy + 1;
+    const size_t lds = sizeof(double2) * (size_t)G * bwy * (N + 1);
+    auto kern = k_band_yz<N, G>;
+    BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int xblk = 4 * G;
+    const int nxb = (N + xblk - 1) / xblk;
+    hipLaunchKernelGGL(kern, dim3((unsigned)((long long)nbands * nxb)), dim3(64), lds, st, W, sm.ncell, sm.rwy,
+                       sm.rwz, xblk, grids);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+}  // namespace
+
+int launch_band_lines(const double2 *C, int nbands, int ngw, const AxisPlan &px, const AxisPlan &py,
+                      const AxisPlan &pz, const SphereMaps &sm, double2 *W, double2 *grids, hipStream_t st) {
+    if (nbands <= 0) return BGW_OK;
+    if (!band_lines_supported(px, py, pz, sm)) return BGW_ERR_UNSUPPORTED;
+    switch (pz.n) {
+        case 16: return launch_band_lines_t<16, 4>(C, nbands, ngw, sm, W, grids, st);
+        case 24: return launch_band_lines_t<24, 2>(C, nbands, ngw, sm, W, grids, st);
+        case 32: return launch_band_lines_t<32, 2>(C, nbands, ngw, sm, W, grids, st);
+        default: return BGW_ERR_UNSUPPORTED;
+    }
 }
 
 }  // namespace bgw
