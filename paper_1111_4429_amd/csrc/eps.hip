@@ -22,6 +22,10 @@
 //
 // Barrier waits are bounded: a wait that exceeds its spin budget stores
 // info = -1000 for that matrix and gives up, so the kernel always terminates.
+#include <cstdlib>
+#include <cstring>
+#include <utility>
+
 #include "common.h"
 
 namespace bgw {
@@ -410,8 +414,8 @@ __global__ __launch_bounds__(256) void k_gje_panel_reg(double2 *__restrict__ A, 
 
 // For every column outside the panel: apply the panel's row interchanges in
 // order, copy the panel rows to Rs [nb][n - nb] and zero them in A.
-__global__ void k_gje_swap_save(double2 *__restrict__ A, int n, int k, int nb, const int *__restrict__ ipiv,
-                                double2 *__restrict__ Rs) {
+__global__ __launch_bounds__(64) void k_gje_swap_save(double2 *__restrict__ A, int n, int k, int nb,
+                                                      const int *__restrict__ ipiv, double2 *__restrict__ Rs) {
     const int mat = blockIdx.y;
     double2 *Am = A + (size_t)mat * n * n;
     const int *ip = ipiv + (size_t)mat * n;
@@ -454,6 +458,21 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
     const int I0 = blockIdx.x * UT, C0 = blockIdx.y * UT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
+
+    // this lane's elements of the output tile, fetched first so that their
+    // latency overlaps the staging of P and R
+    double2 old[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
+                const int cp = C0 + wc * 32 + 16 * b + li;
+                old[a][b][r] = make_double2(0.0, 0.0);
+                if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + (cp < k ? cp : cp + nb)];
+            }
 
     for (int e = tid; e < UT * kPanelMax; e += 256) {
         const int i = e / kPanelMax, j = e % kPanelMax;  // P tile: row i, panel col j
@@ -511,9 +530,8 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
                 const int cp = C0 + wc * 32 + 16 * b + li;
                 if (i < n && cp < m) {
                     const int c = cp < k ? cp : cp + nb;
-                    double2 *dst = Am + (size_t)i * n + c;
-                    const double2 old = *dst;
-                    *dst = make_double2(old.x + cre[a][b][r], old.y + cim[a][b][r]);
+                    Am[(size_t)i * n + c] =
+                        make_double2(old[a][b][r].x + cre[a][b][r], old[a][b][r].y + cim[a][b][r]);
                 }
             }
 }
@@ -550,6 +568,217 @@ __global__ void k_gje_colperm(double2 *__restrict__ A, int n, const int *__restr
     for (int c = threadIdx.x; c < n; c += blockDim.x) row[c] = a[c];
     __syncthreads();
     for (int c = threadIdx.x; c < n; c += blockDim.x) a[c] = row[id[c]];
+}
+
+// ------------------------------------------------------- one-workgroup panels
+//
+// Matrices with n <= kWgThreads * kWgMaxRows take their panels from one
+// workgroup each: thread t holds the panel rows that start at positions
+// t, t + 512, t + 1024 (panel width kWgNb) in registers, so a column step needs
+// two workgroup barriers and no grid barrier.  The column steps are those of
+// k_gje_panel: pivot = largest |Re|+|Im| among positions >= col (first
+// position on ties), positions col and p exchanged, every other row
+// eliminated, the pivot row scaled.  A row stays in its thread's registers;
+// an interchange only swaps the positions recorded for the two rows, and each
+// row is stored at its final position when the panel ends.
+constexpr int kWgNb = 16;
+constexpr int kWgThreads = 512;
+constexpr int kWgMaxRows = 3;
+
+namespace {
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &key) {
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int ok = __builtin_amdgcn_mov_dpp(key, CTRL, 0xF, 0xF, false);
+    const double ov = __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    if (ov > v || (ov == v && ok < key)) {
+        v = ov;
+        key = ok;
+    }
+}
+
+// Largest v over the wavefront, smallest key on ties; every lane gets the
+// result.  Quad swaps and the half-row and row mirrors agree the 16 lanes of
+// each row, then the four rows are compared.
+__device__ __forceinline__ void wave_argmax_dpp(double &v, int &key) {
+    argmax_dpp<0xB1>(v, key);   // quad_perm [1,0,3,2]
+    argmax_dpp<0x4E>(v, key);   // quad_perm [2,3,0,1]
+    argmax_dpp<0x141>(v, key);  // row_half_mirror
+    argmax_dpp<0x140>(v, key);  // row_mirror
+    const unsigned long long b = __double_as_longlong(v);
+    double bv = 0.0;
+    int bk = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int lo = __builtin_amdgcn_readlane((int)(unsigned)b, 16 * r);
+        const int hi = __builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 16 * r);
+        const int kk = __builtin_amdgcn_readlane(key, 16 * r);
+        const double x = __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+        if (r == 0 || x > bv || (x == bv && kk < bk)) {
+            bv = x;
+            bk = kk;
+        }
+    }
+    v = bv;
+    key = bk;
+}
+}  // namespace
+
+struct WgLds {
+    double wv[kWgThreads / 64];
+    int wk[kWgThreads / 64];
+    double2 praw[kWgNb];
+};
+
+// Column step J (compile-time, so every row element keeps a fixed register).
+// pos[r]: current position of row r of this thread (>= n: padding row of zeros).
+template <int ROWS, int J>
+__device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
+                                              int nb, int *ip, int *info) {
+    constexpr int NW = kWgThreads / 64;
+    if (J >= nb) return;  // uniform
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = k + J;
+    // candidate of this thread, then of the wavefront, then of the workgroup
+    double best = -1.0;
+    int key = 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        if (pos[r] >= col && pos[r] < n) {
+            const double v = cabs1(rv[r][J]);
+            if (v > best || (v == best && pos[r] < key)) {
+                best = v;
+                key = pos[r];
+            }
+        }
+    }
+    wave_argmax_dpp(best, key);
+    if (lane == 0) {
+        L.wv[wave] = best;
+        L.wk[wave] = key;
+    }
+    __syncthreads();
+    double bv = L.wv[0];
+    int p = L.wk[0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+        if (L.wv[w] > bv || (L.wv[w] == bv && L.wk[w] < p)) {
+            bv = L.wv[w];
+            p = L.wk[w];
+        }
+    // p >= col always (position col itself is a candidate)
+    int piv_r = -1;  // which of this thread's rows is the pivot row
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+        if (pos[r] == p) piv_r = r;
+    if (piv_r >= 0) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+            if (r == piv_r) {
+#pragma unroll
+                for (int c = 0; c < kWgNb; ++c) L.praw[c] = rv[r][c];
+            }
+    }
+    if (tid == 0) {
+        ip[col] = p;
+        if (bv <= 0.0) atomicCAS(info, 0, col + 1);
+    }
+    // interchange of positions col and p
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) pos[r] = pos[r] == p ? col : (pos[r] == col ? p : pos[r]);
+    __syncthreads();
+    double2 piv = L.praw[J];
+    if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
+    const double2 ipv = cdiv(make_double2(1.0, 0.0), piv);
+    // every row is eliminated with the pivot row, read from LDS once per
+    // column element by element (padding rows hold zeros and stay zero);
+    // the pivot row's own result is replaced below
+    double2 fs[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) fs[r] = cmul(rv[r][J], ipv);
+#pragma unroll
+    for (int c = 0; c < kWgNb; ++c) {
+        const double2 pc = L.praw[c];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+            rv[r][c] = c == J ? make_double2(-fs[r].x, -fs[r].y) : csub(rv[r][c], cmul(fs[r], pc));
+        __builtin_amdgcn_sched_barrier(0);  // keeps the pivot-row reads from piling up in registers
+    }
+    if (piv_r >= 0) {  // the pivot row, now at position col, becomes the scaled pivot row
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r)
+            if (r == piv_r) {
+#pragma unroll
+                for (int c = 0; c < kWgNb; ++c) rv[r][c] = c == J ? ipv : cmul(L.praw[c], ipv);
+            }
+    }
+    // the next step writes praw only after its first barrier, which every
+    // thread reaches after these reads
+}
+
+template <int ROWS, int... Js>
+__device__ __forceinline__ void gje_wg_columns(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
+                                               int nb, int *ip, int *info, std::integer_sequence<int, Js...>) {
+    (gje_wg_column<ROWS, Js>(rv, pos, L, n, k, nb, ip, info), ...);
+}
+
+// One workgroup per matrix (blockIdx.x), panel columns [k, k + nb), nb <= kWgNb.
+// The panel moves between A and the registers through an LDS stage of 512
+// rows (row stride kWgNb + 1 elements, conflict-free row reads), so the
+// global accesses are whole 256-byte row segments.
+constexpr int kWgStageLd = kWgNb + 1;
+constexpr size_t kWgStageBytes = sizeof(double2) * kWgThreads * kWgStageLd;
+
+template <int ROWS>
+__global__ __launch_bounds__(kWgThreads) void k_gje_panel_wg(double2 *__restrict__ A, int n, int k, int nb,
+                                                             int *__restrict__ ipiv, int *__restrict__ info) {
+    __shared__ WgLds L;
+    extern __shared__ double2 wg_stage[];  // [kWgThreads][kWgStageLd]
+    const int mat = blockIdx.x;
+    double2 *Am = A + (size_t)mat * n * n;
+    const int tid = threadIdx.x;
+    double2 rv[ROWS][kWgNb];
+    int pos[ROWS];
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int r0 = r * kWgThreads;
+        const int cnt = min(kWgThreads, n - r0);  // >= 1
+        pos[r] = r0 + tid;
+#pragma unroll 4
+        for (int it = 0; it < kWgNb; ++it) {
+            const int e = tid + it * kWgThreads, i = e / kWgNb, c = e % kWgNb;
+            if (i < cnt)
+                wg_stage[i * kWgStageLd + c] = c < nb ? Am[(size_t)(r0 + i) * n + k + c] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < kWgNb; ++c) rv[r][c] = tid < cnt ? wg_stage[tid * kWgStageLd + c] : make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+    gje_wg_columns<ROWS>(rv, pos, L, n, k, nb, ipiv + (size_t)mat * n, info + mat,
+                         std::make_integer_sequence<int, kWgNb>{});
+    // every row to its final position, one 512-position block at a time
+#pragma unroll
+    for (int b = 0; b < ROWS; ++b) {
+        const int r0 = b * kWgThreads;
+        const int cnt = min(kWgThreads, n - r0);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            if (pos[r] >= r0 && pos[r] < r0 + cnt) {
+#pragma unroll
+                for (int c = 0; c < kWgNb; ++c) wg_stage[(pos[r] - r0) * kWgStageLd + c] = rv[r][c];
+            }
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int it = 0; it < kWgNb; ++it) {
+            const int e = tid + it * kWgThreads, i = e / kWgNb, c = e % kWgNb;
+            if (i < cnt && c < nb) Am[(size_t)(r0 + i) * n + k + c] = wg_stage[i * kWgStageLd + c];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -591,6 +820,39 @@ static size_t gje_panel_reg_lds(int R) { return sizeof(double2) * (kPanelMax + (
 // matrix keep the per-column grid barrier cheap
 int gje_rows_per_wg(int n) { return std::min(256, n); }
 
+// One workgroup per matrix panel for n <= 1536, unless BGW_GJE_PATH=coop asks
+// for the cooperative multi-workgroup panels.
+static bool gje_one_wg(int n) {
+    if (n > kWgThreads * kWgMaxRows) return false;
+    const char *e = std::getenv("BGW_GJE_PATH");
+    return !(e && std::strcmp(e, "coop") == 0);
+}
+
+static int launch_gje_invert_wg(double2 *A, int n, int nmat, int *ipiv, int *info, double2 *Rs, hipStream_t st) {
+    const int rows = (n + kWgThreads - 1) / kWgThreads;
+    const void *kern = rows == 1 ? (const void *)k_gje_panel_wg<1>
+                     : rows == 2 ? (const void *)k_gje_panel_wg<2>
+                                 : (const void *)k_gje_panel_wg<3>;
+    BGW_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWgStageBytes));
+    for (int k = 0; k < n; k += kWgNb) {
+        const int nb = std::min(kWgNb, n - k);
+        void *args[] = {&A, (void *)&n, &k, (void *)&nb, &ipiv, &info};
+        BGW_HIP(hipLaunchKernel(kern, dim3(nmat), dim3(kWgThreads), args, kWgStageBytes, st));
+        const int m = n - nb;
+        if (m > 0) {
+            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 63) / 64, nmat), dim3(64), 0, st, A, n, k, nb, ipiv, Rs);
+            hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n,
+                               k, nb, Rs);
+        }
+        BGW_HIP(hipGetLastError());
+    }
+    return BGW_OK;
+}
+
+static int launch_gje_invert_coop(double2 *A, int n, int nmat, int *info, GjeScratch sc, double2 *Rs, int *ipiv,
+                                  int rows, int R, hipStream_t st);
+static int launch_gje_unpermute(double2 *A, int n, int nmat, const int *ipiv, int *idx, hipStream_t st);
+
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t st) {
     const int rows = gje_rows_per_wg(n);
     const int R = (n + rows - 1) / rows;
@@ -609,6 +871,16 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (unsigned int *)info, (size_t)nmat, 0u);
     BGW_HIP(hipGetLastError());
 
+    if (gje_one_wg(n)) {
+        BGW_TRY(launch_gje_invert_wg(A, n, nmat, ipiv, info, Rs, st));
+    } else {
+        BGW_TRY(launch_gje_invert_coop(A, n, nmat, info, sc, Rs, ipiv, rows, R, st));
+    }
+    return launch_gje_unpermute(A, n, nmat, ipiv, idx, st);
+}
+
+static int launch_gje_invert_coop(double2 *A, int n, int nmat, int *info, GjeScratch sc, double2 *Rs, int *ipiv,
+                                  int rows, int R, hipStream_t st) {
     if (R > kGjeMaxR) return BGW_ERR_UNSUPPORTED;
     const size_t lds = gje_panel_lds(rows, R);
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<kPanelMax>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -629,12 +901,16 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
         bar_done += nb;
         const int m = n - nb;
         if (m > 0) {
-            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 255) / 256, nmat), dim3(256), 0, st, A, n, k, nb, ipiv, Rs);
+            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 63) / 64, nmat), dim3(64), 0, st, A, n, k, nb, ipiv, Rs);
             hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n,
                                k, nb, Rs);
             BGW_HIP(hipGetLastError());
         }
     }
+    return BGW_OK;
+}
+
+static int launch_gje_unpermute(double2 *A, int n, int nmat, const int *ipiv, int *idx, hipStream_t st) {
     const size_t plds = sizeof(int) * 2 * (size_t)n;
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_perm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
     hipLaunchKernelGGL(k_gje_perm, dim3(nmat), dim3(256), plds, st, ipiv, n, idx);
@@ -645,8 +921,11 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     return BGW_OK;
 }
 
-// Largest group of matrices whose panel workgroups can be co-resident.
+// Largest group of matrices inverted together: for cooperative panels, the
+// matrices whose panel workgroups can be co-resident; one-workgroup panels
+// need no co-residency (the cap bounds the workspace).
 int gje_max_group(int n) {
+    if (gje_one_wg(n)) return 64;
     const int rows = gje_rows_per_wg(n);
     const int R = (n + rows - 1) / rows;
     const size_t lds = gje_panel_lds(rows, R);

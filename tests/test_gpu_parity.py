@@ -373,6 +373,30 @@ def test_eps_inv_pivoting_and_batch(torch_dev, handle):
         assert rel(einv[i], ref[i]) <= TOL
 
 
+@pytest.mark.parametrize("n,path", [(16, "wg"), (513, "wg"), (513, "coop"), (1100, "wg"), (1536, "wg"),
+                                    (1536, "coop"), (1537, "wg")])
+def test_eps_inv_panel_paths(torch_dev, handle, n, path, monkeypatch):
+    """Both panel paths (one workgroup per matrix up to n = 1536, cooperative
+    workgroups above or on request) on a random eps that needs row
+    interchanges, with ragged last panels, two matrices per call."""
+    if path == "coop":
+        monkeypatch.setenv("BGW_GJE_PATH", "coop")
+    rng = np.random.default_rng(1000 + n)
+    eps = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    v = rng.uniform(0.5, 2.0, n)
+    chi = (np.eye(n)[None] - eps) / v[None, :, None]  # eps = 1 - v chi
+    einv, info = handle.eps_inv(dev(torch_dev, v), dev(torch_dev, chi))
+    einv = einv.cpu().numpy()
+    assert np.all(info.cpu().numpy() == 0)
+    ref, rinfo = oracle.eps_inv(v, chi)
+    assert np.all(rinfo == 0)
+    for i in range(2):
+        # random eps: cond up to ~5e3 at these sizes, so two backward-stable
+        # inverses differ by up to cond * 1.1e-16 * sqrt(n) ~ 2e-11
+        assert rel(einv[i], ref[i]) <= 2e-11
+        assert np.linalg.norm(eps[i] @ einv[i] - np.eye(n)) / np.sqrt(n) <= 2e-11
+
+
 def test_eps_inv_singular_info(torch_dev, handle):
     """eps with an exactly zero pivot: info = 1-based index, other frequencies fine."""
     n = 70
