@@ -8,17 +8,17 @@
 // value is written as four signed base-256 digits:
 //     x = 2^(e-8) (d1 + d2 2^-8 + d3 2^-16 + d4 2^-24 + r),  |d1| <= 256,
 //     |d2|,|d3|,|d4| <= 128, |r| <= 2^-25,
-// all exact in BF16.  Stored slices: d1, d2, d3, d3*2^-8, d4*2^-8.
+// all exact in BF16.  Stored slices: d1, d2, d3, d4 (8 bytes per value).
 //
-// Products (k_herk_split), grouped by weight 2^-8p:
+// Products (k_herk_split), grouped by weight 2^-8p, one FP32 sum per group:
 //     p = 0: a1 b1                                   (FP32-exact: |sum| <= 2^24)
 //     p = 1: a1 b2 + a2 b1                           (FP32-exact: |sum| <= 2^24)
-//     p = 2,3 together, pre-scaled: a1 b3 + a2 b2 + a3 b1
-//                       + a1 b4' + a2 b3' + a3' b2 + a4' b1
-// Ten BF16 MFMA products per (Re, Im); at each chunk end the three FP32 sums
+//     p = 2: a1 b3 + a2 b2 + a3 b1                   (rounded at 2^-24 of the group)
+//     p = 3: a1 b4 + a2 b3 + a3 b2 + a4 b1
+// Ten BF16 MFMA products per (Re, Im); at each chunk end the four FP32 sums
 // are combined in FP64 with the chunk scales 2^(eA + eB - 16) and added to
 // FP64 accumulators.  Terms with weight <= 2^-32 are dropped; the rounding of
-// the third group is at 2^-40.  Expected relative error ~1e-10.
+// the last two groups is at 2^-40 and below.  Expected relative error ~1e-10.
 //
 // The head row/column (G = 0) is recomputed in FP64 from M (k_headwing)
 // because v(q+G) ~ 1/q^2 amplifies it in epsilon.
@@ -38,7 +38,8 @@ constexpr int SK = 256;      // real contraction rows per exact chunk
 constexpr int SKP = SK / 2;  // pairs per chunk
 constexpr int KS = 32;       // real rows per MFMA k-step (16x16x32)
 constexpr int NKS = SK / KS; // k-steps per chunk
-constexpr int NSL = 5;       // stored slices
+constexpr int NSL = 4;       // stored slices
+constexpr int NGR = 4;       // FP32 product groups
 constexpr int TT = 64;       // output tile (G and G')
 
 __device__ inline double pow2(int e) { return __longlong_as_double((long long)(e + 1023) << 52); }
@@ -129,8 +130,7 @@ __global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__
                     d[0][qq] = bf16_bits_exact(d1);
                     d[1][qq] = bf16_bits_exact(d2);
                     d[2][qq] = bf16_bits_exact(d3);
-                    d[3][qq] = bf16_bits_exact(d3 * 0.00390625);
-                    d[4][qq] = bf16_bits_exact(d4 * 0.00390625);
+                    d[3][qq] = bf16_bits_exact(d4);
                 }
             const size_t dst = (((size_t)chunk * NKS + ks) * gpad + G) * KS + 8 * q;
 #pragma unroll
@@ -168,7 +168,8 @@ __device__ inline uint4 swap_neg(uint4 u) {
 // LDS stage: [side][slice][64 rows][64 B], the four 16-B segments of row r
 // stored in the order seg ^ (r & 3) (conflict-free 16-B fragment reads).
 constexpr int SLICE_LDS = TT * KS * 2;          // 4096 B
-constexpr int STAGE_LDS = 2 * NSL * SLICE_LDS;  // 40960 B
+constexpr int STAGE_LDS = 2 * NSL * SLICE_LDS;  // 32768 B
+constexpr int PIECES = 2 * NSL * 4 / 8;         // 1-KB pieces of a stage per wave
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -179,14 +180,15 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int HT = 512;  // threads per block
 
 struct HerkAcc {
-    float4_t g[3][2][2];        // [group][re/im][a]
+    float4_t g[NGR][2][2];      // [group][re/im][a]
     double re[2][4], im[2][4];  // FP64 sums of the chunks done so far
 };
 
 constexpr int NSTAGE = 4;  // LDS stages: k-steps are loaded NSTAGE - 1 ahead
 
-// vmcnt(n) alone (expcnt and lgkmcnt left at their maxima)
-#define BGW_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x0F70 | (n))
+// vmcnt(n) alone (expcnt and lgkmcnt left at their maxima); vmcnt is split
+// over bits 3:0 and 15:14 of the immediate
+#define BGW_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x0F70 | ((n) & 0xF) | (((n) >> 4) << 14))
 
 // Workgroup barrier for the stage pipeline: the wave's LDS reads are complete
 // (lgkmcnt) and its direct-to-LDS loads have been waited for explicitly, so no
@@ -195,18 +197,18 @@ constexpr int NSTAGE = 4;  // LDS stages: k-steps are loaded NSTAGE - 1 ahead
 __device__ __forceinline__ void stage_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Copy k-step `step` of the A (rows G0..) and B (rows H0..) slices into a
-// stage with direct global->LDS loads.  The stage is 40 pieces of 1 KB
-// (slice-side q/4, rows 16 (q%4) .. +16); wave w issues pieces 5w .. 5w+4,
+// stage with direct global->LDS loads.  The stage is 32 pieces of 1 KB
+// (slice-side q/4, rows 16 (q%4) .. +16); wave w issues pieces 4w .. 4w+3,
 // lane L the 16 B of row 16 (q%4) + L/4 at stored segment L%4.  Addresses: a
 // wave-uniform base plus this lane's 32-bit byte offset.
 __device__ __forceinline__ void herk_issue(unsigned char *stage, const unsigned short *SA,
-                                           const unsigned short *SB, const unsigned (&off)[5],
+                                           const unsigned short *SB, const unsigned (&off)[PIECES],
                                            size_t slice_stride, long long step, int gpad, int wave) {
     const size_t so = (size_t)step * gpad * KS;
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const int q = 5 * wave + i;
-        const int idx = q >> 2;  // 0..4: A slices, 5..9: B slices
+    for (int i = 0; i < PIECES; ++i) {
+        const int q = PIECES * wave + i;
+        const int idx = q >> 2;  // 0..3: A slices, 4..7: B slices
         const unsigned short *base = idx < NSL ? SA + idx * slice_stride : SB + (idx - NSL) * slice_stride;
         __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const char *>(base + so) + off[i]),
                                          (lds_void_t *)(stage + idx * SLICE_LDS + (q & 3) * 1024), 16, 0, 0);
@@ -217,7 +219,7 @@ __device__ __forceinline__ uint4 frag(const unsigned char *slice, int row, int l
     return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
 }
 
-// The wave's fragments of one k-step: 5 slices of the B column block and of
+// The wave's fragments of one k-step: the slices of the B column block and of
 // the two A row blocks.
 struct HerkFrags {
     uint4 b[NSL], a[2][NSL];
@@ -236,19 +238,19 @@ __device__ __forceinline__ void herk_frags(const unsigned char *stage, HerkFrags
 
 // Ten BF16 products per (Re, Im) for the wave's 32 x 16 block of one k-step.
 __device__ __forceinline__ void herk_mfma(const HerkFrags &f, HerkAcc &acc) {
-    // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d3', 4 = d4'
+    // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d4
     const bf16x8_t b1 = as_bf16x8(f.b[0]), b2 = as_bf16x8(f.b[1]), b3 = as_bf16x8(f.b[2]);
-    const bf16x8_t b3p = as_bf16x8(f.b[3]), b4p = as_bf16x8(f.b[4]);
+    const bf16x8_t b4 = as_bf16x8(f.b[3]);
     const bf16x8_t y1 = as_bf16x8(swap_neg(f.b[0])), y2 = as_bf16x8(swap_neg(f.b[1]));
-    const bf16x8_t y3 = as_bf16x8(swap_neg(f.b[2])), y3p = as_bf16x8(swap_neg(f.b[3]));
-    const bf16x8_t y4p = as_bf16x8(swap_neg(f.b[4]));
+    const bf16x8_t y3 = as_bf16x8(swap_neg(f.b[2])), y4 = as_bf16x8(swap_neg(f.b[3]));
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const bf16x8_t a1 = as_bf16x8(f.a[a][0]), a2 = as_bf16x8(f.a[a][1]), a3 = as_bf16x8(f.a[a][2]);
-        const bf16x8_t a3p = as_bf16x8(f.a[a][3]), a4p = as_bf16x8(f.a[a][4]);
+        const bf16x8_t a4 = as_bf16x8(f.a[a][3]);
         float4_t(&g0)[2][2] = acc.g[0];
         float4_t(&g1)[2][2] = acc.g[1];
         float4_t(&g2)[2][2] = acc.g[2];
+        float4_t(&g3)[2][2] = acc.g[3];
         g0[0][a] = MFMA(a1, b1, g0[0][a]);
         g0[1][a] = MFMA(a1, y1, g0[1][a]);
         g1[0][a] = MFMA(a1, b2, g1[0][a]);
@@ -261,14 +263,14 @@ __device__ __forceinline__ void herk_mfma(const HerkFrags &f, HerkAcc &acc) {
         g2[1][a] = MFMA(a2, y2, g2[1][a]);
         g2[0][a] = MFMA(a3, b1, g2[0][a]);
         g2[1][a] = MFMA(a3, y1, g2[1][a]);
-        g2[0][a] = MFMA(a1, b4p, g2[0][a]);
-        g2[1][a] = MFMA(a1, y4p, g2[1][a]);
-        g2[0][a] = MFMA(a2, b3p, g2[0][a]);
-        g2[1][a] = MFMA(a2, y3p, g2[1][a]);
-        g2[0][a] = MFMA(a3p, b2, g2[0][a]);
-        g2[1][a] = MFMA(a3p, y2, g2[1][a]);
-        g2[0][a] = MFMA(a4p, b1, g2[0][a]);
-        g2[1][a] = MFMA(a4p, y1, g2[1][a]);
+        g3[0][a] = MFMA(a1, b4, g3[0][a]);
+        g3[1][a] = MFMA(a1, y4, g3[1][a]);
+        g3[0][a] = MFMA(a2, b3, g3[0][a]);
+        g3[1][a] = MFMA(a2, y3, g3[1][a]);
+        g3[0][a] = MFMA(a3, b2, g3[0][a]);
+        g3[1][a] = MFMA(a3, y2, g3[1][a]);
+        g3[0][a] = MFMA(a4, b1, g3[0][a]);
+        g3[1][a] = MFMA(a4, y1, g3[1][a]);
     }
 }
 
@@ -287,7 +289,7 @@ __device__ __forceinline__ void herk_exp_load(ChunkExp &E, const int *__restrict
         for (int r = 0; r < 4; ++r) E.ea[a][r] = EA[(size_t)ch * gpad + G0 + wr * 32 + 16 * a + 4 * lq + r];
 }
 
-// Chunk end: combine the three FP32 groups in FP64 with the chunk-column
+// Chunk end: combine the four FP32 groups in FP64 with the chunk-column
 // scales into the FP64 accumulators and clear them.  D layout of 16x16x32:
 // lane l, register r -> row 4 (l/16) + r, col l % 16.
 __device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E) {
@@ -296,15 +298,19 @@ __device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double sc = pow2(E.ea[a][r] + E.eb - 16);
-            const double vre = (double)acc.g[0][0][a][r] + (double)acc.g[1][0][a][r] * 0.00390625 +
-                               (double)acc.g[2][0][a][r] * 0.0000152587890625;
-            const double vim = (double)acc.g[0][1][a][r] + (double)acc.g[1][1][a][r] * 0.00390625 +
-                               (double)acc.g[2][1][a][r] * 0.0000152587890625;
+            const double vre = (double)acc.g[0][0][a][r] +
+                               ((double)acc.g[1][0][a][r] +
+                                ((double)acc.g[2][0][a][r] + (double)acc.g[3][0][a][r] * 0.00390625) * 0.00390625) *
+                                   0.00390625;
+            const double vim = (double)acc.g[0][1][a][r] +
+                               ((double)acc.g[1][1][a][r] +
+                                ((double)acc.g[2][1][a][r] + (double)acc.g[3][1][a][r] * 0.00390625) * 0.00390625) *
+                                   0.00390625;
             acc.re[a][r] += vre * sc;
             acc.im[a][r] += vim * sc;
         }
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < NGR; ++p)
 #pragma unroll
             for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
     }
@@ -317,11 +323,11 @@ __device__ __forceinline__ void herk_pipeline(unsigned char *__restrict__ stage0
                                               unsigned char *__restrict__ stage2, unsigned char *__restrict__ stage3,
                                               const unsigned short *__restrict__ SA,
                                               const unsigned short *__restrict__ SB, const int *__restrict__ EA,
-                                              const int *__restrict__ EB, const unsigned (&off)[5],
+                                              const int *__restrict__ EB, const unsigned (&off)[PIECES],
                                               size_t slice_stride, long long s0, long long s1, int gpad, int G0,
                                               int H0, int wave, int wr, int wc, int li, int lq, HerkAcc &acc) {
-    // Each issue is 5 loads per wave.  Before step x+1 is read, the loads of
-    // steps x+2 and x+3 (10, when both were issued) may still be in flight.
+    // Each issue is PIECES loads per wave.  Before step x+1 is read, the loads
+    // of steps x+2 and x+3 (2 PIECES, when both were issued) may be in flight.
     // The fragments of the current step are read before the loads into the
     // free stage are issued, so no wait on those loads is needed for them.
 #define BGW_STEP(cur, nxt_stage, x)                                              \
@@ -333,14 +339,14 @@ __device__ __forceinline__ void herk_pipeline(unsigned char *__restrict__ stage0
         __builtin_amdgcn_sched_barrier(0);                                        \
         herk_mfma(f_, acc);                                                       \
         if (((x) % NKS) == NKS - 1) herk_flush(acc, E);                           \
-        if ((x) + 3 < s1) BGW_WAIT_VM(10);                                        \
+        if ((x) + 3 < s1) BGW_WAIT_VM(2 * PIECES);                                \
         else BGW_WAIT_VM(0);                                                      \
         stage_barrier();                                                          \
     }
     herk_issue(stage0, SA, SB, off, slice_stride, s0, gpad, wave);
     herk_issue(stage1, SA, SB, off, slice_stride, s0 + 1, gpad, wave);
     herk_issue(stage2, SA, SB, off, slice_stride, s0 + 2, gpad, wave);
-    BGW_WAIT_VM(10);
+    BGW_WAIT_VM(2 * PIECES);
     stage_barrier();
     ChunkExp E;
     for (long long s = s0; s < s1; s += NSTAGE) {
@@ -397,11 +403,11 @@ __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restr
     const int wr = wave >> 2, wc = wave & 3;
     const int li = lane & 15, lq = lane >> 4;
 
-    // this lane's source offsets (bytes) for its five pieces of a stage
-    unsigned off[5];
+    // this lane's source offsets (bytes) for its pieces of a stage
+    unsigned off[PIECES];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        const int q = 5 * wave + i;
+    for (int i = 0; i < PIECES; ++i) {
+        const int q = PIECES * wave + i;
         const int row = 16 * (q & 3) + (lane >> 2);
         const int seg = (lane & 3) ^ (row & 3);
         off[i] = (unsigned)((((q >> 2) < NSL ? G0 : H0) + row) * KS * 2 + seg * 16);
@@ -413,7 +419,7 @@ __global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restr
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc.re[a][r] = acc.im[a][r] = 0.0;
 #pragma unroll
-        for (int p = 0; p < 3; ++p)
+        for (int p = 0; p < NGR; ++p)
 #pragma unroll
             for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
     }

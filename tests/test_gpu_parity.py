@@ -308,7 +308,7 @@ def test_split_chi_ragged_superchunks(torch_dev, handle):
     pf = 1.0 / (s["nk"] * s["vol"])
     ref = oracle.chi(M.cpu().numpy(), w, pf)
     one = gpu_chi(handle, torch_dev, s, M, om, precision=bgw.SPLIT_BF16).cpu().numpy()
-    os.environ["BGW_SPLIT_SLICE_BYTES"] = str(5 * 256 * 128 * 2)  # one chunk per super-chunk
+    os.environ["BGW_SPLIT_SLICE_BYTES"] = str(4 * 256 * 128 * 2)  # one chunk (4 slices, gpad 128) per super-chunk
     try:
         many = gpu_chi(handle, torch_dev, s, M, om, precision=bgw.SPLIT_BF16).cpu().numpy()
     finally:
