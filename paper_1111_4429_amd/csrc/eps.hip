@@ -632,16 +632,12 @@ struct WgLds {
     double2 praw[kWgNb];
 };
 
-// Column step J (compile-time, so every row element keeps a fixed register).
-// pos[r]: current position of row r of this thread (>= n: padding row of zeros).
+// Candidate of this thread for pivot column J (largest |Re|+|Im| among its
+// rows at positions >= col, first position on ties), then of the wavefront,
+// published in the LDS slots of the wavefront.
 template <int ROWS, int J>
-__device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
-                                              int nb, int *ip, int *info) {
-    constexpr int NW = kWgThreads / 64;
-    if (J >= nb) return;  // uniform
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col = k + J;
-    // candidate of this thread, then of the wavefront, then of the workgroup
+__device__ __forceinline__ void gje_wg_candidate(const double2 (&rv)[ROWS][kWgNb], const int (&pos)[ROWS], WgLds &L,
+                                                 int n, int col) {
     double best = -1.0;
     int key = 0x7fffffff;
 #pragma unroll
@@ -655,10 +651,39 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
         }
     }
     wave_argmax_dpp(best, key);
-    if (lane == 0) {
-        L.wv[wave] = best;
-        L.wk[wave] = key;
+    if ((threadIdx.x & 63) == 0) {
+        L.wv[threadIdx.x >> 6] = best;
+        L.wk[threadIdx.x >> 6] = key;
     }
+}
+
+// x - f p, complex, as four FMAs
+__device__ __forceinline__ double2 cfms(double2 x, double2 f, double2 p) {
+    return make_double2(fma(-f.x, p.x, fma(f.y, p.y, x.x)), fma(-f.x, p.y, fma(-f.y, p.x, x.y)));
+}
+
+// 1 / z with one division: z is scaled by a power of two first, so that
+// |z|^2 can neither overflow nor underflow.
+__device__ __forceinline__ double2 crecip(double2 z) {
+    int e = 0;
+    (void)frexp(fmax(fabs(z.x), fabs(z.y)), &e);
+    const double x = ldexp(z.x, -e), y = ldexp(z.y, -e);
+    const double t = ldexp(1.0 / (x * x + y * y), -e);
+    return make_double2(x * t, -y * t);
+}
+
+// Column step J (compile-time, so every row element keeps a fixed register).
+// pos[r]: current position of row r of this thread (>= n: padding row of
+// zeros).  The candidates of column J were published by step J - 1 (by the
+// caller for J = 0): right after column J + 1 is eliminated, before the
+// other columns, so their search overlaps the rest of the elimination.
+template <int ROWS, int J>
+__device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
+                                              int nb, int *ip, int *info) {
+    constexpr int NW = kWgThreads / 64;
+    if (J >= nb) return;  // uniform
+    const int tid = threadIdx.x;
+    const int col = k + J;
     __syncthreads();
     double bv = L.wv[0];
     int p = L.wk[0];
@@ -691,19 +716,30 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
     __syncthreads();
     double2 piv = L.praw[J];
     if (piv.x == 0.0 && piv.y == 0.0) piv = make_double2(1.0, 0.0);
-    const double2 ipv = cdiv(make_double2(1.0, 0.0), piv);
+    const double2 ipv = crecip(piv);
     // every row is eliminated with the pivot row, read from LDS once per
     // column element by element (padding rows hold zeros and stay zero);
     // the pivot row's own result is replaced below
     double2 fs[ROWS];
 #pragma unroll
-    for (int r = 0; r < ROWS; ++r) fs[r] = cmul(rv[r][J], ipv);
+    for (int r = 0; r < ROWS; ++r) {
+        fs[r] = cmul(rv[r][J], ipv);
+        rv[r][J] = make_double2(-fs[r].x, -fs[r].y);
+    }
+    constexpr int JN = J + 1 < kWgNb ? J + 1 : J;  // next pivot column
+    if (J + 1 < kWgNb) {
+        const double2 pc = L.praw[JN];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) rv[r][JN] = cfms(rv[r][JN], fs[r], pc);
+        if (J + 1 < nb) gje_wg_candidate<ROWS, JN>(rv, pos, L, n, col + 1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int c = 0; c < kWgNb; ++c) {
+        if (c == J || c == JN) continue;
         const double2 pc = L.praw[c];
 #pragma unroll
-        for (int r = 0; r < ROWS; ++r)
-            rv[r][c] = c == J ? make_double2(-fs[r].x, -fs[r].y) : csub(rv[r][c], cmul(fs[r], pc));
+        for (int r = 0; r < ROWS; ++r) rv[r][c] = cfms(rv[r][c], fs[r], pc);
         __builtin_amdgcn_sched_barrier(0);  // keeps the pivot-row reads from piling up in registers
     }
     if (piv_r >= 0) {  // the pivot row, now at position col, becomes the scaled pivot row
@@ -715,7 +751,9 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
             }
     }
     // the next step writes praw only after its first barrier, which every
-    // thread reaches after these reads
+    // thread reaches after these reads; its candidates were written after
+    // this step's second barrier, which every thread passed after reading
+    // this step's candidates
 }
 
 template <int ROWS, int... Js>
@@ -757,6 +795,7 @@ __global__ __launch_bounds__(kWgThreads) void k_gje_panel_wg(double2 *__restrict
         for (int c = 0; c < kWgNb; ++c) rv[r][c] = tid < cnt ? wg_stage[tid * kWgStageLd + c] : make_double2(0.0, 0.0);
         __syncthreads();
     }
+    gje_wg_candidate<ROWS, 0>(rv, pos, L, n, k);
     gje_wg_columns<ROWS>(rv, pos, L, n, k, nb, ipiv + (size_t)mat * n, info + mat,
                          std::make_integer_sequence<int, kWgNb>{});
     // every row to its final position, one 512-position block at a time
