@@ -63,6 +63,11 @@ __global__ void k_fill_u32(unsigned int *p, size_t n, unsigned int val) {
 
 __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
+// x - f p, complex, as four FMAs
+__device__ __forceinline__ double2 cfms(double2 x, double2 f, double2 p) {
+    return make_double2(fma(-f.x, p.x, fma(f.y, p.y, x.x)), fma(-f.x, p.y, fma(-f.y, p.x, x.y)));
+}
+
 __device__ inline double2 cdiv(double2 a, double2 b) {
     // a / b with scaling (Smith's method)
     if (fabs(b.x) >= fabs(b.y)) {
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
                         const double2 pc = prow[c];
                         const double2 x = pr[c];
                         pr[c] = (c == j) ? make_double2(-(f.x * pj.x - f.y * pj.y), -(f.x * pj.y + f.y * pj.x))
-                                         : csub(x, cmul(f, pc));
+                                         : cfms(x, f, pc);
                     }
             }
         }
@@ -351,7 +356,7 @@ __device__ __forceinline__ void gje_reg_column(const GjeRegCtx &x, double2 (&rv)
             const double2 fs = cmul(rv[J], ipv);
 #pragma unroll
             for (int c = 0; c < nb; ++c)
-                rv[c] = c == J ? make_double2(-fs.x, -fs.y) : csub(rv[c], cmul(fs, praw[c]));
+                rv[c] = c == J ? make_double2(-fs.x, -fs.y) : cfms(rv[c], fs, praw[c]);
         }
     }
 }
@@ -655,11 +660,6 @@ __device__ __forceinline__ void gje_wg_candidate(const double2 (&rv)[ROWS][kWgNb
         L.wv[threadIdx.x >> 6] = best;
         L.wk[threadIdx.x >> 6] = key;
     }
-}
-
-// x - f p, complex, as four FMAs
-__device__ __forceinline__ double2 cfms(double2 x, double2 f, double2 p) {
-    return make_double2(fma(-f.x, p.x, fma(f.y, p.y, x.x)), fma(-f.x, p.y, fma(-f.y, p.x, x.y)));
 }
 
 // 1 / z with one division: z is scaled by a power of two first, so that
