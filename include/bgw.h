@@ -185,7 +185,11 @@ int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cf
  * elimination with partial pivoting (the paper inverts with ZGESV).  The
  * pivot sequence is that of LU with partial pivoting (largest |Re|+|Im|,
  * first index on ties).  info[w] = 0 on success, i > 0 if the i-th pivot
- * (1-based) is exactly zero; epsinv[w] is then unspecified.
+ * (1-based) is exactly zero; epsinv[w] is then unspecified; info[w] = -1000
+ * if an internal wait between workgroups gave up (the call still returns).
+ * For ng <= 1536 each panel is eliminated by one workgroup per matrix; the
+ * environment variable BGW_GJE_PATH=coop selects the cooperative
+ * multi-workgroup panels used above that size (same results to rounding).
  * ---------------------------------------------------------------------- */
 /* vcoul: DEVICE f64 [ng]; chi: DEVICE complex128 [nw][ng][ng];
  * epsinv: DEVICE complex128 [nw][ng][ng], may be the same pointer as chi

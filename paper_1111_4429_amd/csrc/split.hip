@@ -543,7 +543,7 @@ SplitPlan make_plan(long long K, int ng, int nsplit_override) {
     return p;
 }
 
-constexpr int kHeadSplits = 64;
+constexpr int kHeadSplits = 512;  // K ranges of the FP64 head row (enough blocks to stream M at full rate)
 
 size_t al(size_t b) { return (b + 255) / 256 * 256; }
 }  // namespace
