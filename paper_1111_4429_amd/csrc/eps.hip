@@ -479,17 +479,27 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
                 if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + (cp < k ? cp : cp + nb)];
             }
 
-    for (int e = tid; e < UT * kPanelMax; e += 256) {
+    // P and R tiles: all loads issued before the first LDS store, so their
+    // latencies overlap
+    constexpr int SIT = UT * kPanelMax / 256;
+    double2 pv[SIT], rw[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+        const int e = tid + 256 * it;
         const int i = e / kPanelMax, j = e % kPanelMax;  // P tile: row i, panel col j
-        double2 pv = make_double2(0.0, 0.0);
-        if (I0 + i < n && j < nb) pv = Am[(size_t)(I0 + i) * n + k + j];
-        Ps[2 * j][i] = pv.x;
-        Ps[2 * j + 1][i] = pv.y;
+        pv[it] = (I0 + i < n && j < nb) ? Am[(size_t)(I0 + i) * n + k + j] : make_double2(0.0, 0.0);
         const int jr = e / UT, c = e % UT;  // R tile: panel row jr, col c
-        double2 rv = make_double2(0.0, 0.0);
-        if (jr < nb && C0 + c < m) rv = R[(size_t)jr * m + C0 + c];
-        Rsh[2 * jr][c] = rv.x;
-        Rsh[2 * jr + 1][c] = rv.y;
+        rw[it] = (jr < nb && C0 + c < m) ? R[(size_t)jr * m + C0 + c] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+        const int e = tid + 256 * it;
+        const int i = e / kPanelMax, j = e % kPanelMax;
+        Ps[2 * j][i] = pv[it].x;
+        Ps[2 * j + 1][i] = pv[it].y;
+        const int jr = e / UT, c = e % UT;
+        Rsh[2 * jr][c] = rw[it].x;
+        Rsh[2 * jr + 1][c] = rw[it].y;
     }
     __syncthreads();
     double4_t cre[2][2], cim[2][2];
@@ -501,6 +511,7 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
             cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
         }
     const int ksteps = (2 * nb + 3) / 4;
+#pragma unroll 4
     for (int s = 0; s < ksteps; ++s) {
         const int kr = 4 * s + lk;
         double av[2], bre[2], bim[2];
