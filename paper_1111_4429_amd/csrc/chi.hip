@@ -62,22 +62,29 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
         }
 
     const int lcol = tid % T, lrow = tid / T;
+    constexpr int SL = KC / LR;  // pairs each thread stages per stage
+    // the imaginary-part operand is +-B of the other part of the same pair
+    // (row kr ^ 1), negated on imaginary rows: a sign, not a branch
+    const double isign = (lk & 1) ? -1.0 : 1.0;
     for (long long kk = k0; kk < k1; kk += KC) {
+        // all loads of the stage first, so their latencies overlap
+        double2 a[SL], b[SL];
+        double wt[SL];
 #pragma unroll
-        for (int s = 0; s < KC / LR; ++s) {
+        for (int s = 0; s < SL; ++s) {
+            const long long t = kk + lrow + LR * s;
+            const bool in = t < k1;
+            wt[s] = in ? w[t] : 0.0;
+            a[s] = (in && G0 + lcol < ng) ? M[t * ng + G0 + lcol] : make_double2(0.0, 0.0);
+            b[s] = (in && H0 + lcol < ng) ? M[t * ng + H0 + lcol] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
             const int r = lrow + LR * s;
-            const long long t = kk + r;
-            double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
-            double wt = 0.0;
-            if (t < k1) {
-                wt = w[t];
-                if (G0 + lcol < ng) a = M[t * ng + G0 + lcol];
-                if (H0 + lcol < ng) b = M[t * ng + H0 + lcol];
-            }
-            As[2 * r][lcol] = wt * a.x;
-            As[2 * r + 1][lcol] = wt * a.y;
-            Bs[2 * r][lcol] = b.x;
-            Bs[2 * r + 1][lcol] = b.y;
+            As[2 * r][lcol] = wt[s] * a[s].x;
+            As[2 * r + 1][lcol] = wt[s] * a[s].y;
+            Bs[2 * r][lcol] = b[s].x;
+            Bs[2 * r + 1][lcol] = b[s].y;
         }
         __syncthreads();
 #pragma unroll
@@ -90,7 +97,7 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
             for (int b = 0; b < NB; ++b) {
                 const int col = wc * WT + 16 * b + li;
                 bre[b] = Bs[kr][col];
-                bim[b] = (kr & 1) ? -Bs[kr - 1][col] : Bs[kr + 1][col];
+                bim[b] = isign * Bs[kr ^ 1][col];
             }
 #pragma unroll
             for (int a = 0; a < NB; ++a)

@@ -511,6 +511,7 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
             cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
         }
     const int ksteps = (2 * nb + 3) / 4;
+    const double rsign = (lk & 1) ? -1.0 : 1.0;  // kr = 4 s + lk has the parity of lk
 #pragma unroll 4
     for (int s = 0; s < ksteps; ++s) {
         const int kr = 4 * s + lk;
@@ -520,13 +521,9 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int col = wc * 32 + 16 * b + li;
-            if (kr & 1) {
-                bre[b] = -Rsh[kr][col];
-                bim[b] = Rsh[kr - 1][col];
-            } else {
-                bre[b] = Rsh[kr][col];
-                bim[b] = Rsh[kr + 1][col];
-            }
+            // odd rows (imaginary parts): Bre = -Im R, Bim = Re R; even: Re R, Im R
+            bre[b] = rsign * Rsh[kr][col];
+            bim[b] = Rsh[kr ^ 1][col];
         }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
