@@ -66,10 +66,11 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
     // the imaginary-part operand is +-B of the other part of the same pair
     // (row kr ^ 1), negated on imaginary rows: a sign, not a branch
     const double isign = (lk & 1) ? -1.0 : 1.0;
-    for (long long kk = k0; kk < k1; kk += KC) {
-        // all loads of the stage first, so their latencies overlap
-        double2 a[SL], b[SL];
-        double wt[SL];
+    // The stage's values are loaded into registers one stage ahead: the loads
+    // of stage kk + KC are issued before the MFMAs of stage kk.
+    double2 a[SL], b[SL];
+    double wt[SL];
+    auto load_stage = [&](long long kk) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const long long t = kk + lrow + LR * s;
@@ -78,6 +79,10 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
             a[s] = (in && G0 + lcol < ng) ? M[t * ng + G0 + lcol] : make_double2(0.0, 0.0);
             b[s] = (in && H0 + lcol < ng) ? M[t * ng + H0 + lcol] : make_double2(0.0, 0.0);
         }
+    };
+    load_stage(k0);
+    for (long long kk = k0; kk < k1; kk += KC) {
+        __syncthreads();  // the previous stage's reads are done
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
             const int r = lrow + LR * s;
@@ -87,6 +92,7 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
             Bs[2 * r + 1][lcol] = b[s].y;
         }
         __syncthreads();
+        if (kk + KC < k1) load_stage(kk + KC);
 #pragma unroll
         for (int s = 0; s < KR / 4; ++s) {
             const int kr = 4 * s + lk;
@@ -107,8 +113,8 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
                     cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
                 }
         }
-        __syncthreads();
     }
+    __syncthreads();  // the LDS tiles are reused by the block's next item
     // D layout of v_mfma_f64_16x16x4: lane l, register r -> row 4r + l/16, col l%16
 #pragma unroll
     for (int a = 0; a < NB; ++a)
@@ -133,7 +139,7 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
 // and column blocks of M through its L2.  Uneven problems (many q with
 // different ng, many omega) share one launch per tile size.
 template <int T>
-__global__ __launch_bounds__(256) void k_herk_f64(const HerkProb *__restrict__ probs, int nprob, long long i0,
+__global__ __launch_bounds__(256, 3) void k_herk_f64(const HerkProb *__restrict__ probs, int nprob, long long i0,
                                                   long long i1) {
     __shared__ double As[KR][LDA];
     __shared__ double Bs[KR][LDA];
