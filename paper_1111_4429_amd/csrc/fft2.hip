@@ -667,7 +667,24 @@ __global__ __launch_bounds__(NT) void k_pair_x(const double2 *__restrict__ T, in
     for (int xs = 0; xs < n1; xs += XS) {
         const int nx = min(XS, n1 - xs);
         __syncthreads();
-        for (int e = threadIdx.x; e < nx * nbox; e += NT) Ts[e] = Tt[(size_t)xs * nbox + e];
+        {
+            // eight loads per thread in flight before their LDS stores
+            const int cnt = nx * nbox;
+            const double2 *src = Tt + (size_t)xs * nbox;
+            for (int e0 = 0; e0 < cnt; e0 += 8 * NT) {
+                double2 v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT + threadIdx.x;
+                    v[u] = e < cnt ? src[e] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int e = e0 + u * NT + threadIdx.x;
+                    if (e < cnt) Ts[e] = v[u];
+                }
+            }
+        }
         __syncthreads();
         for (int xx = 0; xx < nx; ++xx) {
 #pragma unroll
