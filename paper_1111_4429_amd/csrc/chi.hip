@@ -194,6 +194,7 @@ __global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
         const bool up = G <= H;
         const size_t src = up ? e : (size_t)H * ng + G;
         double2 s = make_double2(0.0, 0.0);
+#pragma unroll 8
         for (int p = 0; p < P.ns; ++p) s = cadd(s, P.part[p * total + src]);
         double2 val = make_double2(P.pf * s.x, up ? P.pf * s.y : -P.pf * s.y);
         if (G == H) val.y = 0.0;

@@ -449,12 +449,24 @@ __global__ void k_headwing(const double2 *__restrict__ M, long long K, int ng, i
     if (H >= ng) return;
     const long long k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
     double2 s = make_double2(0.0, 0.0);
-    for (long long t = k0; t < k1; ++t) {
-        const double2 a = M[t * ng + head];
-        const double2 b = M[t * ng + H];
-        const double wt = w[t];
-        s.x += wt * (a.x * b.x + a.y * b.y);
-        s.y += wt * (a.x * b.y - a.y * b.x);
+    // eight pairs' loads in flight at a time; the sum keeps the order of t
+    constexpr int U = 8;
+    for (long long t0 = k0; t0 < k1; t0 += U) {
+        double2 a[U], b[U];
+        double wt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long t = t0 + u;
+            const bool in = t < k1;
+            a[u] = in ? M[t * ng + head] : make_double2(0.0, 0.0);
+            b[u] = in ? M[t * ng + H] : make_double2(0.0, 0.0);
+            wt[u] = in ? w[t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s.x += wt[u] * (a[u].x * b[u].x + a[u].y * b[u].y);
+            s.y += wt[u] * (a[u].x * b[u].y - a[u].y * b[u].x);
+        }
     }
     hw[(size_t)blockIdx.y * ng + H] = s;
 }
