@@ -906,12 +906,17 @@ __global__ __launch_bounds__(256) void k_band_x(const double2 *__restrict__ C, i
         lo = sm.st_lo[s];
     }
     const double2 *cb = C + (size_t)band * ngw;
-    double2 d[N];
+    // all sphere indices of the stick first, then all coefficients, so each
+    // round of loads is in flight together
+    int gi[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const int j = (k <= N / 2 ? k : k - N) - lo;
-        d[k] = (j >= 0 && j < cnt) ? cb[sm.st_gs[base + j]] : make_double2(0.0, 0.0);
+        gi[k] = (j >= 0 && j < cnt) ? sm.st_gs[base + j] : -1;
     }
+    double2 d[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) d[k] = gi[k] >= 0 ? cb[gi[k]] : make_double2(0.0, 0.0);
     LineDFT<N>::run(d);
     double2 *o = W + (size_t)band * N * sm.ncell + cell;
 #pragma unroll
