@@ -792,11 +792,19 @@ __global__ __launch_bounds__(kWgThreads) void k_gje_panel_wg(double2 *__restrict
         const int r0 = r * kWgThreads;
         const int cnt = min(kWgThreads, n - r0);  // >= 1
         pos[r] = r0 + tid;
-#pragma unroll 4
-        for (int it = 0; it < kWgNb; ++it) {
-            const int e = tid + it * kWgThreads, i = e / kWgNb, c = e % kWgNb;
-            if (i < cnt)
-                wg_stage[i * kWgStageLd + c] = c < nb ? Am[(size_t)(r0 + i) * n + k + c] : make_double2(0.0, 0.0);
+        {
+            // the block's 16 loads per thread in flight together
+            double2 v[kWgNb];
+#pragma unroll
+            for (int it = 0; it < kWgNb; ++it) {
+                const int e = tid + it * kWgThreads, i = e / kWgNb, c = e % kWgNb;
+                v[it] = (i < cnt && c < nb) ? Am[(size_t)(r0 + i) * n + k + c] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int it = 0; it < kWgNb; ++it) {
+                const int e = tid + it * kWgThreads, i = e / kWgNb, c = e % kWgNb;
+                if (i < cnt) wg_stage[i * kWgStageLd + c] = v[it];
+            }
         }
         __syncthreads();
 #pragma unroll
