@@ -216,6 +216,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
                 p = cr_s[q];
                 win = q;
             }
+        if (p >= n) p = col;  // no candidate (a column of NaNs): no interchange; info flags the matrix
         if (tid == 0 && r == 0) {
             if (bv <= 0.0) atomicCAS(info + mat, 0, col + 1);
             ip[col] = p;
@@ -335,6 +336,7 @@ __device__ __forceinline__ void gje_reg_column(const GjeRegCtx &x, double2 (&rv)
             p = x.cr_s[q];
             win = q;
         }
+    if (p == 0x7fffffff) p = col;  // no candidate (a column of NaNs): no interchange; info flags the matrix
     if (x.tid == 0 && x.r == 0) {
         if (bv <= 0.0) atomicCAS(x.info + x.mat, 0, col + 1);
         x.ip[col] = p;
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(64) void k_gje_swap_save(double2 *__restrict__ A, i
         const int c = cp < k ? cp : cp + nb;
         for (int j = 0; j < nb; ++j) {
             const int p = ip[k + j];
-            if (p != k + j) {
+            if (p > k + j && p < n) {
                 const double2 t = Am[(size_t)(k + j) * n + c];
                 Am[(size_t)(k + j) * n + c] = Am[(size_t)p * n + c];
                 Am[(size_t)p * n + c] = t;
@@ -558,7 +560,8 @@ __global__ void k_gje_perm(const int *__restrict__ ipiv, int n, int *__restrict_
     const int mat = blockIdx.x;
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         id[j] = j;
-        ip[j] = ipiv[(size_t)mat * n + j];
+        const int p = ipiv[(size_t)mat * n + j];
+        ip[j] = (p >= j && p < n) ? p : j;  // an out-of-range pivot: no interchange
     }
     __syncthreads();
     if (threadIdx.x == 0)
@@ -687,11 +690,11 @@ __device__ __forceinline__ double2 crecip(double2 z) {
 // other columns, so their search overlaps the rest of the elimination.
 template <int ROWS, int J>
 __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
-                                              int nb, int *ip, int *info) {
+                                              int jb, int nb, int *ip, int *info) {
     constexpr int NW = kWgThreads / 64;
-    if (J >= nb) return;  // uniform
+    if (jb + J >= nb) return;  // uniform
     const int tid = threadIdx.x;
-    const int col = k + J;
+    const int col = k + jb + J;
     __syncthreads();
     double bv = L.wv[0];
     int p = L.wk[0];
@@ -701,7 +704,8 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
             bv = L.wv[w];
             p = L.wk[w];
         }
-    // p >= col always (position col itself is a candidate)
+    // p >= col; no candidate at all (a column of NaNs): no interchange, info flags the matrix
+    if (p >= n) p = col;
     int piv_r = -1;  // which of this thread's rows is the pivot row
 #pragma unroll
     for (int r = 0; r < ROWS; ++r)
@@ -739,7 +743,7 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
         const double2 pc = L.praw[JN];
 #pragma unroll
         for (int r = 0; r < ROWS; ++r) rv[r][JN] = cfms(rv[r][JN], fs[r], pc);
-        if (J + 1 < nb) gje_wg_candidate<ROWS, JN>(rv, pos, L, n, col + 1);
+        if (jb + J + 1 < nb) gje_wg_candidate<ROWS, JN>(rv, pos, L, n, col + 1);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -766,8 +770,8 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
 
 template <int ROWS, int... Js>
 __device__ __forceinline__ void gje_wg_columns(double2 (&rv)[ROWS][kWgNb], int (&pos)[ROWS], WgLds &L, int n, int k,
-                                               int nb, int *ip, int *info, std::integer_sequence<int, Js...>) {
-    (gje_wg_column<ROWS, Js>(rv, pos, L, n, k, nb, ip, info), ...);
+                                               int jb, int nb, int *ip, int *info, std::integer_sequence<int, Js...>) {
+    (gje_wg_column<ROWS, Js>(rv, pos, L, n, k, jb, nb, ip, info), ...);
 }
 
 // One workgroup per matrix (blockIdx.x), panel columns [k, k + nb), nb <= kWgNb.
@@ -775,6 +779,8 @@ __device__ __forceinline__ void gje_wg_columns(double2 (&rv)[ROWS][kWgNb], int (
 // rows (row stride kWgNb + 1 elements, conflict-free row reads), so the
 // global accesses are whole 256-byte row segments.
 constexpr int kWgStageLd = kWgNb + 1;
+constexpr int kWgUnroll = 2;  // column steps per pass of the panel loop
+static_assert(kWgNb % kWgUnroll == 0 && kWgUnroll >= 1, "whole passes");
 constexpr size_t kWgStageBytes = sizeof(double2) * kWgThreads * kWgStageLd;
 
 template <int ROWS>
@@ -812,8 +818,27 @@ __global__ __launch_bounds__(kWgThreads) void k_gje_panel_wg(double2 *__restrict
         __syncthreads();
     }
     gje_wg_candidate<ROWS, 0>(rv, pos, L, n, k);
-    gje_wg_columns<ROWS>(rv, pos, L, n, k, nb, ipiv + (size_t)mat * n, info + mat,
-                         std::make_integer_sequence<int, kWgNb>{});
+    // kWgUnroll column steps per pass on register columns 0 .. kWgUnroll-1,
+    // then the columns rotate left by kWgUnroll, so that the next pass again
+    // starts at register column 0; after kWgNb / kWgUnroll passes every
+    // column is back in its own register.  The pass is a real loop: fully
+    // unrolled, the three-row panel is about 100 KB of code, more than the
+    // instruction cache holds, and each launch fetches all of it once.
+#pragma unroll 1
+    for (int jb = 0; jb < kWgNb; jb += kWgUnroll) {
+        gje_wg_columns<ROWS>(rv, pos, L, n, k, jb, nb, ipiv + (size_t)mat * n, info + mat,
+                             std::make_integer_sequence<int, kWgUnroll>{});
+        if (kWgUnroll < kWgNb) {
+#pragma unroll
+            for (int r = 0; r < ROWS; ++r) {
+                double2 t[kWgNb];
+#pragma unroll
+                for (int c = 0; c < kWgNb; ++c) t[c] = rv[r][(c + kWgUnroll) % kWgNb];
+#pragma unroll
+                for (int c = 0; c < kWgNb; ++c) rv[r][c] = t[c];
+            }
+        }
+    }
     // every row to its final position, one 512-position block at a time
 #pragma unroll
     for (int b = 0; b < ROWS; ++b) {

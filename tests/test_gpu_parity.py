@@ -412,6 +412,29 @@ def test_eps_inv_singular_info(torch_dev, handle):
     assert list(rinfo) == [0, 41]
 
 
+@pytest.mark.parametrize("path", ["wg", "coop"])
+def test_eps_inv_nan_column(torch_dev, handle, path, monkeypatch):
+    """A column of NaNs offers no pivot candidate at all: that matrix is
+    flagged at its column (info = 1-based index, no row interchange), the
+    other matrix of the call is inverted normally, and a following call is
+    unaffected."""
+    if path == "coop":
+        monkeypatch.setenv("BGW_GJE_PATH", "coop")
+    rng = np.random.default_rng(77)
+    n = 70
+    eps = np.eye(n) + 0.1 * (rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n)))
+    v = rng.uniform(0.5, 2.0, n)
+    chi = (np.eye(n)[None] - eps) / v[None, :, None]
+    chi[1, :, 30] = np.nan
+    einv, info = handle.eps_inv(dev(torch_dev, v), dev(torch_dev, chi))
+    assert list(info.cpu().numpy()) == [0, 31]
+    ref, rinfo = oracle.eps_inv(v, chi[:1])
+    assert rel(einv.cpu().numpy()[0], ref[0]) <= TOL
+    einv2, info2 = handle.eps_inv(dev(torch_dev, v), dev(torch_dev, chi[:1].copy()))
+    assert list(info2.cpu().numpy()) == [0]
+    assert rel(einv2.cpu().numpy()[0], ref[0]) <= TOL
+
+
 def test_eps_inv_in_place(torch_dev, handle):
     torch = torch_dev[0]
     rng = np.random.default_rng(9)
