@@ -15,6 +15,9 @@ it follows:
 * ``weights``       1/(E_v,k+q - E_c,k) (static chi equation) and its
   imaginary-frequency continuation Delta/(Delta^2+omega^2), taken from the
   retarded/advanced dielectric equation at E = i omega, delta -> 0+.
+* ``weights_real``  the complex weights of that equation at real E with
+  broadening delta (retarded or advanced), for the full-frequency chi.
+* ``ff_grid``       the real-frequency grid of the full-frequency run.
 * ``chi``           the chi sum, compensated, any block of (G, G').
 * ``vcoul``         bulk bare Coulomb 4 pi/|q+G|^2.
 * ``eps``           epsilon = 1 - v chi (asymmetric Coulomb form).
@@ -63,8 +66,11 @@ def lib():
         L.orc_vcoul.argtypes = [P, P, I, P, P]
         L.orc_eps.argtypes = [I, I, P, P, P]
         L.orc_inverse.argtypes = [I, P, P]
+        L.orc_weights_real.argtypes = [I, I, I, P, P, I, P, D, I, P]
+        L.orc_chi_cw.argtypes = [Lg, I, P, I, P, D, I, P, I, P, P]
+        L.orc_ff_grid.argtypes = [D, D, D, D, I, P]
         for f in (L.orc_pair_density, L.orc_weights, L.orc_chi, L.orc_vcoul, L.orc_eps, L.orc_inverse,
-                  L.orc_num_threads):
+                  L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid):
             f.restype = I
         _lib = L
     return _lib
@@ -118,9 +124,51 @@ def weights(ev: np.ndarray, ec: np.ndarray, omega_ev: Sequence[float]) -> np.nda
     return out
 
 
+def weights_real(ev: np.ndarray, ec: np.ndarray, E_ev: Sequence[float], delta_ev: float,
+                 kind: str = "retarded") -> np.ndarray:
+    """Complex weights [nE][K] of the retarded (or advanced) dielectric equation at real E (eV)."""
+    ev = np.ascontiguousarray(ev, dtype=np.float64)
+    ec = np.ascontiguousarray(ec, dtype=np.float64)
+    E = np.ascontiguousarray(E_ev, dtype=np.float64).reshape(-1)
+    nk, nv = ev.shape
+    nc = ec.shape[1]
+    out = np.zeros((E.size, nk * nv * nc), dtype=np.complex128)
+    rc = lib().orc_weights_real(nk, nv, nc, _p(ev), _p(ec), E.size, _p(E), float(delta_ev),
+                                1 if kind == "retarded" else 0, _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_weights_real failed: {rc}")
+    return out
+
+
+def ff_grid(dE: float, e_low: float, e_high: float, increment: float) -> np.ndarray:
+    """The full-frequency real-axis grid (eV)."""
+    n = lib().orc_ff_grid(float(dE), float(e_low), float(e_high), float(increment), 0, None)
+    if n < 0:
+        raise ValueError("bad frequency-grid parameters")
+    out = np.zeros(n)
+    lib().orc_ff_grid(float(dE), float(e_low), float(e_high), float(increment), n, _p(out))
+    return out
+
+
 def chi(M: np.ndarray, w: np.ndarray, pf: float, rows: Optional[Sequence[int]] = None,
         cols: Optional[Sequence[int]] = None) -> np.ndarray:
+    """chi[w][rows][cols] = pf sum_t conj(M_t(G)) w_t M_t(G'); w real [nw][K], or complex
+    (real frequency axis)."""
     M = np.ascontiguousarray(M, dtype=np.complex128)
+    if np.iscomplexobj(w):
+        wc = np.ascontiguousarray(np.atleast_2d(w), dtype=np.complex128)
+        K, ng = M.shape
+        assert wc.shape[1] == K
+        r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
+        c = None if cols is None else np.ascontiguousarray(cols, dtype=np.int32)
+        nr = ng if r is None else r.size
+        ncl = ng if c is None else c.size
+        out = np.zeros((wc.shape[0], nr, ncl), dtype=np.complex128)
+        rc = lib().orc_chi_cw(K, ng, _p(M), wc.shape[0], _p(wc), float(pf), nr, None if r is None else _p(r),
+                              ncl, None if c is None else _p(c), _p(out))
+        if rc != 0:
+            raise RuntimeError(f"orc_chi_cw failed: {rc}")
+        return out
     w = np.ascontiguousarray(np.atleast_2d(w), dtype=np.float64)
     K, ng = M.shape
     assert w.shape[1] == K

@@ -12,6 +12,10 @@
  *                     plane-wave basis: a convolution over G-vectors.
  *   orc_weights       energy denominators of the static-chi equation and
  *                     its imaginary-frequency continuation.
+ *   orc_weights_real  the complex retarded/advanced weights at real
+ *                     frequencies (full-frequency epsilon).
+ *   orc_chi_cw        the chi sum with those complex weights.
+ *   orc_ff_grid       the real-frequency grid of the full-frequency run.
  *   orc_chi           the chi sum itself, for every (G, G') asked for,
  *                     with compensated summation over the pair index.
  *   orc_vcoul         bare Coulomb interaction of the untruncated bulk case.
@@ -149,6 +153,119 @@ int orc_weights(int nk, int nv, int nc, const double *ev, const double *ec,
         }
     }
     return 0;
+}
+
+/*
+ * Real-frequency weights of the retarded/advanced dielectric equation
+ * (full-frequency part of the epsilon section):
+ *   w_t(E) = 1/2 [ 1/(Delta_t - E - i s delta) + 1/(Delta_t + E + i s delta) ]
+ * with s = +1 for the retarded function and s = -1 for the advanced one,
+ * Delta_t = E_{v,k+q} - E_{c,k}; every input in eV, converted to hartree.
+ * Complex division written out: 1/(x + i y) = (x - i y)/(x^2 + y^2).
+ * w: [nE][K] complex (re, im interleaved).
+ */
+int orc_weights_real(int nk, int nv, int nc, const double *ev, const double *ec,
+                     int nE, const double *E_ev, double delta_ev, int retarded, double *w)
+{
+    if (nk <= 0 || nv <= 0 || nc <= 0 || nE <= 0 || !(delta_ev > 0)) return -1;
+    const long K = (long)nk * nv * nc;
+    const double s = retarded ? 1.0 : -1.0;
+    const double dl = s * delta_ev / HARTREE_EV;
+    for (int ie = 0; ie < nE; ++ie) {
+        if (E_ev[ie] < 0) return -1;
+        double E = E_ev[ie] / HARTREE_EV;
+        for (long t = 0; t < K; ++t) {
+            long c = t % nc, kv = t / nc, k = kv / nv, v = kv % nv;
+            double d = (ev[k * nv + v] - ec[k * nc + c]) / HARTREE_EV;
+            /* first term: 1/(x1 + i y1), x1 = d - E, y1 = -dl */
+            double x1 = d - E, y1 = -dl, n1 = x1 * x1 + y1 * y1;
+            /* second term: 1/(x2 + i y2), x2 = d + E, y2 = +dl */
+            double x2 = d + E, y2 = dl, n2 = x2 * x2 + y2 * y2;
+            w[2 * (ie * K + t)] = 0.5 * (x1 / n1 + x2 / n2);
+            w[2 * (ie * K + t) + 1] = 0.5 * (-y1 / n1 - y2 / n2);
+        }
+    }
+    return 0;
+}
+
+/*
+ * The chi sum with complex weights (real frequency axis): every requested
+ * entry chi_{GG'}(E) = pf * sum_t conj(M_t(G)) w_t(E) M_t(G'), summed over t
+ * in ascending order with Neumaier compensation.  w: [nE][K] complex.
+ * rows/cols as in orc_chi.
+ */
+int orc_chi_cw(long K, int ng, const double *M, int nw, const double *w, double pf,
+               int nrow, const int *rows, int ncol, const int *cols, double *chi)
+{
+    if (K < 0 || ng <= 0 || nw <= 0) return -1;
+    if (!rows) nrow = ng;
+    if (!cols) ncol = ng;
+    for (int iw = 0; iw < nw; ++iw) {
+        const double *wv = w + 2L * iw * K;
+#pragma omp parallel
+        {
+            double *acc = (double *)malloc(sizeof(double) * 4 * ncol);
+#pragma omp for schedule(dynamic, 1)
+            for (int r = 0; r < nrow; ++r) {
+                int g = rows ? rows[r] : r;
+                memset(acc, 0, sizeof(double) * 4 * ncol);
+                for (long t = 0; t < K; ++t) {
+                    const double *mt = M + 2 * t * ng;
+                    /* a = w_t * conj(M_t(G)) */
+                    double cr = mt[2 * g], ci = -mt[2 * g + 1];
+                    double wr = wv[2 * t], wi = wv[2 * t + 1];
+                    double ar = wr * cr - wi * ci, ai = wr * ci + wi * cr;
+                    for (int cidx = 0; cidx < ncol; ++cidx) {
+                        int g2 = cols ? cols[cidx] : cidx;
+                        double br = mt[2 * g2], bi = mt[2 * g2 + 1];
+                        double *s = acc + 4 * cidx;
+                        neu_add(&s[0], &s[1], ar * br - ai * bi);
+                        neu_add(&s[2], &s[3], ar * bi + ai * br);
+                    }
+                }
+                double *out = chi + 2 * ((long)iw * nrow * ncol + (long)r * ncol);
+                for (int cidx = 0; cidx < ncol; ++cidx) {
+                    out[2 * cidx] = pf * (acc[4 * cidx] + acc[4 * cidx + 1]);
+                    out[2 * cidx + 1] = pf * (acc[4 * cidx + 2] + acc[4 * cidx + 3]);
+                }
+            }
+            free(acc);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Real-frequency grid of the full-frequency epsilon calculation (the paper's
+ * frequency-grid figure): uniform from 0 with spacing dE up to the low
+ * cutoff, then the spacing grows by `increment` at every further point until
+ * the high cutoff.  Writes at most maxn points to E (eV) and returns the
+ * number of points the grid has (which may exceed maxn), or -1.
+ */
+int orc_ff_grid(double dE, double e_low, double e_high, double increment, int maxn, double *E)
+{
+    if (!(dE > 0) || e_low < 0 || e_high < e_low || increment < 0) return -1;
+    int n = 0;
+    double x = 0.0;
+    /* uniform part: i * dE for i = 0, 1, ... while <= e_low */
+    for (long i = 0;; ++i) {
+        x = (double)i * dE;
+        if (x > e_low * (1.0 + 1e-12)) break;
+        if (n < maxn) E[n] = x;
+        ++n;
+    }
+    x = (double)(n - 1) * dE;
+    double step = dE;
+    for (;;) {
+        step += increment;
+        double next = x + step;
+        if (next > e_high * (1.0 + 1e-12)) break;
+        if (n < maxn) E[n] = next;
+        ++n;
+        x = next;
+        if (increment == 0 && n > 10000000) return -1;
+    }
+    return n;
 }
 
 /*

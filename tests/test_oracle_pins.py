@@ -213,6 +213,28 @@ def test_chi_hermitian_nsd_trace(c1_chi):
     assert np.all(d[1:] < d[:-1])
 
 
+def test_chi_rows_cols_block(c1_chi):
+    """The (rows, cols) block path of the oracle's chi -- the one the
+    full-size GPU tests compare against -- equals numpy's product on the
+    same rows and columns, and the matching block of the full matrix, for
+    random permuted (and repeated) indices."""
+    M, w, pf, chi = c1_chi
+    rng = np.random.default_rng(11)
+    ng = M.shape[1]
+    rows = rng.permutation(ng)[:37]
+    cols = np.concatenate([rng.permutation(ng)[:23], rows[:3]])
+    blk = oracle.chi(M, w, pf, rows=rows, cols=cols)
+    for i in range(w.shape[0]):
+        ref = pf * (M[:, rows].conj().T * w[i]) @ M[:, cols]
+        assert rel(blk[i], ref) < 1e-14
+        assert rel(blk[i], chi[i][np.ix_(rows, cols)]) < 1e-15
+    # rows only / cols only
+    r_only = oracle.chi(M, w[:1], pf, rows=rows[:5])[0]
+    assert rel(r_only, chi[0][rows[:5]]) < 1e-15
+    c_only = oracle.chi(M, w[:1], pf, cols=cols[:4])[0]
+    assert rel(c_only, chi[0][:, cols[:4]]) < 1e-15
+
+
 def test_chi_rank_one_closed_form():
     """P-chi3: one pair => chi = pf * w * conj(m) m^T exactly."""
     rng = np.random.default_rng(4)
@@ -271,6 +293,22 @@ def test_vcoul_closed_form(c1):
     assert np.allclose(v, 4 * np.pi / (qc ** 2).sum(1), rtol=1e-15)
     with pytest.raises(ValueError):
         oracle.vcoul(c1["bmat"], np.zeros(3), q["ge"])
+
+
+def test_vcoul_non_cubic_cell_hand_value():
+    """v(q+G) on a skewed, non-symmetric reciprocal basis (rows = b_i).
+    By hand for q = (0.1, 0.2, -0.3), G = (1, -2, 3):
+      q+G = (1.1, -1.8, 2.7) in crystal units,
+      cartesian = 1.1 b1 - 1.8 b2 + 2.7 b3 = (0.92, -3.56, 4.86),
+      |q+G|^2 = 0.8464 + 12.6736 + 23.6196 = 37.1396.
+    Using the columns of B instead (a transposed basis) would give
+    (0.74, -1.78, 6.12) and 41.17."""
+    B = np.array([[1.0, 0.2, 0.0], [0.1, 1.5, 0.3], [0.0, -0.4, 2.0]])
+    ge = np.array([[1, -2, 3], [0, 0, 0]], dtype=np.int32)
+    v = oracle.vcoul(B, [0.1, 0.2, -0.3], ge)
+    assert abs(v[0] - 4 * np.pi / 37.1396) <= 1e-14 * v[0]
+    # G = 0: q alone, cartesian 0.1 b1 + 0.2 b2 - 0.3 b3 = (0.12, 0.44, -0.54), |.|^2 = 0.4996
+    assert abs(v[1] - 4 * np.pi / 0.4996) <= 1e-14 * v[1]
 
 
 def test_eps_inverse_residual_and_numpy(c1_eps):
@@ -363,3 +401,95 @@ def test_head_wing_q_scaling():
         assert head == pytest.approx(10.0 ** table[(name, "head")], rel=0.02)
         assert wing == pytest.approx(10.0 ** table[(name, "wing")], rel=0.02)
         assert wingp == pytest.approx(10.0 ** table[(name, "wingp")], rel=0.02)
+
+
+# ---------------------------------------------------------------- real frequency axis (full frequency)
+
+
+def test_weights_real_integral_closed_form():
+    """The imaginary part of the retarded weight of one transition integrates
+    over E >= 0 to atan(Delta / delta) exactly (difference of two
+    Lorentzians centred at E = Delta and E = -Delta); the advanced weight is
+    its complex conjugate.  Trapezoid rule on a fine grid plus the analytic
+    tail beyond it."""
+    ev = np.array([[-3.0]])
+    ec = np.array([[2.0]])           # Delta = -5 eV
+    delta = 0.4                      # eV
+    E = np.linspace(0.0, 400.0, 400001)
+    wr = oracle.weights_real(ev, ec, E, delta, "retarded")[:, 0]
+    wa = oracle.weights_real(ev, ec, E, delta, "advanced")[:, 0]
+    assert np.array_equal(wa, np.conj(wr))
+    d, dl = -5.0 / H, delta / H
+    # integrate in hartree; tail beyond Emax: int_Emax^inf of the difference of the two Lorentzians
+    x = E / H
+    integral = np.trapezoid(wr.imag, x)
+    xm = x[-1]
+    tail = 0.5 * ((np.pi / 2 - np.arctan((xm - d) / dl)) - (np.pi / 2 - np.arctan((xm + d) / dl)))
+    assert abs(integral + tail - np.arctan(d / dl)) < 1e-6
+
+
+def test_weights_real_static_limit_and_sign():
+    """E = 0 with delta -> 0 gives the static 1/Delta (imaginary part -> 0);
+    for E > 0 every imaginary part of the retarded weight is negative
+    (Delta < 0), which makes the anti-Hermitian part of chi^r semidefinite."""
+    rng = np.random.default_rng(3)
+    ev = np.sort(rng.uniform(-10, 0, (2, 3)), axis=1)
+    ec = np.sort(rng.uniform(1, 20, (2, 5)), axis=1)
+    w0 = oracle.weights(ev, ec, [0.0])[0]
+    wr = oracle.weights_real(ev, ec, [0.0], 1e-9, "retarded")[0]
+    assert np.allclose(wr.real, w0, rtol=1e-15, atol=0)
+    assert np.abs(wr.imag).max() <= 1e-9 * np.abs(w0).max()
+    wE = oracle.weights_real(ev, ec, [0.5, 3.0, 12.0, 40.0], 0.1, "retarded")
+    assert np.all(wE.imag < 0)
+
+
+@pytest.fixture(scope="module")
+def c1_ff(c1):
+    q = c1["qs"][0]
+    M = oracle.pair_density(c1["gw"], q["ge"], q["cv"], c1["cc"])
+    E = oracle.ff_grid(2.0, 6.0, 30.0, 2.0)
+    pf = oracle.prefactor(c1["nk"], c1["vol"])
+    wr = oracle.weights_real(q["ev"], c1["ec"], E, 0.5, "retarded")
+    wa = oracle.weights_real(q["ev"], c1["ec"], E, 0.5, "advanced")
+    return M, E, pf, wr, wa, oracle.chi(M, wr, pf), oracle.chi(M, wa, pf)
+
+
+def test_ff_grid_hand_example():
+    """Uniform spacing up to the low cutoff, then the spacing grows by the
+    increment at every point until the high cutoff (hand-worked: spacing 0.5
+    up to 2, increment 0.5 up to 5 -> 0, .5, 1, 1.5, 2, 3, 4.5)."""
+    assert np.allclose(oracle.ff_grid(0.5, 2.0, 5.0, 0.5), [0, 0.5, 1, 1.5, 2, 3, 4.5], rtol=0, atol=1e-15)
+    g = oracle.ff_grid(0.2, 1.0, 30.0, 0.1)
+    assert np.allclose(np.diff(g)[:5], 0.2)
+    assert np.all(np.diff(np.diff(g)[5:]) > 0.0999) and g[-1] <= 30.0
+
+
+def test_chi_real_axis_numpy_and_adjoint(c1_ff):
+    """chi^r against numpy with complex weights; chi^a(E) = chi^r(E)^H; the
+    anti-Hermitian part (chi^r - chi^r^H) / 2i is negative semidefinite for
+    E > 0 and chi^r(0) is Hermitian."""
+    M, E, pf, wr, wa, cr, ca = c1_ff
+    for i in range(len(E)):
+        ref = pf * (M.conj().T * wr[i]) @ M
+        assert rel(cr[i], ref) < 1e-14
+        assert np.abs(ca[i] - cr[i].conj().T).max() <= 1e-15 * np.abs(cr[i]).max()
+        anti = (cr[i] - cr[i].conj().T) / 2j
+        ev = np.linalg.eigvalsh(0.5 * (anti + anti.conj().T))
+        if E[i] > 0:
+            assert ev.max() <= 1e-14 * np.abs(ev).max()
+    assert np.abs(cr[0] - cr[0].conj().T).max() <= 1e-15 * np.abs(cr[0]).max()
+
+
+def test_eps_inverse_real_axis(c1_ff, c1):
+    """The general (non-Hermitian) dielectric matrix of the real axis: the
+    oracle's elimination against numpy.linalg.inv, and its residual."""
+    M, E, pf, wr, wa, cr, ca = c1_ff
+    q = c1["qs"][0]
+    v = oracle.vcoul(c1["bmat"], q["q"], q["ge"])
+    einv, info = oracle.eps_inv(v, cr)
+    e = oracle.eps(v, cr)
+    assert np.all(info == 0)
+    n = e.shape[1]
+    for i in range(e.shape[0]):
+        assert rel(einv[i], np.linalg.inv(e[i])) < 1e-11
+        assert np.linalg.norm(e[i] @ einv[i] - np.eye(n)) / np.sqrt(n) < 1e-12
