@@ -46,6 +46,10 @@ extern "C" {
 #define BGW_ERR_NOMEM (-5)       /* workspace could not be allocated (or exceeds BGW_WORKSPACE_LIMIT) */
 #define BGW_ERR_UNSUPPORTED (-6) /* e.g. an FFT length that is not 2^a 3^b in [4, 128] */
 
+#define BGW_AXIS_IMAG 0          /* chi0 at imaginary frequencies i|omega| (omega = 0: static) */
+#define BGW_AXIS_RETARDED 1      /* chi0^r at real frequencies E >= 0 with broadening delta */
+#define BGW_AXIS_ADVANCED 2      /* chi0^a at real frequencies E >= 0 with broadening delta */
+
 #define BGW_FP64 0               /* chi-sum on FP64 MFMA */
 #define BGW_SPLIT_BF16 1         /* chi-sum as split BF16 slices, FP32 accumulation, FP64 recombination */
 
@@ -65,7 +69,12 @@ int bgw_destroy(bgw_handle_t h);
 /* Message for the last non-zero return on the calling thread ("" if none). */
 const char *bgw_last_error(void);
 
-/* Bytes of device workspace the handle currently holds. */
+/* Bytes of device workspace the handle currently holds (it grows to the
+ * largest requirement of the calls made so far).  What a given call needs
+ * is returned, before the call, by bgw_pair_density_workspace,
+ * bgw_chi0_workspace and bgw_eps_inv_workspace; a call allocates exactly
+ * that much when the handle holds less, and fails with BGW_ERR_NOMEM when
+ * it exceeds the environment variable BGW_WORKSPACE_LIMIT (bytes). */
 size_t bgw_workspace_bytes(bgw_handle_t h);
 
 /* ------------------------------------------------------------------------
@@ -112,6 +121,13 @@ int bgw_pair_transform_box(const bgw_pair_desc *d, int box[3]);
  * identical M. */
 int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream);
 
+/* Device workspace bgw_pair_density(h, d, ...) needs, in bytes, written to
+ * *bytes (HOST).  The k-batch adapts to the free device memory and to
+ * BGW_WORKSPACE_LIMIT, so the answer holds for a call made next, with no
+ * allocation in between.  Builds (and caches in h) the transform plan, a
+ * few small device tables; allocates no workspace. */
+int bgw_pair_density_workspace(bgw_handle_t h, const bgw_pair_desc *d, size_t *bytes);
+
 /* ------------------------------------------------------------------------
  * Polarizability chi0_GG'(q, omega)
  *
@@ -120,14 +136,23 @@ int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *st
  * implicit 1/(N_k V_uc) of every k sum (GW-BSE overview) passed in as
  * `prefactor`:
  *     chi_GG'(omega) = prefactor * sum_t conj(M_t(G)) w_t(omega) M_t(G')
- *     w_t(omega)     = Delta_t / (Delta_t^2 + omega^2),
  *     Delta_t        = E_{v,k+q} - E_{c,k}  (hartree; < 0 for insulators)
- * omega = 0 is the static case 1/Delta; omega > 0 is the imaginary-axis
- * value, i.e. the paper's retarded/advanced bracket evaluated at E = i omega
- * with vanishing broadening.  chi is Hermitian; the full matrix is
- * returned (lower triangle = conjugate mirror of the upper one).  Row and
- * column `head` (the index of G = 0, or -1) are always computed in FP64 from
- * M, also in split precision, because v(q0+0) ~ 1/q0^2 amplifies them.
+ * Imaginary axis (axis = BGW_AXIS_IMAG): w_t = Delta_t / (Delta_t^2 + omega^2);
+ * omega = 0 is the static case 1/Delta, omega > 0 the paper's
+ * retarded/advanced bracket evaluated at E = i omega with vanishing
+ * broadening.  chi is Hermitian; the full matrix is returned (lower triangle
+ * = conjugate mirror of the upper one).
+ * Real axis (full-frequency section of the epsilon step, retarded/advanced
+ * dielectric equation): omega[] holds real frequencies E >= 0 and
+ *     w_t = (1/2) [1/(Delta_t - E -+ i delta) + 1/(Delta_t + E +- i delta)]
+ * with the upper signs for the retarded function (BGW_AXIS_RETARDED) and the
+ * lower ones for the advanced function (BGW_AXIS_ADVANCED), delta the
+ * broadening.  The weight is complex, so chi = pf (A + i B) with A and B the
+ * Hermitian sums of Re w and Im w: chi is a general complex matrix, and
+ * chi^a(E) = chi^r(E)^H.  Both sums run on the kernels of the Hermitian case.
+ * Row and column `head` (the index of G = 0, or -1) are always computed in
+ * FP64 from M, also in split precision, because v(q0+0) ~ 1/q0^2 amplifies
+ * them.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int ng;              /* rows/cols of chi for this q (uneven across q allowed) */
@@ -150,17 +175,29 @@ typedef struct {
     int use_graph;       /* 1: capture the call's launch sequence into a HIP graph the first
                             time this exact descriptor (same pointers, sizes, frequencies) is
                             seen, and replay the graph on later calls; 0: launch directly */
+    int axis;            /* BGW_AXIS_IMAG (0), BGW_AXIS_RETARDED or BGW_AXIS_ADVANCED */
+    double broadening;   /* delta in eV, > 0 on the real axis (ignored on the imaginary axis) */
 } bgw_chi_desc;
 
-/* All q entries and all frequencies form one batch of (q, omega) problems.
- * FP64: one launch for the weights, one persistent rank-K-update launch over
- * every (problem, output tile, K range) work item, one finalize launch.
- * Split: weights in one launch, then slicing, BF16 GEMM, finalize and FP64
- * head row per problem.  Output tiles and K-split counts per size class
+/* All q entries and all frequencies form one batch: one weight vector per
+ * (q, frequency) on the imaginary axis, two (Re w, Im w) on the real axis.
+ * FP64: one launch for the weights, one persistent rank-K-update launch per
+ * output-tile size over every (vector, output tile, K range) work item, one
+ * finalize launch.  Split: weights in one launch; the frequency-independent
+ * digit slices of every q (k_split_slice); one persistent BF16 launch over
+ * every (q, vector, tile, K range) item whose slices fit in the workspace
+ * together (usually the whole batch), which slices the weighted side in
+ * registers; the FP64 head rows of all vectors of a q in one pass over M;
+ * one finalize launch.  Output tiles and K-split counts per size class
  * (ng rounded up to 512, ceil(log2 K)) come from bgw_autotune when it has
  * run, from fixed rules otherwise.  Work is ordered on `stream`; calls on one
  * handle must not run concurrently (they share its workspace). */
 int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
+
+/* Device workspace bgw_chi0(h, d, ...) needs, in bytes (HOST *bytes):
+ * weights, partial sums and, in split precision, the digit slices.
+ * Allocates nothing. */
+int bgw_chi0_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t *bytes);
 
 /* Autotuner.  For every size class present in d (precision taken from d),
  * times the candidate configurations (FP64: output tile 32 or 64 and the
@@ -197,6 +234,10 @@ int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cf
 int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
                 double *epsinv, int *info, void *stream);
 
+/* Device workspace bgw_eps_inv(h, ng, nw, ...) needs, in bytes (HOST
+ * *bytes).  Allocates nothing. */
+int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes);
+
 /* ------------------------------------------------------------------------
  * Per-kernel timing.  When enabled, every kernel launch (or launch group)
  * of the compute calls is bracketed by HIP events recorded on the call's
@@ -220,6 +261,15 @@ int bgw_set_timing(bgw_handle_t h, int enable);
 /* total_ms and launches may be NULL.  Unknown kernel id: BGW_ERR_ARG. */
 int bgw_get_timing(bgw_handle_t h, int kernel, double *total_ms, long long *launches);
 int bgw_reset_timing(bgw_handle_t h);
+
+/* Host helper: the real-frequency grid of a full-frequency calculation
+ * (epsilon section, frequency-grid figure): E = 0, spacing, 2 spacing, ...
+ * up to low_cutoff, then each step longer than the previous one by
+ * `increment`, up to high_cutoff (all in eV).  Writes min(maxn, count)
+ * points to E (HOST, may be NULL when maxn = 0) and the count to *n.
+ * BGW_ERR_ARG for spacing <= 0, negative cutoffs or increment, or
+ * high_cutoff < low_cutoff. */
+int bgw_ff_grid(double spacing, double low_cutoff, double high_cutoff, double increment, int maxn, double *E, int *n);
 
 /* Host helper: bulk bare Coulomb v(q+G) = 4 pi / |q+G|^2 (epsilon section,
  * untruncated bare-Coulomb equation).  bvec: HOST f64 [3][3], rows are the

@@ -27,13 +27,18 @@ BGW_ERR_NOMEM = -5
 BGW_ERR_UNSUPPORTED = -6
 FP64 = 0
 SPLIT_BF16 = 1
+AXIS_IMAG = 0
+AXIS_RETARDED = 1
+AXIS_ADVANCED = 2
+_AXES = {"imag": AXIS_IMAG, "retarded": AXIS_RETARDED, "advanced": AXIS_ADVANCED}
 
 # every symbol declared in include/bgw.h
 EXPORTS = [
     "bgw_version", "bgw_create", "bgw_destroy", "bgw_last_error", "bgw_workspace_bytes",
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
-    "bgw_tuned_config",
+    "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
+    "bgw_ff_grid",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -85,6 +90,8 @@ class ChiDesc(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("accumulate", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("axis", ctypes.c_int),
+        ("broadening", ctypes.c_double),
     ]
 
 
@@ -97,6 +104,16 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"native library {LIB_PATH} is missing; run __graft_entry__.build()")
+        # A process must hold one HIP runtime.  PyTorch ships its own
+        # libamdhip64 and asks for it by its unversioned name, so if this
+        # library were loaded first (binding the system runtime) a later
+        # torch import would map a second runtime and one of the two would
+        # find no device.  Loading torch first lets this library bind to
+        # torch's runtime through the shared soname.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.bgw_version.restype = I
@@ -116,9 +133,15 @@ def lib():
         L.bgw_pair_transform_box.argtypes = [ctypes.POINTER(PairDesc), ctypes.POINTER(ctypes.c_int)]
         L.bgw_autotune.argtypes = [P, ctypes.POINTER(ChiDesc), P]
         L.bgw_tuned_config.argtypes = [P, I, I, ctypes.c_longlong, ctypes.POINTER(ctypes.c_int)]
+        SZ = ctypes.POINTER(ctypes.c_size_t)
+        L.bgw_pair_density_workspace.argtypes = [P, ctypes.POINTER(PairDesc), SZ]
+        L.bgw_chi0_workspace.argtypes = [P, ctypes.POINTER(ChiDesc), SZ]
+        L.bgw_eps_inv_workspace.argtypes = [P, I, I, SZ]
+        L.bgw_ff_grid.argtypes = [D, D, D, D, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
         for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
-                  "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config"):
+                  "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
+                  "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -178,6 +201,16 @@ def pair_transform_box(n, gw, ge):
     return tuple(box)
 
 
+def ff_grid(spacing: float, low_cutoff: float, high_cutoff: float, increment: float) -> np.ndarray:
+    """Real-frequency grid (eV) of a full-frequency calculation (host only)."""
+    n = ctypes.c_int()
+    _check(lib().bgw_ff_grid(spacing, low_cutoff, high_cutoff, increment, 0, None, ctypes.byref(n)))
+    out = np.zeros(n.value)
+    _check(lib().bgw_ff_grid(spacing, low_cutoff, high_cutoff, increment, n.value,
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(n)))
+    return out
+
+
 def vcoul_bulk(bvec, q, ge) -> np.ndarray:
     bvec = np.ascontiguousarray(bvec, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.float64)
@@ -211,6 +244,27 @@ class Handle:
 
     def workspace_bytes(self) -> int:
         return int(lib().bgw_workspace_bytes(self._h))
+
+    def pair_density_workspace(self, n, gw, ge, cv, cc) -> int:
+        """Workspace bytes the next pair_density call with these arguments needs."""
+        d = make_pair_desc(n, gw, ge, cv, cc)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_pair_density_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
+        return int(out.value)
+
+    def chi0_workspace(self, qs, omega, precision: int = FP64, accumulate: bool = False, chis=None, axis="imag",
+                       broadening: float = 0.0) -> int:
+        """Workspace bytes the chi0 call with these arguments needs."""
+        d, outs, keep = self._chi_desc(qs, omega, precision, accumulate, chis, False, axis, broadening)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_chi0_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
+        del keep
+        return int(out.value)
+
+    def eps_inv_workspace(self, ng: int, nw: int) -> int:
+        out = ctypes.c_size_t()
+        _check(lib().bgw_eps_inv_workspace(self._h, int(ng), int(nw), ctypes.byref(out)))
+        return int(out.value)
 
     # ---------------------------------------------------------------- timing
     def set_timing(self, enable: bool = True):
@@ -248,7 +302,7 @@ class Handle:
 
     # ---------------------------------------------------------------- chi0
     def _chi_desc(self, qs: Sequence[dict], omega: Sequence[float], precision: int, accumulate: bool,
-                  chis: Optional[List], use_graph: bool):
+                  chis: Optional[List], use_graph: bool, axis="imag", broadening: float = 0.0):
         import torch
         om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1)
         arr = (ChiQ * len(qs))()
@@ -285,15 +339,19 @@ class Handle:
         d.precision = int(precision)
         d.accumulate = 1 if accumulate else 0
         d.use_graph = 1 if use_graph else 0
+        d.axis = _AXES[axis] if isinstance(axis, str) else int(axis)
+        d.broadening = float(broadening)
         return d, outs, keep
 
     def chi0(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64, accumulate: bool = False,
-             chis: Optional[List] = None, use_graph: bool = False):
+             chis: Optional[List] = None, use_graph: bool = False, axis="imag", broadening: float = 0.0):
         """qs: list of dicts {M, ev, ec, nk, nv, nc, head, prefactor} (device tensors); all q and all
         frequencies form one batch.  Returns the list of chi tensors [nw][ng][ng] (complex128).
         use_graph: capture the call into a HIP graph on first use of this exact descriptor and
-        replay it afterwards (the tensors' addresses are part of the descriptor)."""
-        d, outs, keep = self._chi_desc(qs, omega, precision, accumulate, chis, use_graph)
+        replay it afterwards (the tensors' addresses are part of the descriptor).
+        axis: "imag" (omega = |omega| on the imaginary axis), "retarded" or "advanced" (omega = real
+        frequencies E, broadening delta in eV)."""
+        d, outs, keep = self._chi_desc(qs, omega, precision, accumulate, chis, use_graph, axis, broadening)
         _check(lib().bgw_chi0(self._h, ctypes.byref(d), _stream()))
         del keep
         return outs

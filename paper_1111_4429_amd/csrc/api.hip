@@ -25,9 +25,6 @@ int launch_band_to_real(const double2 *C, int nbands, int ngw, const AxisPlan &,
 int launch_pair_fft(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
                     const AxisPlan &, const AxisPlan &, const SphereMaps &, int lc, double2 *M, long long row0,
                     hipStream_t);
-int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &,
-                     const AxisPlan &, const AxisPlan &, const int *ge_code2, const int *ge_out, int ng, int rey,
-                     int rez, double2 *M, long long row0, hipStream_t);
 size_t pair_yz_bytes_per_pair(int n1, int rey, int rez);
 size_t band_lines_bytes(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm,
                         int nbands);
@@ -135,7 +132,35 @@ extern "C" int bgw_vcoul_bulk(const double *bvec, const double *q, int ng, const
     return BGW_OK;
 }
 
-extern "C" int bgw_version(void) { return 100; }
+extern "C" int bgw_ff_grid(double spacing, double low_cutoff, double high_cutoff, double increment, int maxn,
+                           double *E, int *n) {
+    clear_error();
+    if (!(spacing > 0.0) || !(low_cutoff >= 0.0) || !(high_cutoff >= low_cutoff) || !(increment >= 0.0) || !n ||
+        maxn < 0 || (maxn > 0 && !E))
+        return fail(BGW_ERR_ARG, "bad frequency-grid parameters");
+    const double tol = 1e-12;
+    // uniform part: i * spacing up to the low cutoff
+    const long long nu = (long long)std::floor(low_cutoff / spacing * (1.0 + tol)) + 1;
+    std::vector<double> g;
+    for (long long i = 0; i < nu; ++i) g.push_back((double)i * spacing);
+    // then every step longer than the previous one by `increment`
+    double step = spacing, last = g.back();
+    if (increment > 0.0 || last + step <= high_cutoff * (1.0 + tol)) {
+        for (;;) {
+            step += increment;
+            const double nx = last + step;
+            if (nx > high_cutoff * (1.0 + tol)) break;
+            g.push_back(nx);
+            last = nx;
+            if (g.size() > 100000000) return fail(BGW_ERR_ARG, "frequency grid larger than 1e8 points");
+        }
+    }
+    *n = (int)g.size();
+    for (int i = 0; i < std::min<int>(maxn, (int)g.size()); ++i) E[i] = g[(size_t)i];
+    return BGW_OK;
+}
+
+extern "C" int bgw_version(void) { return 200; }
 
 extern "C" const char *bgw_last_error(void) { return g_err.c_str(); }
 
@@ -415,26 +440,35 @@ extern "C" int bgw_destroy(bgw_handle_t h) {
 
 extern "C" size_t bgw_workspace_bytes(bgw_handle_t h) { return h ? h->ws.bytes : 0; }
 
-extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream) {
-    BGW_TRY(bgw_pair_desc_check(d));
-    if (!h || !M) return fail(BGW_ERR_ARG, "null handle or output");
-    BGW_TRY(set_device(h));
-    hipStream_t st = (hipStream_t)stream;
+namespace bgw {
+
+// Everything bgw_pair_density decides on the host before it launches: the
+// transform plan, the k- and c-batches and the workspace carve-up.
+struct PairRun {
+    FFTPlan *pl = nullptr;
+    int lcb = 0, lcp = 0, ncb = 0, kb = 0;
+    bool two_pass = false, band_lines = false;
+    size_t N = 0, t_off = 0, w_off = 0, ws_need = 0;
+};
+
+static int plan_pair(bgw_handle_t h, const bgw_pair_desc *d, PairRun &R) {
     FFTPlan *pl = nullptr;
     BGW_TRY(get_plan(h, d, &pl));
+    R.pl = pl;
     const AxisPlan &px = pl->ax[0], &py = pl->ax[1], &pz = pl->ax[2];
     const int n2 = pl->box[1], n3 = pl->box[2];
     const size_t fixed_b = band_lds_bytes(px, py, pz, pl->sm.bwz, 0) + sizeof(int) * n3;
     const size_t fixed_p = pair_lds_bytes(px, py, pz, pl->sm.bez, 0);
-    const int lcb = pick_lc(n2, n3, fixed_b), lcp = pick_lc(n2, n3, fixed_p);
-    if (lcb < 1 || lcp < 1) return fail(BGW_ERR_UNSUPPORTED, "FFT grid/sphere too large for the LDS budget");
+    R.lcb = pick_lc(n2, n3, fixed_b);
+    R.lcp = pick_lc(n2, n3, fixed_p);
+    if (R.lcb < 1 || R.lcp < 1) return fail(BGW_ERR_UNSUPPORTED, "FFT grid/sphere too large for the LDS budget");
 
     const size_t N = (size_t)pl->box[0] * n2 * n3;
+    R.N = N;
     const size_t per_k = sizeof(double2) * N * (size_t)(d->nv + d->nc);
-    // two-pass transform (y,z pass -> T in workspace -> x pass) on the fast sizes,
-    // unless BGW_PAIR_FUSED=1 asks for the single-pass kernel
-    const char *fused_env = std::getenv("BGW_PAIR_FUSED");
-    const bool two_pass = !generic_fft() && !(fused_env && *fused_env == '1') && pair_two_pass_supported(py, pz);
+    // two-pass transform (y,z pass -> T in workspace -> x pass) on the fast sizes
+    const bool two_pass = !generic_fft() && pair_two_pass_supported(py, pz);
+    R.two_pass = two_pass;
     const size_t t_per_pair = pair_yz_bytes_per_pair(pl->box[0], pl->sm.rey, pl->sm.rez);
     size_t free_b = 0, total_b = 0;
     BGW_HIP(hipMemGetInfo(&free_b, &total_b));
@@ -445,17 +479,48 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
     if (two_pass) {
         ncb = (int)std::max<size_t>(1, std::min<size_t>((size_t)d->nc, t_cap / (t_per_pair * d->nv)));
     }
+    R.ncb = ncb;
     const size_t t_bytes_for = two_pass ? t_per_pair * (size_t)d->nv * ncb : 0;  // per k in the batch
     // x-stick results of the lane-per-line band path, reused by the valence and conduction launches
     const bool band_lines = !generic_fft() && band_lines_supported(px, py, pz, pl->sm);
+    R.band_lines = band_lines;
     const size_t w_per_k = band_lines ? band_lines_bytes(px, py, pz, pl->sm, std::max(d->nv, d->nc)) : 0;
     int kb = (int)std::min<size_t>((size_t)d->nk, budget / (per_k + t_bytes_for + w_per_k + 1));
     if (kb < 1) return fail(BGW_ERR_NOMEM, "workspace for one k-point of band grids does not fit");
     if (two_pass) kb = (int)std::min<size_t>((size_t)kb, std::max<size_t>(1, t_cap / (t_per_pair * d->nv * ncb)));
+    R.kb = kb;
     const size_t grid_bytes = per_k * kb;
-    const size_t t_off = ((grid_bytes + 255) / 256) * 256;
-    const size_t w_off = t_off + ((two_pass ? t_bytes_for * kb : 0) + 255) / 256 * 256;
-    BGW_TRY(ensure_ws(h, w_off + w_per_k * kb, st));
+    R.t_off = ((grid_bytes + 255) / 256) * 256;
+    R.w_off = R.t_off + ((two_pass ? t_bytes_for * kb : 0) + 255) / 256 * 256;
+    R.ws_need = R.w_off + w_per_k * kb;
+    return BGW_OK;
+}
+
+}  // namespace bgw
+
+extern "C" int bgw_pair_density_workspace(bgw_handle_t h, const bgw_pair_desc *d, size_t *bytes) {
+    BGW_TRY(bgw_pair_desc_check(d));
+    if (!h || !bytes) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    PairRun R;
+    BGW_TRY(plan_pair(h, d, R));
+    *bytes = R.ws_need;
+    return BGW_OK;
+}
+
+extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream) {
+    BGW_TRY(bgw_pair_desc_check(d));
+    if (!h || !M) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    PairRun R;
+    BGW_TRY(plan_pair(h, d, R));
+    FFTPlan *pl = R.pl;
+    const AxisPlan &px = pl->ax[0], &py = pl->ax[1], &pz = pl->ax[2];
+    const int lcb = R.lcb, lcp = R.lcp, ncb = R.ncb, kb = R.kb;
+    const bool two_pass = R.two_pass, band_lines = R.band_lines;
+    const size_t N = R.N, t_off = R.t_off, w_off = R.w_off;
+    BGW_TRY(ensure_ws(h, R.ws_need, st));
     double2 *gv = (double2 *)h->ws.p;
     double2 *T = (double2 *)((char *)h->ws.p + t_off);
     double2 *Wb = (double2 *)((char *)h->ws.p + w_off);
@@ -502,18 +567,34 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
             }
         } else {
             Timed tm(h, BGW_KERNEL_PAIR, st);
-            int rc = generic_fft() ? BGW_ERR_UNSUPPORTED
-                                   : launch_pair_fft2(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm.ge_code2,
-                                                      pl->sm.ge_out, d->ng, pl->sm.rey, pl->sm.rez, (double2 *)M, row0,
-                                                      st);
-            if (rc == BGW_ERR_UNSUPPORTED)
-                rc = launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M, row0, st);
-            BGW_TRY(rc);
+            BGW_TRY(launch_pair_fft(gv, gc, kn, d->nv, d->nc, px, py, pz, pl->sm, lcp, (double2 *)M, row0, st));
         }
     }
     return BGW_OK;
 }
 
+
+namespace bgw {
+// Matrices inverted per cooperative launch and the workspace the inversion needs.
+static void eps_plan(int ng, int nw, int *group, size_t *gws, size_t *need) {
+    *group = std::max(1, std::min(nw, gje_max_group(ng)));
+    const int rows = gje_rows_per_wg(ng);
+    const int R = (ng + rows - 1) / rows;
+    *gws = gje_workspace_bytes(ng, *group, R);
+    *need = *gws + sizeof(int) * 2 * (size_t)*group * ng + 512;
+}
+}  // namespace bgw
+
+extern "C" int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes) {
+    clear_error();
+    if (!h || ng < 1 || nw < 1 || !bytes) return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_workspace");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    BGW_TRY(set_device(h));
+    int group = 0;
+    size_t gws = 0;
+    eps_plan(ng, nw, &group, &gws, bytes);
+    return BGW_OK;
+}
 
 extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi, double *epsinv,
                            int *info, void *stream) {
@@ -523,11 +604,10 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
     if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
     BGW_TRY(set_device(h));
     hipStream_t st = (hipStream_t)stream;
-    const int group = std::max(1, std::min(nw, gje_max_group(ng)));
-    const int rows = gje_rows_per_wg(ng);
-    const int R = (ng + rows - 1) / rows;
-    const size_t gws = gje_workspace_bytes(ng, group, R);
-    BGW_TRY(ensure_ws(h, gws + sizeof(int) * 2 * (size_t)group * ng + 512, st));
+    int group = 0;
+    size_t gws = 0, need = 0;
+    eps_plan(ng, nw, &group, &gws, &need);
+    BGW_TRY(ensure_ws(h, need, st));
     int *ipiv = (int *)((char *)h->ws.p + ((gws + 255) / 256) * 256);
     {
         Timed tm(h, BGW_KERNEL_EPS_BUILD, st);

@@ -18,8 +18,14 @@ namespace bgw {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
-// w[t] = Delta_t / (Delta_t^2 + omega^2), Delta_t = (E_v,k+q - E_c,k) / Ha  (omega in Ha)
-// grid.y: problem; every block strides over that problem's pairs.
+// Energy weights of one vector, Delta_t = (E_v,k+q - E_c,k) / Ha (see WeightKind):
+//   imaginary axis:  w = Delta / (Delta^2 + omega^2)
+//   real axis:       the real or the imaginary part of
+//                    (1/2) [1/(Delta - E -+ i delta) + 1/(Delta + E +- i delta)],
+//                    with a = Delta - E, b = Delta + E:
+//                    Re = (a / (a^2 + delta^2) + b / (b^2 + delta^2)) / 2,
+//                    Im = +-(delta / (a^2 + delta^2) - delta / (b^2 + delta^2)) / 2.
+// grid.y: vector; every block strides over that vector's pairs.
 __global__ void k_weights(const WProb *__restrict__ probs) {
     const WProb P = probs[blockIdx.y];
     const long long K = (long long)P.nk * P.nv * P.nc;
@@ -28,7 +34,20 @@ __global__ void k_weights(const WProb *__restrict__ probs) {
         const long long c = t % P.nc, kv = t / P.nc;
         const long long k = kv / P.nv;
         const double d = (P.ev[kv] - P.ec[k * P.nc + c]) / kHartreeEv;
-        P.w[t] = d / (d * d + P.omega_ha * P.omega_ha);
+        double w;
+        if (P.kind == kWeightImag) {
+            w = d / (d * d + P.omega_ha * P.omega_ha);
+        } else {
+            const double a = d - P.omega_ha, b = d + P.omega_ha, dl = P.delta_ha;
+            const double da = a * a + dl * dl, db = b * b + dl * dl;
+            if (P.kind == kWeightRealRe) {
+                w = 0.5 * (a / da + b / db);
+            } else {
+                const double im = 0.5 * (dl / da - dl / db);
+                w = P.kind == kWeightRetIm ? im : -im;
+            }
+        }
+        P.w[t] = w;
     }
 }
 
@@ -165,12 +184,14 @@ __global__ __launch_bounds__(256, 3) void k_herk_f64(const HerkProb *__restrict_
     }
 }
 
-// chi[G][H] (+)= pf * sum_s part[s][G][H] for G <= H, conjugate mirror below the
-// diagonal, diagonal made exactly real; the split sum runs in fixed order.
-// In place (ns == 1): chi's upper triangle holds the raw sums and each
+// chi[G][H] (+)= pf * (A_GH + i B_GH), where A (and B, when part_im is set)
+// are Hermitian with raw upper-triangle sums part[s][G][H], G <= H, reduced
+// over the K splits s in fixed order; below the diagonal A_GH = conj(A_HG).
+// Without B (imaginary axis) chi is Hermitian and its diagonal exactly real.
+// In place (ns == 1, no B): chi's upper triangle holds the raw sums and each
 // thread reads (G, H), G <= H, and writes (G, H) and (H, G).  Row and column
 // `skip` (>= 0) are left untouched (written by the FP64 head kernel).
-// grid.y: problem.
+// grid.y: output matrix.
 __global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
     const FinProb P = probs[blockIdx.y];
     const int ng = P.ng;
@@ -193,11 +214,22 @@ __global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
         }
         const bool up = G <= H;
         const size_t src = up ? e : (size_t)H * ng + G;
-        double2 s = make_double2(0.0, 0.0);
+        double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
 #pragma unroll 8
-        for (int p = 0; p < P.ns; ++p) s = cadd(s, P.part[p * total + src]);
-        double2 val = make_double2(P.pf * s.x, up ? P.pf * s.y : -P.pf * s.y);
-        if (G == H) val.y = 0.0;
+        for (int p = 0; p < P.ns; ++p) a = cadd(a, P.part[p * total + src]);
+        if (P.part_im) {
+#pragma unroll 8
+            for (int p = 0; p < P.ns; ++p) b = cadd(b, P.part_im[p * total + src]);
+        }
+        if (!up) {
+            a.y = -a.y;
+            b.y = -b.y;
+        }
+        if (G == H) {
+            a.y = 0.0;
+            b.y = 0.0;
+        }
+        double2 val = make_double2(P.pf * (a.x - b.y), P.pf * (a.y + b.x));
         if (P.accumulate) val = cadd(P.chi[e], val);
         P.chi[e] = val;
     }

@@ -1,12 +1,17 @@
 // bgw_chi0 and bgw_autotune: planning of a batched chi0 call (all q of the
-// descriptor, all frequencies), its launch sequence, HIP-graph capture and
-// replay, and the tile autotuner with its optional JSON-lines cache.
+// descriptor, all frequencies, both frequency axes), its launch sequence,
+// HIP-graph capture and replay, and the tile autotuner with its optional
+// JSON-lines cache.
 //
-// FP64 path: one weights launch, one persistent rank-K-update launch over
-// every (q, omega, tile, K-split) work item and one finalize launch, whatever
-// the number of q and omega.  Split path: weights for all problems in one
-// launch, then per (q, omega) the slicing, the BF16 GEMM, the finalize and
-// the FP64 head row (the omega-independent slices are made once per q).
+// A weight vector is one (q, frequency) on the imaginary axis and one
+// (q, frequency, Re w / Im w) on the real axis.  FP64 path: one weights
+// launch, one persistent rank-K-update launch per tile size over every
+// (vector, tile, K-split) work item and one finalize launch, whatever the
+// number of q and frequencies.  Split path: one weights launch; per q the
+// frequency-independent digit slices; one persistent launch over every
+// (q, vector, tile, K-split) item of the q whose slices fit together (one
+// launch for the whole batch unless the device memory runs out); the FP64
+// head rows of every q; one finalize launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,7 +84,7 @@ void chi_state_free(ChiState *s) { delete s; }
 
 namespace {
 
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxGraphs = 64;
 constexpr int kHerkKC = 16;  // pairs per LDS stage of the FP64 kernel (split ranges are multiples of it)
 
 ChiState *state(bgw_handle_t h) {
@@ -159,7 +164,12 @@ int check_chi_desc(const bgw_chi_desc *d) {
     if (!d || d->nq < 1 || !d->q || d->nw < 1 || !d->omega) return fail(BGW_ERR_ARG, "bad chi descriptor");
     if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16)
         return fail(BGW_ERR_ARG, "unknown precision");
-    if ((long long)d->nq * d->nw > 65535) return fail(BGW_ERR_UNSUPPORTED, "more than 65535 (q, omega) problems");
+    if (d->axis != BGW_AXIS_IMAG && d->axis != BGW_AXIS_RETARDED && d->axis != BGW_AXIS_ADVANCED)
+        return fail(BGW_ERR_ARG, "unknown frequency axis");
+    if (d->axis != BGW_AXIS_IMAG && !(d->broadening > 0.0))
+        return fail(BGW_ERR_ARG, "the real frequency axis needs a broadening > 0");
+    const long long nvec = (long long)d->nq * d->nw * (d->axis == BGW_AXIS_IMAG ? 1 : 2);
+    if (nvec > 65535) return fail(BGW_ERR_UNSUPPORTED, "more than 65535 weight vectors (q x frequencies)");
     for (int i = 0; i < d->nw; ++i)
         if (!(d->omega[i] >= 0.0)) return fail(BGW_ERR_ARG, "frequencies must be >= 0");
     for (int i = 0; i < d->nq; ++i) {
@@ -174,107 +184,144 @@ int check_chi_desc(const bgw_chi_desc *d) {
 
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Everything one chi0 call launches, decided on the host.
-struct ChiPlan {
-    int precision = 0;
-    int nprob = 0;
-    std::vector<HerkProb> herk;  // FP64 only, ordered by first work item (tile 64, then tile 32)
-    std::vector<int> herk_prob;  // problem index of each herk entry
-    long long nitems64 = 0;      // items [0, nitems64) have tile 64
-    std::vector<FinProb> fin;
-    std::vector<WProb> wts;
-    std::vector<int> prob_q, prob_w;
-    long long nitems = 0, maxK = 0;
-    int maxng = 0, grid = 0;
-    // workspace offsets (bytes from the workspace base)
-    size_t off_w = 0, off_part = 0, off_split = 0, ws_bytes = 0;
-    std::vector<size_t> w_off, part_off;
-    std::vector<int> split_ns;  // tuned split override per problem
-    size_t table_bytes = 0;
+constexpr int kHeadSplits = 128;  // K ranges of the FP64 head rows (enough blocks to stream M at full rate)
+
+// One launch of the persistent split-precision GEMM: entries (q, chunk range).
+struct SplitLaunch {
+    std::vector<SplitQ> qs;      // table entries (pointers bound later)
+    std::vector<int> qidx;       // q of each entry
+    std::vector<size_t> sb_off;  // slices of each entry (offset in the slice region)
+    std::vector<size_t> ew_off;  // weighted-side exponents of each entry (offset in the EA region)
+    long long nitems = 0;
+    size_t tab_off = 0;          // offset of the entries in the device table
 };
 
-// Table layout in device memory: [HerkProb * nprob][FinProb * nprob][WProb * nprob].
-size_t table_size(int nprob) {
-    return al256(sizeof(HerkProb) * nprob) + al256(sizeof(FinProb) * nprob) + al256(sizeof(WProb) * nprob);
+// Everything one chi0 call launches, decided on the host.  A weight vector
+// is one (q, frequency) on the imaginary axis and one (q, frequency, Re/Im)
+// on the real axis; an output matrix is one (q, frequency).
+struct ChiPlan {
+    int precision = 0, axis = 0;
+    int vpq = 1;                 // weight vectors per (q, frequency): 1 or 2
+    int nvec = 0, nout = 0;
+    std::vector<WProb> wts;      // per vector, q-major, then frequency, then Re/Im
+    std::vector<size_t> w_off;   // per vector
+    std::vector<FinProb> fin;    // per output matrix
+    long long maxK = 0;
+    int maxng = 0;
+    // FP64
+    std::vector<HerkProb> herk;  // ordered by first work item (tile 64, then tile 32)
+    std::vector<int> herk_vec;   // vector of each herk entry
+    std::vector<size_t> vpart_off;  // FP64: per vector partial sums ((size_t)-1: in place)
+    long long nitems64 = 0, nitems = 0;
+    int grid = 0;
+    // split
+    std::vector<SplitLaunch> launches;
+    std::vector<std::vector<unsigned>> tiles;  // per q
+    std::vector<size_t> tiles_off;             // per q, in the device table
+    std::vector<size_t> qpart_off;             // per q: [nvec_q][ns][ng][ng] partial sums ((size_t)-1: in place)
+    std::vector<int> q_ns;
+    size_t off_slices = 0, off_ew = 0, off_hw = 0;
+    // workspace and table sizes
+    size_t ws_bytes = 0, table_bytes = 0;
+    size_t off_fin = 0, off_wts = 0, off_split = 0;  // table offsets
+};
+
+long long q_pairs(const bgw_chi_q &q) { return (long long)q.nk * q.nv * q.nc; }
+
+// Wave-filling rule shared by both precisions: at least `ipc` items per CU,
+// then the count whose last round of items fills the resident slots best
+// (smallest such count within 3% of the best makespan).
+long long choose_splits(long long base_items, long long slots, int ipc, long long cap) {
+    const long long cus = device_cus();
+    long long lo = std::max<long long>(1, ((long long)ipc * cus + base_items - 1) / base_items);
+    lo = std::min(lo, std::max<long long>(1, cap));
+    const long long hi = std::max(lo, std::min<long long>(cap, 32));
+    auto makespan = [&](long long n) { return (double)((base_items * n + slots - 1) / slots) / (double)n; };
+    double best = makespan(lo);
+    for (long long n = lo; n <= hi; ++n) best = std::min(best, makespan(n));
+    long long ns = lo;
+    while (ns < hi && makespan(ns) > 1.03 * best) ++ns;
+    return ns;
 }
 
 int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile, int force_ipc, int force_nsplit) {
     ChiState *s = state(h);
     load_cache(s);
     P.precision = d->precision;
-    P.nprob = d->nq * d->nw;
-    P.table_bytes = table_size(P.nprob);
+    P.axis = d->axis;
+    P.vpq = d->axis == BGW_AXIS_IMAG ? 1 : 2;
+    P.nvec = d->nq * d->nw * P.vpq;
+    P.nout = d->nq * d->nw;
+    const bool real_axis = d->axis != BGW_AXIS_IMAG;
+    const int cus = device_cus();
     size_t off = 0;
-    P.off_w = off;
+    // weight vectors
     for (int iq = 0; iq < d->nq; ++iq) {
         const bgw_chi_q &q = d->q[iq];
-        const long long K = (long long)q.nk * q.nv * q.nc;
+        const long long K = q_pairs(q);
         P.maxK = std::max(P.maxK, K);
         P.maxng = std::max(P.maxng, q.ng);
-        for (int iw = 0; iw < d->nw; ++iw) {
-            P.prob_q.push_back(iq);
-            P.prob_w.push_back(iw);
-            P.w_off.push_back(off);
-            off += al256(sizeof(double) * K);
-        }
+        for (int iw = 0; iw < d->nw; ++iw)
+            for (int part = 0; part < P.vpq; ++part) {
+                WProb wp;
+                wp.ev = q.ev;
+                wp.ec = q.ec;
+                wp.w = nullptr;
+                wp.omega_ha = d->omega[iw] / kHartreeEv;
+                wp.delta_ha = real_axis ? d->broadening / kHartreeEv : 0.0;
+                wp.nk = q.nk;
+                wp.nv = q.nv;
+                wp.nc = q.nc;
+                wp.kind = !real_axis ? kWeightImag
+                                     : (part == 0 ? kWeightRealRe
+                                                  : (d->axis == BGW_AXIS_RETARDED ? kWeightRetIm : kWeightAdvIm));
+                P.wts.push_back(wp);
+                P.w_off.push_back(off);
+                off += al256(sizeof(double) * (K + 128));  // padded: the split GEMM stages whole 16-pair steps
+            }
     }
-    P.off_part = off;
-    const int cus = device_cus();
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = (size_t)64 << 30;
     if (d->precision == BGW_FP64) {
-        // tiles per problem, then one K-split count for the batch
+        // tiles per vector, then one K-split count for the batch
         long long total_tiles = 0;
         int ipc = 0;
-        std::vector<int> tile(P.nprob);
+        std::vector<int> tile(P.nvec);
         if (!force_tile) {  // BGW_HERK_TILE=32|64 pins the FP64 output tile
             const char *env = std::getenv("BGW_HERK_TILE");
             if (env && (std::atoi(env) == 32 || std::atoi(env) == 64)) force_tile = std::atoi(env);
         }
-        for (int p = 0; p < P.nprob; ++p) {
-            const bgw_chi_q &q = d->q[P.prob_q[p]];
-            const long long K = (long long)q.nk * q.nv * q.nc;
-            const TuneEntry e = lookup(s, BGW_FP64, q.ng, K);
-            tile[p] = force_tile ? force_tile : e.tile;
+        for (int v = 0; v < P.nvec; ++v) {
+            const bgw_chi_q &q = d->q[v / (d->nw * P.vpq)];
+            const TuneEntry e = lookup(s, BGW_FP64, q.ng, q_pairs(q));
+            tile[v] = force_tile ? force_tile : e.tile;
             ipc = std::max(ipc, force_ipc ? force_ipc : e.ipc);
-            const long long nt = (q.ng + tile[p] - 1) / tile[p];
+            const long long nt = (q.ng + tile[v] - 1) / tile[v];
             total_tiles += nt * (nt + 1) / 2;
         }
-        // K splits: at least ipc work items per CU, then the count whose last
-        // round of items fills the resident block slots best (smallest such
-        // count within 3% of the best makespan)
         const long long slots = (long long)cus * herk_blocks_per_cu();
-        const long long ns_min = std::min<long long>(64, std::max<long long>(1, ((long long)ipc * cus + total_tiles - 1) / total_tiles));
-        auto makespan = [&](long long n) { return (double)((total_tiles * n + slots - 1) / slots) / (double)n; };
-        double best = makespan(ns_min);
-        for (long long n = ns_min; n <= std::max<long long>(ns_min, 32); ++n) best = std::min(best, makespan(n));
-        long long ns = ns_min;
-        while (makespan(ns) > 1.03 * best) ++ns;
+        long long ns = choose_splits(total_tiles, slots, ipc, 64);
         // keep the partial sums within a quarter of the device memory
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) total_b = (size_t)64 << 30;
         for (;;) {
             size_t part = 0;
-            for (int p = 0; p < P.nprob; ++p) {
-                const bgw_chi_q &q = d->q[P.prob_q[p]];
-                const long long K = (long long)q.nk * q.nv * q.nc;
-                const long long nsp = std::min<long long>(ns, std::max<long long>(1, K / (8 * kHerkKC)));
-                if (nsp > 1 || d->accumulate) part += al256(sizeof(double2) * (size_t)nsp * q.ng * q.ng);
+            for (int v = 0; v < P.nvec; ++v) {
+                const bgw_chi_q &q = d->q[v / (d->nw * P.vpq)];
+                const long long nsp = std::min<long long>(ns, std::max<long long>(1, q_pairs(q) / (8 * kHerkKC)));
+                if (nsp > 1 || d->accumulate || real_axis) part += al256(sizeof(double2) * (size_t)nsp * q.ng * q.ng);
             }
             if (ns == 1 || part <= total_b / 4) break;
             ns = std::max<long long>(1, ns / 2);
         }
-        // per-problem split ranges; items numbered tile-64 problems first so
-        // that each tile size is one contiguous item range (one launch each)
-        std::vector<HerkProb> hps(P.nprob);
-        for (int p = 0; p < P.nprob; ++p) {
-            const int iq = P.prob_q[p], iw = P.prob_w[p];
+        std::vector<HerkProb> hps(P.nvec);
+        for (int v = 0; v < P.nvec; ++v) {
+            const int iq = v / (d->nw * P.vpq), iw = (v / P.vpq) % d->nw;
             const bgw_chi_q &q = d->q[iq];
-            const long long K = (long long)q.nk * q.nv * q.nc;
+            const long long K = q_pairs(q);
             long long nsp = std::min<long long>(ns, std::max<long long>(1, K / (8 * kHerkKC)));
             long long kper = (K + nsp - 1) / nsp;
             kper = (kper + kHerkKC - 1) / kHerkKC * kHerkKC;
             nsp = (K + kper - 1) / kper;
-            double2 *chi = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
-            const bool inplace = nsp == 1 && !d->accumulate;
+            const bool inplace = nsp == 1 && !d->accumulate && !real_axis;
             HerkProb hp;
             hp.M = (const double2 *)q.M;
             hp.w = nullptr;  // set once the workspace base is known
@@ -282,190 +329,315 @@ int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile,
             hp.kper = kper;
             hp.item0 = 0;
             hp.ng = q.ng;
-            hp.tile = tile[p];
-            hp.nt = (q.ng + tile[p] - 1) / tile[p];
+            hp.tile = tile[v];
+            hp.nt = (q.ng + tile[v] - 1) / tile[v];
             hp.ns = (int)nsp;
             if (inplace) {
-                hp.out = chi;
-                P.part_off.push_back((size_t)-1);
+                hp.out = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
+                P.vpart_off.push_back((size_t)-1);
             } else {
                 hp.out = nullptr;
-                P.part_off.push_back(off);
+                P.vpart_off.push_back(off);
                 off += al256(sizeof(double2) * (size_t)nsp * q.ng * q.ng);
             }
-            hps[p] = hp;
+            hps[v] = hp;
+        }
+        for (int o = 0; o < P.nout; ++o) {
+            const int iq = o / d->nw, iw = o % d->nw;
+            const bgw_chi_q &q = d->q[iq];
+            const int va = o * P.vpq;
             FinProb fp;
             fp.part = nullptr;
-            fp.chi = chi;
+            fp.part_im = nullptr;
+            fp.chi = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
             fp.pf = q.prefactor;
-            fp.ns = (int)nsp;
+            fp.ns = hps[va].ns;
             fp.ng = q.ng;
             fp.accumulate = d->accumulate;
             fp.skip = -1;
-            fp.inplace = inplace ? 1 : 0;
+            fp.inplace = P.vpart_off[va] == (size_t)-1 ? 1 : 0;
             fp.pad = 0;
             P.fin.push_back(fp);
         }
         long long item0 = 0;
         for (int t : {64, 32}) {
-            for (int p = 0; p < P.nprob; ++p) {
-                if (hps[p].tile != t) continue;
-                hps[p].item0 = item0;
-                hps[p].nitems = ((long long)hps[p].nt * (hps[p].nt + 1) / 2 * hps[p].ns + 7) / 8 * 8;
-                item0 += hps[p].nitems;
-                P.herk.push_back(hps[p]);
-                P.herk_prob.push_back(p);
+            for (int v = 0; v < P.nvec; ++v) {
+                if (hps[v].tile != t) continue;
+                hps[v].item0 = item0;
+                hps[v].nitems = ((long long)hps[v].nt * (hps[v].nt + 1) / 2 * hps[v].ns + 7) / 8 * 8;
+                item0 += hps[v].nitems;
+                P.herk.push_back(hps[v]);
+                P.herk_vec.push_back(v);
             }
             if (t == 64) P.nitems64 = item0;
         }
         P.nitems = item0;
         P.grid = (int)(slots / 8 * 8);  // a multiple of 8: item i stays on XCD i % 8
-        P.off_split = off;
     } else {
-        P.off_split = off;
-        size_t split_need = 0;
-        for (int p = 0; p < P.nprob; ++p) {
-            const bgw_chi_q &q = d->q[P.prob_q[p]];
-            const long long K = (long long)q.nk * q.nv * q.nc;
-            const TuneEntry e = lookup(s, BGW_SPLIT_BF16, q.ng, K);
+        // ---- split precision: per q the K-split count, the partial sums and the tile walk
+        const int vq = d->nw * P.vpq;  // weight vectors per q
+        const long long slots = split_grid();
+        long long base_items = 0;
+        for (int iq = 0; iq < d->nq; ++iq) {
+            P.tiles.emplace_back();
+            split_tiles(d->q[iq].ng, P.tiles.back());
+            base_items += (long long)P.tiles.back().size() * vq;
+        }
+        // K splits per q: the wave-filling rule over the whole batch (or the tuned count)
+        P.q_ns.assign(d->nq, 1);
+        for (int iq = 0; iq < d->nq; ++iq) {
+            const bgw_chi_q &q = d->q[iq];
+            const TuneEntry e = lookup(s, BGW_SPLIT_BF16, q.ng, q_pairs(q));
             const int nso = force_nsplit ? force_nsplit : e.nsplit;
-            P.split_ns.push_back(nso);
-            size_t b = 0;
-            BGW_TRY(split_workspace_bytes(K, q.ng, nso, &b));
-            split_need = std::max(split_need, b);
+            const long long ns = nso > 0 ? nso : choose_splits(base_items, slots, 4, 64);
+            P.q_ns[iq] = (int)std::max<long long>(1, std::min<long long>(ns, split_chunks(q_pairs(q))));
+        }
+        // partial sums per q (none when the raw sums can go straight into chi)
+        auto part_bytes = [&](int iq) {
+            return al256(sizeof(double2) * (size_t)vq * P.q_ns[iq] * d->q[iq].ng * d->q[iq].ng);
+        };
+        P.qpart_off.assign(d->nq, (size_t)-1);
+        for (int iq = 0; iq < d->nq; ++iq) {
+            if (P.q_ns[iq] == 1 && !d->accumulate && !real_axis) continue;
+            P.qpart_off[iq] = off;
+            off += part_bytes(iq);
+        }
+        size_t hw = 0, ew_all = 0;
+        for (int iq = 0; iq < d->nq; ++iq) {
+            if (d->q[iq].head >= 0) hw = std::max(hw, sizeof(double2) * (size_t)kHeadSplits * vq * d->q[iq].ng);
+            ew_all += al256((size_t)vq * split_chunks(q_pairs(d->q[iq])) * split_gpad(d->q[iq].ng));
+        }
+        // slice budget: what the device holds next to everything else of the call
+        const size_t other = off + al256(hw) + ew_all + ((size_t)2 << 30);
+        const size_t avail = (size_t)(0.9 * (double)(free_b + h->ws.bytes));
+        size_t budget = avail > other + ((size_t)1 << 30) ? avail - other : ((size_t)1 << 30);
+        if (const char *env = std::getenv("BGW_SPLIT_SLICE_BYTES"))
+            budget = std::max<size_t>(1, std::strtoull(env, nullptr, 10));
+        // launches: consecutive q whose slices fit together; a q too large alone
+        // is cut into chunk ranges (one launch each, later ones adding)
+        std::vector<std::pair<int, std::pair<long long, long long>>> ranges;  // (q, [c0, c1))
+        for (int iq = 0; iq < d->nq; ++iq) {
+            const long long nch = split_chunks(q_pairs(d->q[iq]));
+            const size_t per_chunk = split_slice_bytes(1, d->q[iq].ng);
+            long long fit = std::max<long long>(1, (long long)(budget / per_chunk));
+            if (fit < nch) fit = std::max<long long>(fit, P.q_ns[iq]);  // the first range initialises every split
+            for (long long c0 = 0; c0 < nch; c0 += fit) ranges.push_back({iq, {c0, std::min(nch, c0 + fit)}});
+        }
+        size_t slice_max = 0, ew_max = 0;
+        {
+            SplitLaunch cur;
+            size_t cur_bytes = 0, cur_ew = 0;
+            auto close = [&]() {
+                if (cur.qs.empty()) return;
+                slice_max = std::max(slice_max, cur_bytes);
+                ew_max = std::max(ew_max, cur_ew);
+                P.launches.push_back(cur);
+                cur = SplitLaunch();
+                cur_bytes = cur_ew = 0;
+            };
+            for (auto &r : ranges) {
+                const int iq = r.first;
+                const long long nchr = r.second.second - r.second.first;
+                const size_t b = al256(split_slice_bytes(nchr, d->q[iq].ng));
+                const bool whole = r.second.first == 0 && r.second.second == split_chunks(q_pairs(d->q[iq]));
+                if (!cur.qs.empty() && (!whole || cur_bytes + b > budget)) close();
+                SplitQ e;
+                std::memset(&e, 0, sizeof(e));
+                e.chunk0 = (int)r.second.first;
+                e.nch = (int)nchr;
+                cur.qs.push_back(e);
+                cur.qidx.push_back(iq);
+                cur.sb_off.push_back(cur_bytes);
+                cur.ew_off.push_back(cur_ew);
+                cur_bytes += b;
+                cur_ew += al256((size_t)vq * nchr * split_gpad(d->q[iq].ng));
+                if (!whole) close();
+                if (!whole && P.qpart_off[iq] == (size_t)-1) {  // several launches: sums through partials
+                    P.qpart_off[iq] = off;
+                    off += part_bytes(iq);
+                }
+            }
+            close();
+        }
+        // fill the launch entries (workspace pointers are bound later)
+        std::vector<int> seen(d->nq, 0);
+        for (auto &L : P.launches) {
+            long long item0 = 0;
+            for (size_t i = 0; i < L.qs.size(); ++i) {
+                const int iq = L.qidx[i];
+                const bgw_chi_q &q = d->q[iq];
+                SplitQ &e = L.qs[i];
+                e.M = (const double2 *)q.M;
+                e.K = q_pairs(q);
+                e.ng = q.ng;
+                e.gpad = split_gpad(q.ng);
+                e.nvec = vq;
+                e.ntiles = (int)P.tiles[iq].size();
+                // every split non-empty; the first range of a q holds >= q_ns chunks, so it
+                // writes all q_ns partial sums that the finalize reads
+                e.ns = std::min<int>(P.q_ns[iq], e.nch);
+                e.add = seen[iq] ? 1 : 0;
+                seen[iq] = 1;
+                e.item0 = item0;
+                e.nitems = ((long long)e.ntiles * e.ns * e.nvec + 7) / 8 * 8;
+                item0 += e.nitems;
+            }
+            L.nitems = item0;
+        }
+        for (int o = 0; o < P.nout; ++o) {
+            const int iq = o / d->nw, iw = o % d->nw;
+            const bgw_chi_q &q = d->q[iq];
             FinProb fp;
-            fp.part = nullptr;  // split partial sums, set at launch time
-            fp.chi = (double2 *)q.chi + (size_t)P.prob_w[p] * q.ng * q.ng;
+            fp.part = nullptr;  // bound later
+            fp.part_im = nullptr;
+            fp.chi = (double2 *)q.chi + (size_t)iw * q.ng * q.ng;
             fp.pf = q.prefactor;
-            fp.ns = 0;
+            fp.ns = P.q_ns[iq];
             fp.ng = q.ng;
             fp.accumulate = d->accumulate;
             fp.skip = q.head;
-            fp.inplace = 0;
+            fp.inplace = P.qpart_off[iq] == (size_t)-1 ? 1 : 0;
             fp.pad = 0;
             P.fin.push_back(fp);
         }
-        off += al256(split_need + 256);
+        P.off_slices = off;
+        off += al256(slice_max);
+        P.off_ew = off;
+        off += al256(ew_max);
+        P.off_hw = off;
+        off += al256(hw);
     }
-    for (int p = 0; p < P.nprob; ++p) {
-        const bgw_chi_q &q = d->q[P.prob_q[p]];
-        WProb wp;
-        wp.ev = q.ev;
-        wp.ec = q.ec;
-        wp.w = nullptr;
-        wp.omega_ha = d->omega[P.prob_w[p]] / kHartreeEv;
-        wp.nk = q.nk;
-        wp.nv = q.nv;
-        wp.nc = q.nc;
-        wp.pad = 0;
-        P.wts.push_back(wp);
+    // device table: [HerkProb * nvec][FinProb * nout][WProb * nvec][SplitQ ...][tile walks]
+    size_t t = al256(sizeof(HerkProb) * P.herk.size());
+    P.off_fin = t;
+    t += al256(sizeof(FinProb) * P.nout);
+    P.off_wts = t;
+    t += al256(sizeof(WProb) * P.nvec);
+    P.off_split = t;
+    for (auto &L : P.launches) {
+        L.tab_off = t;
+        t += al256(sizeof(SplitQ) * L.qs.size());
     }
+    for (auto &tl : P.tiles) {
+        P.tiles_off.push_back(t);
+        t += al256(sizeof(unsigned) * tl.size());
+    }
+    P.table_bytes = std::max<size_t>(t, 256);
     P.ws_bytes = off + 256;
     return BGW_OK;
 }
 
-// Fill the workspace-dependent pointers of the tables.
-void bind_plan(ChiPlan &P, char *ws) {
-    for (int p = 0; p < P.nprob; ++p) {
-        double *w = (double *)(ws + P.w_off[p]);
-        P.wts[p].w = w;
-    }
-    for (size_t i = 0; i < P.herk.size(); ++i) {
-        const int p = P.herk_prob[i];
-        P.herk[i].w = P.wts[p].w;
-        if (P.part_off[p] != (size_t)-1) {
-            P.herk[i].out = (double2 *)(ws + P.part_off[p]);
-            P.fin[p].part = P.herk[i].out;
+// Fill the workspace- and table-dependent pointers: ws is the workspace base,
+// tab the device table base the kernels will read.
+void bind_plan(const bgw_chi_desc *d, ChiPlan &P, char *ws, char *tab) {
+    for (int v = 0; v < P.nvec; ++v) P.wts[v].w = (double *)(ws + P.w_off[v]);
+    const int vq = d->nw * P.vpq;
+    if (P.precision == BGW_FP64) {
+        std::vector<double2 *> vout(P.nvec, nullptr);
+        for (size_t i = 0; i < P.herk.size(); ++i) {
+            const int v = P.herk_vec[i];
+            P.herk[i].w = P.wts[v].w;
+            if (P.vpart_off[v] != (size_t)-1) P.herk[i].out = (double2 *)(ws + P.vpart_off[v]);
+            vout[v] = P.herk[i].out;
         }
+        for (int o = 0; o < P.nout; ++o) {
+            const int va = o * P.vpq;
+            if (!P.fin[o].inplace) P.fin[o].part = vout[va];
+            if (P.vpq == 2) P.fin[o].part_im = vout[va + 1];
+        }
+        return;
+    }
+    for (auto &L : P.launches)
+        for (size_t i = 0; i < L.qs.size(); ++i) {
+            const int iq = L.qidx[i];
+            const bgw_chi_q &q = d->q[iq];
+            SplitQ &e = L.qs[i];
+            e.w = P.wts[iq * vq].w;
+            e.wstride = vq > 1 ? (long long)((P.w_off[iq * vq + 1] - P.w_off[iq * vq]) / sizeof(double)) : 0;
+            e.SB = (const unsigned short *)(ws + P.off_slices + L.sb_off[i]);
+            e.EB = (const int *)(ws + P.off_slices + L.sb_off[i] + split_slices_only_bytes(e.nch, e.ng));
+            e.EA = (const signed char *)(ws + P.off_ew + L.ew_off[i]);
+            e.out = P.qpart_off[iq] == (size_t)-1 ? (double2 *)q.chi : (double2 *)(ws + P.qpart_off[iq]);
+            e.vstride = (long long)(P.qpart_off[iq] == (size_t)-1 ? 1 : P.q_ns[iq]) * q.ng * q.ng;
+            e.tiles = (const unsigned *)(tab + P.tiles_off[iq]);
+        }
+    for (int o = 0; o < P.nout; ++o) {
+        const int iq = o / d->nw, iw = o % d->nw;
+        if (P.qpart_off[iq] == (size_t)-1) continue;
+        const bgw_chi_q &q = d->q[iq];
+        double2 *base = (double2 *)(ws + P.qpart_off[iq]);
+        const size_t blk = (size_t)P.q_ns[iq] * q.ng * q.ng;
+        P.fin[o].part = base + (size_t)(iw * P.vpq) * blk;
+        if (P.vpq == 2) P.fin[o].part_im = base + (size_t)(iw * P.vpq + 1) * blk;
     }
 }
 
 void write_tables(const ChiPlan &P, void *host) {
     char *b = (char *)host;
     std::memset(b, 0, P.table_bytes);
-    if (!P.herk.empty()) std::memcpy(b, P.herk.data(), sizeof(HerkProb) * P.nprob);
-    b += al256(sizeof(HerkProb) * P.nprob);
-    std::memcpy(b, P.fin.data(), sizeof(FinProb) * P.nprob);
-    b += al256(sizeof(FinProb) * P.nprob);
-    std::memcpy(b, P.wts.data(), sizeof(WProb) * P.nprob);
+    if (!P.herk.empty()) std::memcpy(b, P.herk.data(), sizeof(HerkProb) * P.herk.size());
+    std::memcpy(b + P.off_fin, P.fin.data(), sizeof(FinProb) * P.nout);
+    std::memcpy(b + P.off_wts, P.wts.data(), sizeof(WProb) * P.nvec);
+    for (auto &L : P.launches) std::memcpy(b + L.tab_off, L.qs.data(), sizeof(SplitQ) * L.qs.size());
+    for (size_t i = 0; i < P.tiles.size(); ++i)
+        std::memcpy(b + P.tiles_off[i], P.tiles[i].data(), sizeof(unsigned) * P.tiles[i].size());
 }
 
-// The launch sequence of one chi0 call.  tab: device copy of the tables (for
-// the split path the finalize entries' part pointers are patched on the host
-// copy `P` and re-sent per problem through `patch`).
+// The launch sequence of one chi0 call (tables already in device memory at tab).
 int enqueue(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, char *ws, char *tab, hipStream_t st) {
     const HerkProb *dherk = (const HerkProb *)tab;
-    FinProb *dfin = (FinProb *)(tab + al256(sizeof(HerkProb) * P.nprob));
-    const WProb *dw = (const WProb *)((char *)dfin + al256(sizeof(FinProb) * P.nprob));
+    const FinProb *dfin = (const FinProb *)(tab + P.off_fin);
+    const WProb *dw = (const WProb *)(tab + P.off_wts);
     {
         Timed tm(h, BGW_KERNEL_WEIGHTS, st);
-        BGW_TRY(launch_weights_batch(dw, P.nprob, P.maxK, st));
+        BGW_TRY(launch_weights_batch(dw, P.nvec, P.maxK, st));
     }
     if (P.precision == BGW_FP64) {
         {
             Timed tm(h, BGW_KERNEL_HERK, st);
-            BGW_TRY(launch_herk_batch(dherk, P.nprob, 0, P.nitems64, 64, P.grid, st));
-            BGW_TRY(launch_herk_batch(dherk, P.nprob, P.nitems64, P.nitems, 32, P.grid, st));
+            const int nh = (int)P.herk.size();
+            BGW_TRY(launch_herk_batch(dherk, nh, 0, P.nitems64, 64, P.grid, st));
+            BGW_TRY(launch_herk_batch(dherk, nh, P.nitems64, P.nitems, 32, P.grid, st));
         }
         Timed tm(h, BGW_KERNEL_FINALIZE, st);
-        BGW_TRY(launch_finalize_batch(dfin, P.nprob, P.maxng, st));
+        BGW_TRY(launch_finalize_batch(dfin, P.nout, P.maxng, st));
         return BGW_OK;
     }
-    // split precision, problem by problem (q-major, omega-minor)
-    void *sws = ws + P.off_split;
-    for (int p = 0; p < P.nprob; ++p) {
-        const int iq = P.prob_q[p], iw = P.prob_w[p];
-        const bgw_chi_q &q = d->q[iq];
-        const long long K = (long long)q.nk * q.nv * q.nc;
-        const double *w = P.wts[p].w;
-        const SplitLayout L = split_layout(K, q.ng, P.split_ns[p], sws);
-        // the slices of the unweighted side do not depend on omega: with a
-        // single super-chunk they are made once per q
-        const bool resident_b = L.sc_pairs >= K;
-        int nslots = 0;
-        for (long long t0 = 0; t0 < K; t0 += L.sc_pairs) {
-            const long long kn = std::min<long long>(L.sc_pairs, K - t0);
-            const int nch = (int)((kn + 127) / 128);
-            {
-                Timed tm(h, BGW_KERNEL_SPLIT_SLICE, st);
-                BGW_TRY(launch_split_slices(L, (const double2 *)q.M, K, q.ng, w, t0, nch, !(resident_b && iw > 0),
-                                            st));
-            }
-            Timed tm(h, BGW_KERNEL_SPLIT_HERK, st);
-            int used = 0;
-            BGW_TRY(launch_split_gemm(L, q.ng, nch, nslots, &used, st));
-            if (!nslots) nslots = used;
-        }
-        if (P.fin[p].ns != nslots || P.fin[p].part != L.part) return fail(BGW_ERR_HIP, "split plan mismatch");
+    const int vq = d->nw * P.vpq;
+    std::vector<int> remaining(d->nq, 0);
+    for (auto &L : P.launches)
+        for (int qi : L.qidx) ++remaining[qi];
+    for (auto &L : P.launches) {
         {
-            Timed tm(h, BGW_KERNEL_FINALIZE, st);
-            BGW_TRY(launch_finalize_batch(dfin + p, 1, q.ng, st));
+            Timed tm(h, BGW_KERNEL_SPLIT_SLICE, st);
+            for (size_t i = 0; i < L.qs.size(); ++i) {
+                const SplitQ &e = L.qs[i];
+                BGW_TRY(launch_split_slices(e.M, e.K, e.ng, e.chunk0, e.nch, (unsigned short *)e.SB, (int *)e.EB, e.w,
+                                            e.wstride, e.nvec, (signed char *)e.EA, st));
+            }
         }
-        if (q.head >= 0) {
+        {
+            Timed tm(h, BGW_KERNEL_SPLIT_HERK, st);
+            BGW_TRY(launch_chi_split((const SplitQ *)(tab + L.tab_off), (int)L.qs.size(), L.nitems, st));
+        }
+        // FP64 head rows of every q whose sums are complete
+        for (size_t i = 0; i < L.qs.size(); ++i) {
+            const int iq = L.qidx[i];
+            if (--remaining[iq] > 0) continue;
+            const bgw_chi_q &q = d->q[iq];
+            if (q.head < 0) continue;
+            const SplitQ &e = L.qs[i];
             Timed tm(h, BGW_KERNEL_HEADWING, st);
-            BGW_TRY(launch_split_headwing(L, (const double2 *)q.M, K, q.ng, q.head, w, q.prefactor,
-                                          (double2 *)P.fin[p].chi, d->accumulate, st));
+            double2 *hw = (double2 *)(ws + P.off_hw);
+            BGW_TRY(launch_headwing(e.M, e.K, q.ng, q.head, e.w, e.wstride, vq, kHeadSplits, hw, st));
+            // the finalize skips row/column head, so these writes may come first
+            BGW_TRY(launch_headwing_write(hw, kHeadSplits, vq, q.ng, q.head, q.prefactor, (double2 *)q.chi, d->nw,
+                                          P.vpq == 2 ? 1 : 0, d->accumulate, st));
         }
     }
+    Timed tm(h, BGW_KERNEL_FINALIZE, st);
+    BGW_TRY(launch_finalize_batch(dfin, P.nout, P.maxng, st));
     return BGW_OK;
-}
-
-// The split layout's partial-sum pointer and slot count are fixed by the
-// plan: fill them into the finalize entries before the tables are sent.
-void bind_split(const bgw_chi_desc *d, ChiPlan &P, char *ws) {
-    if (P.precision != BGW_SPLIT_BF16) return;
-    for (int p = 0; p < P.nprob; ++p) {
-        const bgw_chi_q &q = d->q[P.prob_q[p]];
-        const long long K = (long long)q.nk * q.nv * q.nc;
-        const SplitLayout L = split_layout(K, q.ng, P.split_ns[p], ws + P.off_split);
-        // slots used by the first super-chunk (the largest): same rule as launch_split_gemm
-        const long long nch = std::min<long long>(L.sc_pairs, K) / 128 + ((std::min<long long>(L.sc_pairs, K) % 128) != 0);
-        int ns = (int)std::min<long long>(L.nsplit, nch);
-        const int cps = (int)((nch + ns - 1) / ns);
-        ns = (int)((nch + cps - 1) / cps);
-        P.fin[p].part = L.part;
-        P.fin[p].ns = ns;
-    }
 }
 
 unsigned long long fnv(unsigned long long hsh, const void *p, size_t n) {
@@ -482,6 +654,8 @@ unsigned long long desc_key(bgw_handle_t h, const bgw_chi_desc *d) {
     k = fnv(k, d->omega, sizeof(double) * d->nw);
     k = fnv(k, &d->precision, sizeof(int));
     k = fnv(k, &d->accumulate, sizeof(int));
+    k = fnv(k, &d->axis, sizeof(int));
+    k = fnv(k, &d->broadening, sizeof(double));
     k = fnv(k, &h->ws.p, sizeof(void *));
     k = fnv(k, &h->ws.bytes, sizeof(size_t));
     k = fnv(k, &h->chi->generation, sizeof(unsigned));
@@ -492,8 +666,6 @@ int run_eager(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, hipStream_t st)
     ChiState *s = state(h);
     BGW_TRY(ensure_ws(h, P.ws_bytes, st));
     char *ws = (char *)h->ws.p;
-    bind_plan(P, ws);
-    bind_split(d, P, ws);
     if (s->tables.bytes < P.table_bytes) {
         BGW_HIP(hipStreamSynchronize(st));
         if (s->tables.p) BGW_HIP(hipFree(s->tables.p));
@@ -514,6 +686,7 @@ int run_eager(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, hipStream_t st)
         s->pinned_bytes = P.table_bytes;
     }
     if (!s->pinned_done) BGW_HIP(hipEventCreateWithFlags(&s->pinned_done, hipEventDisableTiming));
+    bind_plan(d, P, ws, (char *)s->tables.p);
     write_tables(P, s->pinned);
     BGW_HIP(hipMemcpyAsync(s->tables.p, s->pinned, P.table_bytes, hipMemcpyHostToDevice, st));
     BGW_HIP(hipEventRecord(s->pinned_done, st));
@@ -531,12 +704,11 @@ int run_graph(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, hipStream_t st)
             return BGW_OK;
         }
     char *ws = (char *)h->ws.p;
-    bind_plan(P, ws);
-    bind_split(d, P, ws);
     auto g = std::make_unique<GraphEntry>();
     g->key = key;
     BGW_HIP(hipMalloc(&g->tables.p, P.table_bytes));
     g->tables.bytes = P.table_bytes;
+    bind_plan(d, P, ws, (char *)g->tables.p);
     std::vector<char> host(P.table_bytes);
     write_tables(P, host.data());
     BGW_HIP(hipMemcpy(g->tables.p, host.data(), P.table_bytes, hipMemcpyHostToDevice));
@@ -586,6 +758,17 @@ extern "C" int bgw_chi0(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
     return run_eager(h, d, P, st);
 }
 
+extern "C" int bgw_chi0_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t *bytes) {
+    clear_error();
+    BGW_TRY(check_chi_desc(d));
+    if (!h || !bytes) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    ChiPlan P;
+    BGW_TRY(make_plan(h, d, P, 0, 0, 0));
+    *bytes = P.ws_bytes;
+    return BGW_OK;
+}
+
 extern "C" int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
     clear_error();
     BGW_TRY(check_chi_desc(d));
@@ -626,7 +809,7 @@ extern "C" int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream)
             for (int tile : {32, 64})
                 for (int ipc : {2, 8, 32}) cands.emplace_back(tile, ipc, 0);
         } else {
-            for (int ns : {8, 16, 24, 32}) cands.emplace_back(0, 0, ns);
+            for (int ns : {1, 2, 4, 8, 16}) cands.emplace_back(0, 0, ns);
         }
         TuneEntry best;
         best.ms = 1e300;

@@ -86,16 +86,24 @@ struct SphereMaps {
     bool sticks_contiguous;
 };
 
-// Workspace carve-up of the split-precision chi sum (split.hip).
-struct SplitLayout {
-    int gpad, nt;
-    long long tiles;
-    long long sc_pairs;      // pairs per slice super-chunk (multiple of 128)
-    int nsplit;              // split slots of the partial sums
-    unsigned short *SA, *SB; // BF16 digit slices of X_w and X
-    int *EA, *EB;            // chunk-column exponents
-    double2 *part;           // [nsplit][ng][ng] FP64 partial sums
-    double2 *hw;             // FP64 head-row partials
+// One q of a split-precision chi-sum launch (split.hip), a device table
+// entry.  The launch covers the pair chunks [chunk0, chunk0 + nch) of every
+// entry (96 pairs per chunk) and, per entry, all of its weight vectors.
+struct SplitQ {
+    const double2 *M;          // [K][ng]
+    const double *w;           // weight vector v at w + v * wstride, [K] each
+    const unsigned short *SB;  // BF16 digit slices of M for the launch's chunks: [4][nch][6][gpad][32]
+    const int *EB;             // chunk-column exponents of those slices: [nch][gpad]
+    double2 *out;              // raw upper-tile sums of (vector v, K split s): out + v * vstride + s * ng * ng
+    const unsigned *tiles;     // upper tiles (64-row x 128-column) in walk order: I | J << 16
+    long long K, wstride, vstride;
+    long long item0, nitems;   // work items of this entry (nitems a multiple of 8)
+    int ng, gpad, nvec, ntiles;
+    int chunk0, nch;           // chunk range of the launch
+    int ns;                    // K splits of the chunk range: split s takes chunks [s nch / ns, (s + 1) nch / ns)
+    int add;                   // 1: add to the raw sums already in out (later chunk ranges)
+    int pad[2];
+    const signed char *EA;     // [nvec][nch][gpad] chunk-column exponents of the weighted side
 };
 
 // Upper-triangle tile number u -> (ti, tj) in grouped order: bands of four
@@ -141,23 +149,35 @@ struct HerkProb {
     int ns;            // K splits
 };
 
+// One output matrix of a chi0 call: chi = pf * (A + i B) where A (and, on
+// the real frequency axis, B) are the Hermitian chi sums of one weight
+// vector each, held as raw upper-triangle sums.
 struct FinProb {
-    const double2 *part;  // [ns][ng][ng] raw sums (unused in place)
-    double2 *chi;         // [ng][ng]
+    const double2 *part;     // [ns][ng][ng] raw sums of A (unused in place)
+    const double2 *part_im;  // [ns][ng][ng] raw sums of B, or null (imaginary axis: chi = pf A)
+    double2 *chi;            // [ng][ng]
     double pf;
     int ns, ng;
     int accumulate;
     int skip;      // row/column left untouched (FP64 head row written separately), -1 for none
-    int inplace;   // raw upper-triangle sums already sit in chi (ns == 1, no accumulation)
+    int inplace;   // raw upper-triangle sums already sit in chi (ns == 1, no accumulation, no B)
     int pad;
 };
+
+// Kinds of weight vectors (k_weights), Delta = E_v,k+q - E_c,k < 0, all in hartree:
+//   imaginary axis   w = Delta / (Delta^2 + omega^2)   (omega = 0: static 1 / Delta)
+//   real axis        w = (1/2) [1/(Delta - E -+ i delta) + 1/(Delta + E +- i delta)]
+//                    (upper signs retarded, lower advanced), as its real part and
+//                    its imaginary part, each a real weight vector.
+enum WeightKind { kWeightImag = 0, kWeightRealRe = 1, kWeightRetIm = 2, kWeightAdvIm = 3 };
 
 struct WProb {
     const double *ev;  // [nk][nv] eV
     const double *ec;  // [nk][nc] eV
     double *w;         // [K]
-    double omega_ha;
-    int nk, nv, nc, pad;
+    double omega_ha;   // |omega| (imaginary axis) or E (real axis), hartree
+    double delta_ha;   // broadening (real axis), hartree
+    int nk, nv, nc, kind;
 };
 
 }  // namespace bgw

@@ -171,8 +171,11 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
         double best = -1.0;
         int brow = 0x7fffffff;
         if (mine && gi >= col) {
-            best = cabs1(pr[j]);
-            brow = gi;
+            const double v = cabs1(pr[j]);
+            if (v >= 0.0) {  // a NaN entry is never a pivot candidate
+                best = v;
+                brow = gi;
+            }
         }
         wave_argmax(best, brow);
         if (lane == 0) {
@@ -218,7 +221,7 @@ __global__ __launch_bounds__(256) void k_gje_panel(double2 *__restrict__ A, int 
             }
         if (p >= n) p = col;  // no candidate (a column of NaNs): no interchange; info flags the matrix
         if (tid == 0 && r == 0) {
-            if (bv <= 0.0) atomicCAS(info + mat, 0, col + 1);
+            if (!(bv > 0.0)) atomicCAS(info + mat, 0, col + 1);
             ip[col] = p;
         }
         const double2 *praw = cand + win * nb;
@@ -287,8 +290,11 @@ __device__ __forceinline__ void gje_reg_column(const GjeRegCtx &x, double2 (&rv)
     double best = -1.0;
     int brow = 0x7fffffff;
     if (x.mine && x.gi >= col) {
-        best = cabs1(rv[J]);
-        brow = x.gi;
+        const double v = cabs1(rv[J]);
+        if (v >= 0.0) {  // a NaN entry is never a pivot candidate
+            best = v;
+            brow = x.gi;
+        }
     }
     wave_argmax(best, brow);
     if (x.lane == 0) {
@@ -338,7 +344,7 @@ __device__ __forceinline__ void gje_reg_column(const GjeRegCtx &x, double2 (&rv)
         }
     if (p == 0x7fffffff) p = col;  // no candidate (a column of NaNs): no interchange; info flags the matrix
     if (x.tid == 0 && x.r == 0) {
-        if (bv <= 0.0) atomicCAS(x.info + x.mat, 0, col + 1);
+        if (!(bv > 0.0)) atomicCAS(x.info + x.mat, 0, col + 1);
         x.ip[col] = p;
     }
     const double2 *praw = x.cand + win * nb;
@@ -720,7 +726,7 @@ __device__ __forceinline__ void gje_wg_column(double2 (&rv)[ROWS][kWgNb], int (&
     }
     if (tid == 0) {
         ip[col] = p;
-        if (bv <= 0.0) atomicCAS(info, 0, col + 1);
+        if (!(bv > 0.0)) atomicCAS(info, 0, col + 1);
     }
     // interchange of positions col and p
 #pragma unroll

@@ -261,176 +261,17 @@ __host__ __device__ constexpr int plane_stride() {
     return Z1 * Z2 + ((Z2 % 16) - (Z1 * Z2) % 16 + 16) % 16;
 }
 
-template <int Z1, int Z2, int Y1, int Y2, int ACC, int NT, int LC>
-__global__ __launch_bounds__(NT) void k_pair_fft2(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
-                                                  int nkb, int nv, int nc, int n1, const double2 *__restrict__ tw1g,
-                                                  const double2 *__restrict__ tw2g, const double2 *__restrict__ tw3g,
-                                                  const int *__restrict__ ge_code, const int *__restrict__ ge_out,
-                                                  int ng, int rey, int rez, int vb, int cb,
-                                                  double2 *__restrict__ M, long long m_row0) {
-    constexpr int n3 = Z1 * Z2, n2 = Y1 * Y2;
-    constexpr int PS = plane_stride<Z1, Z2>();
-    constexpr int CH = LC * n3;               // product elements per z chunk
-    constexpr int PER = (CH + NT - 1) / NT;   // per thread
-    constexpr int NCHUNK = (n2 + LC - 1) / LC;
-    const int bez = 2 * rez + 1, bey = 2 * rey + 1;
-    const int QS = bez;
-    // e / bez as (e * mdiv) >> 20, exact for e * bez < 2^20 (here e < 128 bez and bez < 90)
-    const unsigned mdiv = (1u << 20) / (unsigned)bez + 1u;
-    extern __shared__ double2 lds[];
-    double2 *tw1 = lds, *tw2 = tw1 + n1, *tw3 = tw2 + n2;
-    double2 *P = tw3 + n3;            // [LC][PS]
-    double2 *Q = P + LC * PS;         // [n2][QS]
-    double2 *R = Q + n2 * QS;         // [bey][bez]
-
-    for (int i = threadIdx.x; i < n1; i += NT) tw1[i] = tw1g[i];
-    for (int i = threadIdx.x; i < n2; i += NT) tw2[i] = tw2g[i];
-    for (int i = threadIdx.x; i < n3; i += NT) tw3[i] = tw3g[i];
-
-    // ---- work order: XCD-contiguous chunks, then (k, c-tile, v-tile, c, v) with v fastest
-    const long long total = (long long)nkb * nv * nc;
-    long long L = blockIdx.x;
-    {
-        const long long per = total / 8;
-        if (L < per * 8) L = (L % 8) * per + L / 8;
-    }
-    const int vtiles = (nv + vb - 1) / vb;
-    const int ctiles = (nc + cb - 1) / cb;
-    long long rem = L;
-    int k = (int)(rem / ((long long)nv * nc));
-    rem -= (long long)k * nv * nc;
-    int v = 0, c = 0;
-    {
-        int done = 0;
-        for (int ct = 0; ct < ctiles; ++ct) {
-            const int cw = min(cb, nc - ct * cb);
-            const int rowblock = cw * nv;
-            if (rem < done + rowblock) {
-                int r2 = (int)(rem - done);
-                for (int vt = 0; vt < vtiles; ++vt) {
-                    const int vw = min(vb, nv - vt * vb);
-                    const int blk = vw * cw;
-                    if (r2 < blk) {
-                        v = vt * vb + r2 % vw;
-                        c = ct * cb + r2 / vw;
-                        break;
-                    }
-                    r2 -= blk;
-                }
-                break;
-            }
-            done += rowblock;
-        }
-    }
-    const long long t = ((long long)k * nv + v) * nc + c;
-    const size_t N = (size_t)n1 * n2 * n3;
-    const double2 *uv = gv + (size_t)(k * nv + v) * N;
-    const double2 *uc = gc + (size_t)(k * nc + c) * N;
-
-    // sphere points in (mx, my, mz) order: a wave shares the phase w^{mx x}
-    // (LDS broadcast) and reads neighbouring R entries
-    int code[ACC], ph[ACC], mxs[ACC];
-    double2 acc[ACC];
-#pragma unroll
-    for (int i = 0; i < ACC; ++i) {
-        const int g = threadIdx.x + i * NT;
-        code[i] = g < ng ? ge_code[g] : -1;
-        mxs[i] = code[i] >= 0 ? (code[i] & 0xff) : 0;
-        ph[i] = 0;
-        acc[i] = make_double2(0.0, 0.0);
-    }
-
-    // software pipeline: the u_c values of the next z chunk are loaded into
-    // registers while the current chunk is transformed; u_v (shared by all the
-    // concurrently running pairs of a c-tile, so L2-resident) is read when the
-    // product is formed
-    double2 fc[PER];
-    auto fetch = [&](int x, int y0) {
-        const int Lc = min(LC, n2 - y0);
-        const double2 *pc = uc + ((size_t)x * n2 + y0) * n3;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int e = threadIdx.x + j * NT;
-            if (e < Lc * n3) fc[j] = pc[e];
-        }
-    };
-    fetch(0, 0);
-    __syncthreads();
-
-    for (int x = 0; x < n1; ++x) {
-#pragma unroll 1
-        for (int ci = 0; ci < NCHUNK; ++ci) {
-            const int y0 = ci * LC;
-            const int Lc = min(LC, n2 - y0);
-            const double2 *pv = uv + ((size_t)x * n2 + y0) * n3;
-            double2 fv[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int e = threadIdx.x + j * NT;
-                if (e < Lc * n3) fv[j] = pv[e];
-            }
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const int e = threadIdx.x + j * NT;
-                if (e < Lc * n3) {
-                    const int yy = e / n3, z = e - yy * n3;
-                    P[yy * PS + z] = cconjmul(fv[j], fc[j]);
-                }
-            }
-            // prefetch the next chunk (next y block, or the first block of the next plane)
-            if (ci + 1 < NCHUNK)
-                fetch(x, y0 + LC);
-            else if (x + 1 < n1)
-                fetch(x + 1, 0);
-            __syncthreads();
-            LineFFT<Z1, Z2>::stage1(P, Lc, PS, 1, tw3);
-            __syncthreads();
-            for (int e = threadIdx.x; e < Lc * bez; e += NT) {
-                const int yy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - yy * bez;
-                Q[(y0 + yy) * QS + iz] = LineFFT<Z1, Z2>::output(P + yy * PS, 1, wrap(iz - rez, n3), tw3);
-            }
-            __syncthreads();
-        }
-        LineFFT<Y1, Y2>::stage1(Q, bez, 1, QS, tw2);
-        __syncthreads();
-        for (int e = threadIdx.x; e < bey * bez; e += NT) {
-            const int iy = (int)(((unsigned long long)e * mdiv) >> 20), iz = e - iy * bez;
-            R[e] = LineFFT<Y1, Y2>::output(Q + iz, QS, wrap(iy - rey, n2), tw2);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ACC; ++i) {
-            if (code[i] >= 0) {
-                const int iy = (code[i] >> 8) & 0xff, iz = code[i] >> 16;
-                acc[i] = cadd(acc[i], cmul(tw1[ph[i]], R[iy * bez + iz]));
-                ph[i] += mxs[i];
-                if (ph[i] >= n1) ph[i] -= n1;
-            }
-        }
-    }
-    const double inv = 1.0 / (double)N;
-    double2 *out = M + (size_t)(m_row0 + t) * ng;
-#pragma unroll
-    for (int i = 0; i < ACC; ++i) {
-        const int g = threadIdx.x + i * NT;
-        if (g < ng) out[ge_out[g]] = cscale(acc[i], inv);
-    }
-}
-
-
 // ------------------------------------------------------------------ two-pass pair transform
 //
 // Pass A (k_pair_yz): one workgroup per (k, c, block of x-planes); for every x of
 // the block and every valence band v: product conj(u_v) u_c on the plane, z FFT
 // pruned to the dielectric box, y FFT pruned likewise; the bey x bez values are
-// written to T[t][x][iy][iz].  No per-pair accumulators, so the next chunk's
-// u_v, u_c values are prefetched into registers while the current one is
-// transformed.  Concurrent workgroups (same k and x-block, consecutive c) share
-// the u_v planes in L2.
+// written to T[t][x][iy][iz] (no per-pair accumulators).  Concurrent
+// workgroups (same k and x-block, consecutive c) share the u_v planes in L2.
 // Pass B (k_pair_x): one workgroup per pair; T[t] is staged through LDS a few
 // planes at a time and every sphere point accumulates w_{n1}^{mx x} T[x][iy][iz].
-template <int Z1, int Z2, int NT, int LC, bool PF, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
+template <int Z1, int Z2, int NT, int LC>
+__global__ __launch_bounds__(NT) void k_pair_yz(const double2 *__restrict__ gv, const double2 *__restrict__ gc,
                                                 int nkb, int nv, int nc, int c0, int ncb, int n1,
                                                 const double2 *__restrict__ tw2g, const double2 *__restrict__ tw3g,
                                                 int rey, int rez, int xblk, double2 *__restrict__ T) {
@@ -479,7 +320,6 @@ __global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict_
             }
         }
     };
-    if (PF) fetch(x0, 0, 0);
     __syncthreads();
     for (int x = x0; x < x1; ++x) {
 #pragma unroll 1
@@ -488,7 +328,7 @@ __global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict_
             for (int ci = 0; ci < NCHUNK; ++ci) {
                 const int y0 = ci * LC;
                 const int Lc = min(LC, n2 - y0);
-                if (!PF) fetch(x, v, ci);
+                fetch(x, v, ci);
 #pragma unroll
                 for (int j = 0; j < PER; ++j) {
                     const int e = threadIdx.x + j * NT;
@@ -496,15 +336,6 @@ __global__ __launch_bounds__(NT, MINW) void k_pair_yz(const double2 *__restrict_
                         const int yy = e / n3, z = e - yy * n3;
                         P[yy * PS + z] = cconjmul(fv[j], fc[j]);
                     }
-                }
-                if (PF) {
-                    // prefetch the next chunk: next y block, next valence band, or next plane
-                    if (ci + 1 < NCHUNK)
-                        fetch(x, v, ci + 1);
-                    else if (v + 1 < nv)
-                        fetch(x, v + 1, 0);
-                    else if (x + 1 < x1)
-                        fetch(x + 1, 0, 0);
                 }
                 __syncthreads();
                 LineFFT<Z1, Z2>::stage1(P, Lc, PS, 1, tw3);
@@ -994,60 +825,7 @@ __global__ __launch_bounds__(64) void k_band_yz(const double2 *__restrict__ W, i
 // ------------------------------------------------------------------ host side
 
 namespace {
-
-template <int Z1, int Z2, int ACC, int NT, int LC>
-int launch_pair2_t(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, const int *ge_out, int ng, int rey,
-                   int rez, double2 *M, long long row0, hipStream_t st) {
-    constexpr int n = Z1 * Z2;
-    constexpr int PS = plane_stride<Z1, Z2>();
-    const int bez = 2 * rez + 1, bey = 2 * rey + 1;
-    const size_t lds = sizeof(double2) * ((size_t)px.n + n + n + (size_t)LC * PS + (size_t)n * bez + (size_t)bey * bez);
-    if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
-    auto kern = k_pair_fft2<Z1, Z2, Z1, Z2, ACC, NT, LC>;
-    BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    const long long npairs = (long long)nkb * nv * nc;
-    const int vb = std::min(nv, 8);
-    const int cb = std::max(1, 256 / vb);
-    hipLaunchKernelGGL(kern, dim3((unsigned)npairs), dim3(NT), lds, st, gv, gc, nkb, nv, nc, px.n, px.tw, py.tw,
-                       pz.tw, ge_code, ge_out, ng, rey, rez, vb, cb, M, row0);
-    BGW_HIP(hipGetLastError());
-    return BGW_OK;
-}
-
-// lines per z chunk: the whole plane up to 48, else a block that keeps two
-// workgroups per CU for the usual dielectric boxes
-template <int N>
-constexpr int pair_lc() {
-    return N <= 48 ? N : (N <= 64 ? 32 : 16);
-}
-
-template <int Z1, int Z2, int NT>
-int launch_pair2_n(int per, const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                   const AxisPlan &py, const AxisPlan &pz, const int *ge_code, const int *ge_out, int ng, int rey,
-                   int rez, double2 *M, long long row0, hipStream_t st) {
-#define BGW_P2(A)                                                                                                \
-    if (per <= A)                                                                                                \
-        return launch_pair2_t<Z1, Z2, A, NT, pair_lc<Z1 * Z2>()>(gv, gc, nkb, nv, nc, px, py, pz, ge_code, ge_out, \
-                                                                 ng, rey, rez, M, row0, st);
-    BGW_P2(1)
-    BGW_P2(2)
-    BGW_P2(4)
-    BGW_P2(6)
-    BGW_P2(8)
-    BGW_P2(12)
-    BGW_P2(16)
-    BGW_P2(24)
-    BGW_P2(32)
-#undef BGW_P2
-    return BGW_ERR_UNSUPPORTED;
-}
-
-}  // namespace
-
-
-namespace {
-template <int Z1, int Z2, int LC, bool PF, int MINW = 1>
+template <int Z1, int Z2, int LC>
 int launch_pair_yz_t(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
                      const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
                      hipStream_t st) {
@@ -1056,7 +834,7 @@ int launch_pair_yz_t(const double2 *gv, const double2 *gc, int nkb, int nv, int 
     const int bez = 2 * rez + 1;
     const size_t lds = sizeof(double2) * ((size_t)n + n + (size_t)LC * PS + (size_t)n * bez);
     if (lds > 150 * 1024) return BGW_ERR_UNSUPPORTED;
-    auto kern = k_pair_yz<Z1, Z2, 256, LC, PF, MINW>;
+    auto kern = k_pair_yz<Z1, Z2, 256, LC>;
     BGW_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const int n1 = px.n;
     const int xblk = std::max(1, std::min(n1, 8));
@@ -1099,24 +877,11 @@ int launch_pair_yzr_t(const double2 *gv, const double2 *gc, int nkb, int nv, int
     return BGW_OK;
 }
 
-int pair_variant() {
-    const char *s = std::getenv("BGW_PAIR_VARIANT");
-    return (s && *s) ? std::atoi(s) : 0;
-}
-
 template <int Z1, int Z2, int LCF>
 int launch_pair_yz_sel(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
                        const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
                        hipStream_t st) {
-    // experimental variants (BGW_PAIR_VARIANT): 1 = prefetch, whole chunk; 2 = half chunk,
-    // no prefetch; 3 = whole chunk, >= 3 waves/SIMD; 4 = half chunk, >= 3 waves/SIMD
-    switch (pair_variant()) {
-        case 1: return launch_pair_yz_t<Z1, Z2, LCF, true>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        case 2: return launch_pair_yz_t<Z1, Z2, (LCF + 1) / 2, false>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        case 3: return launch_pair_yz_t<Z1, Z2, LCF, false, 3>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        case 4: return launch_pair_yz_t<Z1, Z2, (LCF + 1) / 2, false, 3>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        default: return launch_pair_yz_t<Z1, Z2, LCF, false>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-    }
+    return launch_pair_yz_t<Z1, Z2, LCF>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
 }
 }  // namespace
 
@@ -1141,11 +906,7 @@ int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc
         case 16: return launch_pair_yz_sel<16, 1, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         case 24: return launch_pair_yz_sel<8, 3, 24>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         case 32: return launch_pair_yz_sel<16, 2, 32>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        case 48: {
-            const char *r8 = std::getenv("BGW_PAIR_RADIX8");
-            if (r8 && *r8 == '1') return launch_pair_yz_sel<8, 6, 48>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-            return launch_pair_yz_sel<16, 3, 48>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
-        }
+        case 48: return launch_pair_yz_sel<16, 3, 48>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         case 64: return launch_pair_yz_sel<16, 4, 32>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         case 96: return launch_pair_yz_sel<16, 6, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
         case 128: return launch_pair_yz_sel<16, 8, 16>(gv, gc, nkb, nv, nc, c0, ncb, px, py, pz, rey, rez, T, st);
@@ -1158,8 +919,7 @@ int launch_pair_yz(const double2 *gv, const double2 *gc, int nkb, int nv, int nc
 int launch_pair_yzr(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, int c0, int ncb,
                     const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, int rey, int rez, double2 *T,
                     hipStream_t st) {
-    const char *e = std::getenv("BGW_PAIR_YZ_LEGACY");
-    if ((e && *e == '1') || py.n != pz.n) return BGW_ERR_UNSUPPORTED;
+    if (py.n != pz.n) return BGW_ERR_UNSUPPORTED;
     switch (pz.n) {
         case 16: return launch_pair_yzr_t<16, 4, 1>(gv, gc, nkb, nv, nc, c0, ncb, px.n, rey, rez, T, st);
         case 24: return launch_pair_yzr_t<24, 2, 1>(gv, gc, nkb, nv, nc, c0, ncb, px.n, rey, rez, T, st);
@@ -1191,25 +951,6 @@ int launch_pair_x(const double2 *T, long long npairs, const AxisPlan &px, int re
     BGW_PX(32)
 #undef BGW_PX
     return BGW_ERR_UNSUPPORTED;
-}
-
-// Returns BGW_ERR_UNSUPPORTED (without launching) when no fast path applies.
-int launch_pair_fft2(const double2 *gv, const double2 *gc, int nkb, int nv, int nc, const AxisPlan &px,
-                     const AxisPlan &py, const AxisPlan &pz, const int *ge_code2, const int *ge_out, int ng, int rey,
-                     int rez, double2 *M, long long row0, hipStream_t st) {
-    if (py.n != pz.n) return BGW_ERR_UNSUPPORTED;
-    const int n = pz.n;
-    const int per = (ng + 255) / 256;
-    switch (n) {
-        case 16: return launch_pair2_n<16, 1, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 24: return launch_pair2_n<8, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 32: return launch_pair2_n<16, 2, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 48: return launch_pair2_n<16, 3, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 64: return launch_pair2_n<16, 4, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 96: return launch_pair2_n<16, 6, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        case 128: return launch_pair2_n<16, 8, 256>(per, gv, gc, nkb, nv, nc, px, py, pz, ge_code2, ge_out, ng, rey, rez, M, row0, st);
-        default: return BGW_ERR_UNSUPPORTED;
-    }
 }
 
 namespace {
@@ -1294,8 +1035,6 @@ size_t band_lines_bytes(const AxisPlan &px, const AxisPlan &py, const AxisPlan &
 }
 
 bool band_lines_supported(const AxisPlan &px, const AxisPlan &py, const AxisPlan &pz, const SphereMaps &sm) {
-    const char *e = std::getenv("BGW_BAND_LEGACY");
-    if (e && *e == '1') return false;
     if (px.n != py.n || py.n != pz.n || !sm.sticks_contiguous) return false;
     const int n = pz.n, G = n == 16 ? 4 : 2;
     return (n == 16 || n == 24 || n == 32) && G * (2 * sm.rwy + 1) <= 64;

@@ -103,13 +103,19 @@ int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long 
 int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_t);
 
 // ---- split-precision launchers (split.hip)
-int split_workspace_bytes(long long K, int ng, int nsplit_override, size_t *bytes);
-SplitLayout split_layout(long long K, int ng, int nsplit_override, void *ws);
-int launch_split_slices(const SplitLayout &, const double2 *M, long long K, int ng, const double *w, long long t0,
-                        int nch, bool with_b, hipStream_t);
-int launch_split_gemm(const SplitLayout &, int ng, int nch, int add, int *used, hipStream_t);
-int launch_split_headwing(const SplitLayout &, const double2 *M, long long K, int ng, int head, const double *w,
-                          double pf, double2 *chi, int accumulate, hipStream_t);
+int split_gpad(int ng);                         // columns of the digit slices (multiple of 128)
+long long split_chunks(long long K);            // chunks (96 pairs each) of K pairs
+size_t split_slice_bytes(long long nch, int ng);  // slices + exponents of nch chunks
+size_t split_slices_only_bytes(long long nch, int ng);  // the slices alone (the exponents follow them)
+void split_tiles(int ng, std::vector<unsigned> &out);  // upper 64 x 128 tiles in walk order
+int split_grid();                               // blocks of the persistent split launch
+int launch_split_slices(const double2 *M, long long K, int ng, long long c0, int nch, unsigned short *S, int *E,
+                        const double *w, long long wstride, int nvec, signed char *EA, hipStream_t);
+int launch_chi_split(const SplitQ *qs, int nq, long long nitems, hipStream_t);
+int launch_headwing(const double2 *M, long long K, int ng, int head, const double *w, long long wstride, int nvec,
+                    int nsplit, double2 *hw, hipStream_t);
+int launch_headwing_write(const double2 *hw, int nsplit, int nvec, int ng, int head, double pf, double2 *chi, int nout,
+                          int two, int accumulate, hipStream_t);
 
 int device_cus();
 

@@ -2,23 +2,34 @@
 // M^H diag(w) M, see chi.hip) computed from BF16 digit slices on MFMA with
 // FP32 accumulation, recombined in FP64.
 //
-// Slicing (k_split_slice).  The real contraction index k' = 2t + part is cut
-// into chunks of 256 (128 pairs).  Within a chunk every column G gets its own
-// power-of-two scale 2^e (e = exponent of the chunk-column max), and each
-// value is written as four signed base-256 digits:
-//     x = 2^(e-8) (d1 + d2 2^-8 + d3 2^-16 + d4 2^-24 + r),  |d1| <= 256,
-//     |d2|,|d3|,|d4| <= 128, |r| <= 2^-25,
-// all exact in BF16.  Stored slices: d1, d2, d3, d4 (8 bytes per value).
+// Digits.  The real contraction index k' = 2t + part is cut into chunks of
+// 192 (96 pairs, six MFMA k-steps).  Within a chunk every column G of X gets a power-of-two
+// scale 2^eB (eB = exponent of the chunk-column max of |Re M|, |Im M|), and
+// every column of X_w, for each weight vector, the scale 2^eA of the
+// chunk-column max of |w_t Re M|, |w_t Im M| (both found by k_split_slice in
+// its pass over M).  Each scaled value y = x 2^(8-e), |y| < 256, is written
+// as four signed digits in base 512:
+//     y = d1 + d2 2^-9 + d3 2^-18 + d4 2^-27 + r,  |di| <= 256,  |r| <= 2^-28,
+// every digit an integer of magnitude <= 256 and so exact in BF16 (eight
+// significant bits).  The unweighted side's digits do not depend on the
+// frequency: k_split_slice stores them once per q (8 bytes per real value).
+// The weighted side is sliced inside the GEMM from M and w, in registers,
+// for each frequency, so no weighted slices are stored at all.
 //
-// Products (k_herk_split), grouped by weight 2^-8p, one FP32 sum per group:
-//     p = 0: a1 b1                                   (FP32-exact: |sum| <= 2^24)
-//     p = 1: a1 b2 + a2 b1                           (FP32-exact: |sum| <= 2^24)
-//     p = 2: a1 b3 + a2 b2 + a3 b1                   (rounded at 2^-24 of the group)
-//     p = 3: a1 b4 + a2 b3 + a3 b2 + a4 b1
-// Ten BF16 MFMA products per (Re, Im); at each chunk end the four FP32 sums
-// are combined in FP64 with the chunk scales 2^(eA + eB - 16) and added to
-// FP64 accumulators.  Terms with weight <= 2^-32 are dropped; the rounding of
-// the last two groups is at 2^-40 and below.  Expected relative error ~1e-10.
+// Products (k_chi_split), grouped by weight 2^-9p, one FP32 sum per group:
+//     p = 0: a1 b1                                   (exact: |sum| <= 2^16 * 192 < 2^24)
+//     p = 1: a1 b2 + a2 b1                           (exact while |sum| < 2^24)
+//     p = 2: a1 b3 + a2 b2 + a3 b1
+//            + a1' b4 + a2' b3 + a3' b2 + a4' b1     (rounded at 2^-24 of the group)
+// where ai' = ai 2^-9 (exact in BF16) folds the weight-2^-27 products into
+// the third group.  Ten BF16 MFMA products per (Re, Im); at each chunk end
+// the three FP32 sums are combined in FP64 with the chunk scales
+// 2^(eA + eB - 16) and added to FP64 accumulators.  Terms of weight
+// <= 2^-36 are dropped, and so is the remainder r.  The second group's
+// partial sums pass 2^24 only if most of the chunk's 384 products reach
+// 2^16 with one sign; FP32 then rounds at 2^-24 of that group, 2^-33 of the
+// chunk's leading term.  Expected relative error: a few 1e-11 for positive
+// weights, a few 1e-10 where the weights change sign across a resonance.
 //
 // The head row/column (G = 0) is recomputed in FP64 from M (k_headwing)
 // because v(q+G) ~ 1/q^2 amplifies it in epsilon.
@@ -31,117 +42,134 @@ namespace bgw {
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef double double4_t __attribute__((ext_vector_type(4)));
 
 namespace {
-constexpr int SK = 256;      // real contraction rows per exact chunk
-constexpr int SKP = SK / 2;  // pairs per chunk
-constexpr int KS = 32;       // real rows per MFMA k-step (16x16x32)
-constexpr int NKS = SK / KS; // k-steps per chunk
-constexpr int NSL = 4;       // stored slices
-constexpr int NGR = 4;       // FP32 product groups
-constexpr int TT = 64;       // output tile (G and G')
+constexpr int SK = 192;       // real contraction rows per chunk (one set of exponents, FP32 group sums)
+constexpr int SKP = SK / 2;   // pairs per chunk
+constexpr int KS = 32;        // real rows per MFMA k-step (16x16x32)
+constexpr int KSP = KS / 2;   // pairs per k-step
+constexpr int NKS = SK / KS;  // k-steps per chunk
+constexpr int NSL = 4;        // stored slices
+constexpr int NGR = 3;        // FP32 product groups
+constexpr int TR = 64;        // output tile rows: weighted side, sliced in registers
+constexpr int TC = 128;       // output tile columns: unweighted side, digit slices through LDS
+constexpr int XT = 512;       // GEMM block: 8 waves (two per SIMD), 4 x 2 over the tile
+constexpr int kMinExp = -500; // chunk exponents are clamped here (values below 2^-500 count as zero)
 
 __device__ inline double pow2(int e) { return __longlong_as_double((long long)(e + 1023) << 52); }
 
+__device__ inline int chunk_exp(double mx) {
+    int e = 0;
+    if (mx > 0.0) (void)frexp(mx, &e);  // mx < 2^e
+    return max(e, kMinExp);
+}
+
 __device__ inline unsigned short bf16_bits_exact(double v) {
-    // v is an integer of at most 9 significant bits times a power of two: exact in BF16
+    // v is an integer of at most 9 significant bits: exact in BF16
     const float f = (float)v;
     return (unsigned short)(__float_as_uint(f) >> 16);
 }
 }  // namespace
 
-// Block = one chunk x 32 columns.  Thread t owns column G = 32 blockIdx.x +
-// (t/4) % 32 and, in each of the k-steps 4 (t/128) .. +3, the four pairs
-// 4 (t%4) .. +3; it keeps its 16 pairs in registers, so M is read once for
-// both sides.  With this assignment every 16-byte store instruction of a wave
-// writes 1 KB of contiguous slice memory.  Side A (X_w, weighted by w) and
-// side B (X) are written when their slice pointer is non-null.
+// Digit slices of the unweighted side for chunks [c0, c0 + nchunk) of one q,
+// and the chunk-column exponents of the weighted side of every weight vector.
+// Block = one chunk x 32 columns, 384 threads.  Thread t owns column G = 32
+// blockIdx.x + (t/4) % 32 and, in each of the k-steps 2 (t/128) and
+// 2 (t/128) + 1, the four pairs 4 (t%4) .. +3; with this assignment every
+// 16-byte store instruction of a wave writes 1 KB of contiguous slice memory.
 // S: [NSL][nchunk][NKS][gpad][KS] bf16 bits, each group of 8 values holding four
-// pairs as (Re t0..t3, Im t0..t3); E: [nchunk][gpad].
-// Rows t0 .. t0 + nchunk*128 of M (zero beyond K).
-__global__ __launch_bounds__(256) void k_split_slice(const double2 *__restrict__ M, long long K, int ng, int gpad,
-                                                     const double *__restrict__ w, long long t0, int nchunk,
-                                                     unsigned short *__restrict__ SA, int *__restrict__ EA,
-                                                     unsigned short *__restrict__ SB, int *__restrict__ EB) {
-    __shared__ double red[2][8][32];
+// pairs as (Re t0..t3, Im t0..t3); E: [nchunk][gpad] (2^E above the chunk-column
+// max of |Re M|, |Im M|); EA: [nvec][nchunk][gpad], 2^EA above the chunk-column
+// max of |w_v(t) Re M|, |w_v(t) Im M| (clamped to [-128, 127]: a value below
+// 2^-128 only keeps fewer digits).  Pairs >= K are zero.
+constexpr int SLICE_T = 32 * 4 * (NKS / 2);  // 384
+__global__ __launch_bounds__(SLICE_T) void k_split_slice(const double2 *__restrict__ M, long long K, int ng, int gpad,
+                                                         long long c0, int nchunk, unsigned short *__restrict__ S,
+                                                         int *__restrict__ E, const double *__restrict__ w,
+                                                         long long wstride, int nvec, signed char *__restrict__ EA) {
+    constexpr int NP = 4 * (NKS / 2);  // partial maxima per column
+    __shared__ double red[NP][32];
     const int q = threadIdx.x & 3, cl = (threadIdx.x >> 2) & 31, kh = threadIdx.x >> 7;
     const int G = blockIdx.x * 32 + cl;
     const int chunk = blockIdx.y;
-    const long long tb = t0 + (long long)chunk * SKP;
+    const long long tb = (c0 + chunk) * SKP;
     const bool col = G < ng;
-    double2 m[4][4];  // [k-step i][pair j]
-    double s[4][4];
-    double mxa = 0.0, mxb = 0.0;
+    double2 m[2][4];  // [k-step i][pair j]
+    double mx = 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const long long t = tb + (4 * kh + i) * (KS / 2) + 4 * q + j;
-            m[i][j] = make_double2(0.0, 0.0);
-            s[i][j] = 0.0;
-            if (t < K) {
-                s[i][j] = w ? w[t] : 1.0;
-                if (col) m[i][j] = M[t * ng + G];
-            }
-            mxa = fmax(mxa, fabs(s[i][j]) * fmax(fabs(m[i][j].x), fabs(m[i][j].y)));
-            mxb = fmax(mxb, fmax(fabs(m[i][j].x), fabs(m[i][j].y)));
+            const long long t = tb + (2 * kh + i) * KSP + 4 * q + j;
+            m[i][j] = (t < K && col) ? M[t * ng + G] : make_double2(0.0, 0.0);
+            mx = fmax(mx, fmax(fabs(m[i][j].x), fabs(m[i][j].y)));
         }
-    red[0][4 * kh + q][cl] = mxa;
-    red[1][4 * kh + q][cl] = mxb;
+    red[4 * kh + q][cl] = mx;
     __syncthreads();
-    mxa = 0.0;
-    mxb = 0.0;
+    mx = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        mxa = fmax(mxa, red[0][k][cl]);
-        mxb = fmax(mxb, red[1][k][cl]);
-    }
-    if (G >= gpad) return;
+    for (int k = 0; k < NP; ++k) mx = fmax(mx, red[k][cl]);
     const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
+    const int e = chunk_exp(mx);
+    if (q == 0 && kh == 0) E[(size_t)chunk * gpad + G] = e;
+    const double up = pow2(8 - e);
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-        unsigned short *S = side ? SB : SA;
-        int *E = side ? EB : EA;
-        if (!S) continue;
-        const double mx = side ? mxb : mxa;
-        int e = 0;
-        if (mx > 0.0) (void)frexp(mx, &e);  // mx < 2^e
-        if (q == 0 && kh == 0) E[(size_t)chunk * gpad + G] = e;
-        const double up = pow2(8 - e);
+    for (int i = 0; i < 2; ++i) {
+        const int ks = 2 * kh + i;
+        unsigned short d[NSL][8];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ks = 4 * kh + i;
-            unsigned short d[NSL][8];
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int part = 0; part < 2; ++part) {
-                    const double v = part ? m[i][j].y : m[i][j].x;
-                    const double y = (side ? v : s[i][j] * v) * up;
-                    const double d1 = rint(y);
-                    double r = (y - d1) * 256.0;
-                    const double d2 = rint(r);
-                    r = (r - d2) * 256.0;
-                    const double d3 = rint(r);
-                    r = (r - d3) * 256.0;
-                    const double d4 = rint(r);
-                    const int qq = 4 * part + j;  // real parts first, then imaginary parts
-                    d[0][qq] = bf16_bits_exact(d1);
-                    d[1][qq] = bf16_bits_exact(d2);
-                    d[2][qq] = bf16_bits_exact(d3);
-                    d[3][qq] = bf16_bits_exact(d4);
-                }
-            const size_t dst = (((size_t)chunk * NKS + ks) * gpad + G) * KS + 8 * q;
-#pragma unroll
-            for (int sl = 0; sl < NSL; ++sl) {
-                uint4 pk;
-                pk.x = d[sl][0] | ((unsigned)d[sl][1] << 16);
-                pk.y = d[sl][2] | ((unsigned)d[sl][3] << 16);
-                pk.z = d[sl][4] | ((unsigned)d[sl][5] << 16);
-                pk.w = d[sl][6] | ((unsigned)d[sl][7] << 16);
-                *reinterpret_cast<uint4 *>(S + sl * slice_stride + dst) = pk;
+            for (int part = 0; part < 2; ++part) {
+                const double y = (part ? m[i][j].y : m[i][j].x) * up;
+                const double d1 = rint(y);
+                double r = (y - d1) * 512.0;
+                const double d2 = rint(r);
+                r = (r - d2) * 512.0;
+                const double d3 = rint(r);
+                r = (r - d3) * 512.0;
+                const double d4 = rint(r);
+                const int qq = 4 * part + j;  // real parts first, then imaginary parts
+                d[0][qq] = bf16_bits_exact(d1);
+                d[1][qq] = bf16_bits_exact(d2);
+                d[2][qq] = bf16_bits_exact(d3);
+                d[3][qq] = bf16_bits_exact(d4);
             }
+        const size_t dst = (((size_t)chunk * NKS + ks) * gpad + G) * KS + 8 * q;
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) {
+            uint4 pk;
+            pk.x = d[sl][0] | ((unsigned)d[sl][1] << 16);
+            pk.y = d[sl][2] | ((unsigned)d[sl][3] << 16);
+            pk.z = d[sl][4] | ((unsigned)d[sl][5] << 16);
+            pk.w = d[sl][6] | ((unsigned)d[sl][7] << 16);
+            *reinterpret_cast<uint4 *>(S + sl * slice_stride + dst) = pk;
+        }
+    }
+    // weighted side: the same products fl(w x) the GEMM forms, so 2^EA bounds them
+    double mr[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mr[i][j] = fmax(fabs(m[i][j].x), fabs(m[i][j].y));
+    for (int v = 0; v < nvec; ++v) {
+        const double *wv = w + (size_t)v * wstride;
+        double mw = 0.0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long long t = tb + (2 * kh + i) * KSP + 4 * q + j;
+                if (t < K) mw = fmax(mw, fabs(wv[t]) * mr[i][j]);
+            }
+        __syncthreads();  // the previous vector's reduction has been read
+        red[4 * kh + q][cl] = mw;
+        __syncthreads();
+        if (q == 0 && kh == 0) {
+            mw = 0.0;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) mw = fmax(mw, red[k][cl]);
+            EA[((size_t)v * nchunk + chunk) * gpad + G] = (signed char)min(127, max(-128, chunk_exp(mw)));
         }
     }
 }
@@ -165,26 +193,26 @@ __device__ inline uint4 swap_neg(uint4 u) {
 }
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f32_16x16x32_bf16((a), (b), (c), 0, 0, 0)
 
-// LDS stage: [side][slice][64 rows][64 B], the four 16-B segments of row r
-// stored in the order seg ^ (r & 3) (conflict-free 16-B fragment reads).
-constexpr int SLICE_LDS = TT * KS * 2;          // 4096 B
-constexpr int STAGE_LDS = 2 * NSL * SLICE_LDS;  // 32768 B
-constexpr int PIECES = 2 * NSL * 4 / 8;         // 1-KB pieces of a stage per wave
-
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Block: 8 waves (512 threads) in a 2 x 4 layout over the 64 x 64 tile; wave
-// (wr, wc) owns rows wr*32 .. +32 (two 16-row MFMA blocks a) and columns
-// wc*16 .. +16.  Two waves per SIMD let one wave's LDS reads and VALU work
-// run under the other's MFMAs.
-constexpr int HT = 512;  // threads per block
-
-struct HerkAcc {
-    float4_t g[NGR][2][2];      // [group][re/im][a]
-    double re[2][4], im[2][4];  // FP64 sums of the chunks done so far
-};
-
-constexpr int NSTAGE = 4;  // LDS stages: k-steps are loaded NSTAGE - 1 ahead
+// LDS stage of one k-step: the weighted side as FP64 complex, [16 pairs][64
+// columns] (16 B each, 1 KB per pair row); the unweighted side's four digit
+// slices, [slice][128 rows][64 B] with the four 16-B segments of row r stored
+// in the order seg ^ (r & 3) (conflict-free 16-B fragment reads); the
+// step's 16 weights.  Besides the three stages, two exponent buffers hold a
+// chunk's 128 column exponents (int32, bytes 0..511) and 64 row exponents of
+// the weighted side (int8, bytes 512..575): chunk c in buffer c % 2, staged
+// with the chunk's first step and read when the chunk starts and when it ends.
+constexpr int A_LDS = KSP * TR * 16;          // 16 KB
+constexpr int B_SLICE_LDS = TC * KS * 2;      // 8 KB
+constexpr int W_OFF = A_LDS + NSL * B_SLICE_LDS;
+constexpr int STG = W_OFF + 256;              // 48.25 KB
+constexpr int E_LDS = 1024;
+constexpr int NWAVE = XT / 64;
+constexpr int PA = KSP / NWAVE;               // 1-KB pieces of the A part per wave: 2
+constexpr int PB = NSL * B_SLICE_LDS / 1024 / NWAVE;  // of the B part: 4
+constexpr int PIECES = PA + PB;               // direct loads per wave and k-step (wave 1: one more, the weights;
+                                              // wave 0 on chunk-start steps: two more, the exponents)
 
 // vmcnt(n) alone (expcnt and lgkmcnt left at their maxima); vmcnt is split
 // over bits 3:0 and 15:14 of the immediate
@@ -196,297 +224,414 @@ constexpr int NSTAGE = 4;  // LDS stages: k-steps are loaded NSTAGE - 1 ahead
 // flight for later stages.
 __device__ __forceinline__ void stage_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-// Copy k-step `step` of the A (rows G0..) and B (rows H0..) slices into a
-// stage with direct global->LDS loads.  The stage is 32 pieces of 1 KB
-// (slice-side q/4, rows 16 (q%4) .. +16); wave w issues pieces 4w .. 4w+3,
-// lane L the 16 B of row 16 (q%4) + L/4 at stored segment L%4.  Addresses: a
-// wave-uniform base plus this lane's 32-bit byte offset.
-__device__ __forceinline__ void herk_issue(unsigned char *stage, const unsigned short *SA,
-                                           const unsigned short *SB, const unsigned (&off)[PIECES],
-                                           size_t slice_stride, long long step, int gpad, int wave) {
-    const size_t so = (size_t)step * gpad * KS;
+// Per-lane sources of one item's stage loads.  A piece i of wave w is pair
+// row j = 2w + i of the k-step: lane L loads M[t][G0 + L] (clamped into M;
+// the slicing zeroes what lies outside).  B piece i of wave w is slice w/2,
+// rows 64 (w%2) + 16 i .. +16: lane L loads row 64 (w%2) + 16 i + L/4 at
+// stored segment L%4, i.e. source segment (L%4) ^ ((L/4) & 3), one per-lane
+// address plus i KB.
+// Wave 1 loads the step's weights (lanes 0..7, two each): the weight
+// vectors are padded by 128 entries, and the slicing zeroes pairs past K.
+struct StageSrc {
+    const char *a_base;      // M + G(lane) (bytes), pair rows added per step
+    long long a_row_bytes;   // ng * 16
+    long long kmax;          // last valid pair
+    const char *b_base;      // slice wave/2, row 64 (wave%2) + L/4 and segment of this lane (bytes), k-step added
+    size_t b_step_bytes;     // gpad * KS * 2
+    const double *w;         // weights of this vector
+    const int *eb;           // EB: chunk-column exponents of the slices, [nch][gpad]
+    const signed char *ea;   // EA of this vector: chunk-column exponents of the weighted side, [nch][gpad]
+    int gpad, G0, H0;
+};
+
+__device__ __forceinline__ void stage_issue(unsigned char *__restrict__ stage, unsigned char *__restrict__ ebuf,
+                                            const StageSrc &S, long long t0, long long step, int wave, int lane) {
 #pragma unroll
-    for (int i = 0; i < PIECES; ++i) {
-        const int q = PIECES * wave + i;
-        const int idx = q >> 2;  // 0..3: A slices, 4..7: B slices
-        const unsigned short *base = idx < NSL ? SA + idx * slice_stride : SB + (idx - NSL) * slice_stride;
-        __builtin_amdgcn_global_load_lds((const void *)(reinterpret_cast<const char *>(base + so) + off[i]),
-                                         (lds_void_t *)(stage + idx * SLICE_LDS + (q & 3) * 1024), 16, 0, 0);
+    for (int i = 0; i < PA; ++i) {
+        const long long t = min(t0 + PA * wave + i, S.kmax);
+        __builtin_amdgcn_global_load_lds((const void *)(S.a_base + t * S.a_row_bytes),
+                                         (lds_void_t *)(stage + (PA * wave + i) * 1024), 16, 0, 0);
+    }
+    const char *b = S.b_base + step * S.b_step_bytes;
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+        __builtin_amdgcn_global_load_lds((const void *)(b + i * 1024),
+                                         (lds_void_t *)(stage + A_LDS + (wave >> 1) * B_SLICE_LDS +
+                                                        (wave & 1) * 4096 + i * 1024),
+                                         16, 0, 0);
+    if (wave == 1 && lane < 8)
+        __builtin_amdgcn_global_load_lds((const void *)(S.w + t0 + 2 * lane), (lds_void_t *)(stage + W_OFF), 16, 0,
+                                         0);
+    if (wave == 0 && step % NKS == 0) {
+        const long long ch = step / NKS;
+        const int *er = S.eb + ch * S.gpad;
+        if (lane < 32)
+            __builtin_amdgcn_global_load_lds((const void *)(er + S.H0 + 4 * lane), (lds_void_t *)ebuf, 16, 0, 0);
+        if (lane < 4)
+            __builtin_amdgcn_global_load_lds((const void *)(S.ea + ch * S.gpad + S.G0 + 16 * lane),
+                                             (lds_void_t *)(ebuf + 512), 16, 0, 0);
     }
 }
 
-__device__ __forceinline__ uint4 frag(const unsigned char *slice, int row, int lq) {
+
+__device__ __forceinline__ uint4 bfrag(const unsigned char *slice, int row, int lq) {
     return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
 }
 
-// The wave's fragments of one k-step: the slices of the B column block and of
-// the two A row blocks.
-struct HerkFrags {
-    uint4 b[NSL], a[2][NSL];
+constexpr int NCB = TC / 32;  // column blocks of a wave (each wave spans 64 of the 128 columns)
+
+struct SplitAcc {
+    float4_t g[NCB][NGR][2];  // [col block][group][re/im]
+    double re[NCB][4], im[NCB][4];
 };
 
-__device__ __forceinline__ void herk_frags(const unsigned char *stage, HerkFrags &f, int wr, int wc, int li,
-                                           int lq) {
-    const unsigned char *As = stage, *Bs = stage + NSL * SLICE_LDS;
+// Digits of two values as the BF16 pairs (low half first) of each slice, and
+// the same digits times 2^-9.
+__device__ __forceinline__ void digits2(double y0, double y1, unsigned (&d)[NSL], unsigned (&ds)[NSL]) {
+    double r0 = y0, r1 = y1;
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl) f.b[sl] = frag(Bs + sl * SLICE_LDS, wc * 16 + li, lq);
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int sl = 0; sl < NSL; ++sl) f.a[a][sl] = frag(As + sl * SLICE_LDS, wr * 32 + 16 * a + li, lq);
-}
-
-// Ten BF16 products per (Re, Im) for the wave's 32 x 16 block of one k-step.
-__device__ __forceinline__ void herk_mfma(const HerkFrags &f, HerkAcc &acc) {
-    // slice indices: 0 = d1, 1 = d2, 2 = d3, 3 = d4
-    const bf16x8_t b1 = as_bf16x8(f.b[0]), b2 = as_bf16x8(f.b[1]), b3 = as_bf16x8(f.b[2]);
-    const bf16x8_t b4 = as_bf16x8(f.b[3]);
-    const bf16x8_t y1 = as_bf16x8(swap_neg(f.b[0])), y2 = as_bf16x8(swap_neg(f.b[1]));
-    const bf16x8_t y3 = as_bf16x8(swap_neg(f.b[2])), y4 = as_bf16x8(swap_neg(f.b[3]));
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const bf16x8_t a1 = as_bf16x8(f.a[a][0]), a2 = as_bf16x8(f.a[a][1]), a3 = as_bf16x8(f.a[a][2]);
-        const bf16x8_t a4 = as_bf16x8(f.a[a][3]);
-        float4_t(&g0)[2][2] = acc.g[0];
-        float4_t(&g1)[2][2] = acc.g[1];
-        float4_t(&g2)[2][2] = acc.g[2];
-        float4_t(&g3)[2][2] = acc.g[3];
-        g0[0][a] = MFMA(a1, b1, g0[0][a]);
-        g0[1][a] = MFMA(a1, y1, g0[1][a]);
-        g1[0][a] = MFMA(a1, b2, g1[0][a]);
-        g1[1][a] = MFMA(a1, y2, g1[1][a]);
-        g1[0][a] = MFMA(a2, b1, g1[0][a]);
-        g1[1][a] = MFMA(a2, y1, g1[1][a]);
-        g2[0][a] = MFMA(a1, b3, g2[0][a]);
-        g2[1][a] = MFMA(a1, y3, g2[1][a]);
-        g2[0][a] = MFMA(a2, b2, g2[0][a]);
-        g2[1][a] = MFMA(a2, y2, g2[1][a]);
-        g2[0][a] = MFMA(a3, b1, g2[0][a]);
-        g2[1][a] = MFMA(a3, y1, g2[1][a]);
-        g3[0][a] = MFMA(a1, b4, g3[0][a]);
-        g3[1][a] = MFMA(a1, y4, g3[1][a]);
-        g3[0][a] = MFMA(a2, b3, g3[0][a]);
-        g3[1][a] = MFMA(a2, y3, g3[1][a]);
-        g3[0][a] = MFMA(a3, b2, g3[0][a]);
-        g3[1][a] = MFMA(a3, y2, g3[1][a]);
-        g3[0][a] = MFMA(a4, b1, g3[0][a]);
-        g3[1][a] = MFMA(a4, y1, g3[1][a]);
+    for (int sl = 0; sl < NSL; ++sl) {
+        const double a = rint(r0), b = rint(r1);
+        if (sl + 1 < NSL) {
+            r0 = (r0 - a) * 512.0;
+            r1 = (r1 - b) * 512.0;
+        }
+        const float fa = (float)a, fb = (float)b;
+        d[sl] = __builtin_amdgcn_perm(__float_as_uint(fb), __float_as_uint(fa), 0x07060302u);
+        ds[sl] = __builtin_amdgcn_perm(__float_as_uint(fb * 0.001953125f), __float_as_uint(fa * 0.001953125f),
+                                       0x07060302u);
     }
 }
 
-// Chunk-column exponents of this lane's output rows and column, loaded when
-// the chunk starts and used when it is flushed.
-struct ChunkExp {
-    int ea[2][4], eb;
-};
-
-__device__ __forceinline__ void herk_exp_load(ChunkExp &E, const int *__restrict__ EA, const int *__restrict__ EB,
-                                              long long ch, int gpad, int G0, int H0, int wr, int wc, int li, int lq) {
-    E.eb = EB[(size_t)ch * gpad + H0 + wc * 16 + li];
+// The four slice fragments f of this lane's 8 values (Re t0..t3, Im t0..t3)
+// y = w_t M_t(G) 2^(8 - eA), and fs = f times 2^-9.  The values of pairs
+// (t0, t1) are read and sliced before those of (t2, t3).
+__device__ __forceinline__ void slice_frags(const unsigned char *src, const double (&sw)[4], uint4 (&f)[NSL],
+                                            uint4 (&fs)[NSL]) {
+    unsigned d[NSL], ds[NSL];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int h = 0; h < 2; ++h) {
+        const double2 m0 = *reinterpret_cast<const double2 *>(src + (2 * h) * 1024);
+        const double2 m1 = *reinterpret_cast<const double2 *>(src + (2 * h + 1) * 1024);
+        digits2(m0.x * sw[2 * h], m1.x * sw[2 * h + 1], d, ds);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) E.ea[a][r] = EA[(size_t)ch * gpad + G0 + wr * 32 + 16 * a + 4 * lq + r];
+        for (int sl = 0; sl < NSL; ++sl) {
+            if (h == 0) f[sl].x = d[sl], fs[sl].x = ds[sl];
+            else f[sl].y = d[sl], fs[sl].y = ds[sl];
+        }
+        digits2(m0.y * sw[2 * h], m1.y * sw[2 * h + 1], d, ds);
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) {
+            if (h == 0) f[sl].z = d[sl], fs[sl].z = ds[sl];
+            else f[sl].w = d[sl], fs[sl].w = ds[sl];
+        }
+    }
 }
 
-// Chunk end: combine the four FP32 groups in FP64 with the chunk-column
-// scales into the FP64 accumulators and clear them.  D layout of 16x16x32:
-// lane l, register r -> row 4 (l/16) + r, col l % 16.
-__device__ __forceinline__ void herk_flush(HerkAcc &acc, const ChunkExp &E) {
+// Ten BF16 products per (Re, Im) of the wave's row block and one column block.
+__device__ __forceinline__ void split_mfma(const uint4 (&af)[NSL], const uint4 (&as)[NSL], const uint4 (&bf)[NSL],
+                                           float4_t (&g)[NGR][2]) {
+    const bf16x8_t a1 = as_bf16x8(af[0]), a2 = as_bf16x8(af[1]), a3 = as_bf16x8(af[2]);
+    const bf16x8_t s1 = as_bf16x8(as[0]), s2 = as_bf16x8(as[1]), s3 = as_bf16x8(as[2]), s4 = as_bf16x8(as[3]);
+    const bf16x8_t b1 = as_bf16x8(bf[0]), b2 = as_bf16x8(bf[1]), b3 = as_bf16x8(bf[2]), b4 = as_bf16x8(bf[3]);
+    const bf16x8_t y1 = as_bf16x8(swap_neg(bf[0])), y2 = as_bf16x8(swap_neg(bf[1]));
+    const bf16x8_t y3 = as_bf16x8(swap_neg(bf[2])), y4 = as_bf16x8(swap_neg(bf[3]));
+    g[0][0] = MFMA(a1, b1, g[0][0]);
+    g[0][1] = MFMA(a1, y1, g[0][1]);
+    g[1][0] = MFMA(a1, b2, g[1][0]);
+    g[1][1] = MFMA(a1, y2, g[1][1]);
+    g[1][0] = MFMA(a2, b1, g[1][0]);
+    g[1][1] = MFMA(a2, y1, g[1][1]);
+    g[2][0] = MFMA(a1, b3, g[2][0]);
+    g[2][1] = MFMA(a1, y3, g[2][1]);
+    g[2][0] = MFMA(a2, b2, g[2][0]);
+    g[2][1] = MFMA(a2, y2, g[2][1]);
+    g[2][0] = MFMA(a3, b1, g[2][0]);
+    g[2][1] = MFMA(a3, y1, g[2][1]);
+    g[2][0] = MFMA(s1, b4, g[2][0]);
+    g[2][1] = MFMA(s1, y4, g[2][1]);
+    g[2][0] = MFMA(s2, b3, g[2][0]);
+    g[2][1] = MFMA(s2, y3, g[2][1]);
+    g[2][0] = MFMA(s3, b2, g[2][0]);
+    g[2][1] = MFMA(s3, y2, g[2][1]);
+    g[2][0] = MFMA(s4, b1, g[2][0]);
+    g[2][1] = MFMA(s4, y1, g[2][1]);
+}
+
+// Chunk end: the three FP32 groups combined in FP64 with the chunk scales
+// 2^(eA + eB - 16) into the FP64 accumulators.  D layout of 16x16x32: lane
+// l, register r -> row 4 (l/16) + r, col l % 16.  E: the chunk's exponent
+// buffer.
+__device__ __forceinline__ void split_flush(SplitAcc &acc, const int *E, int wave, int li, int lq) {
+    const signed char *Ea = reinterpret_cast<const signed char *>(E) + 512;
+    int era[4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
+    for (int r = 0; r < 4; ++r) era[r] = (int)Ea[16 * (wave >> 1) + 4 * lq + r] - 16;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int ec = E[64 * (wave & 1) + 16 * cb + li];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double sc = pow2(E.ea[a][r] + E.eb - 16);
-            const double vre = (double)acc.g[0][0][a][r] +
-                               ((double)acc.g[1][0][a][r] +
-                                ((double)acc.g[2][0][a][r] + (double)acc.g[3][0][a][r] * 0.00390625) * 0.00390625) *
-                                   0.00390625;
-            const double vim = (double)acc.g[0][1][a][r] +
-                               ((double)acc.g[1][1][a][r] +
-                                ((double)acc.g[2][1][a][r] + (double)acc.g[3][1][a][r] * 0.00390625) * 0.00390625) *
-                                   0.00390625;
-            acc.re[a][r] += vre * sc;
-            acc.im[a][r] += vim * sc;
+            const double sc = pow2(era[r] + ec);
+            const float4_t(&g)[NGR][2] = acc.g[cb];
+            const double vre =
+                (double)g[0][0][r] + ((double)g[1][0][r] + (double)g[2][0][r] * 0.001953125) * 0.001953125;
+            const double vim =
+                (double)g[0][1][r] + ((double)g[1][1][r] + (double)g[2][1][r] * 0.001953125) * 0.001953125;
+            acc.re[cb][r] = fma(vre, sc, acc.re[cb][r]);
+            acc.im[cb][r] = fma(vim, sc, acc.im[cb][r]);
         }
-#pragma unroll
-        for (int p = 0; p < NGR; ++p)
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
+        __builtin_amdgcn_sched_barrier(0);  // one column block at a time
     }
 }
-// The k-step loop over [s0, s1) (a whole number of chunks).  The four stages
-// are distinct restrict-qualified buffers, which tells the compiler that the
-// loads in flight into one stage do not alias the reads of another, so it
-// inserts no wait for them before those reads.
-__device__ __forceinline__ void herk_pipeline(unsigned char *__restrict__ stage0, unsigned char *__restrict__ stage1,
-                                              unsigned char *__restrict__ stage2, unsigned char *__restrict__ stage3,
-                                              const unsigned short *__restrict__ SA,
-                                              const unsigned short *__restrict__ SB, const int *__restrict__ EA,
-                                              const int *__restrict__ EB, const unsigned (&off)[PIECES],
-                                              size_t slice_stride, long long s0, long long s1, int gpad, int G0,
-                                              int H0, int wave, int wr, int wc, int li, int lq, HerkAcc &acc) {
-    // Each issue is PIECES loads per wave.  Before step x+1 is read, the loads
-    // of steps x+2 and x+3 (2 PIECES, when both were issued) may be in flight.
-    // The fragments of the current step are read before the loads into the
-    // free stage are issued, so no wait on those loads is needed for them.
-#define BGW_STEP(cur, nxt_stage, x)                                              \
-    {                                                                             \
-        HerkFrags f_;                                                             \
-        herk_frags(cur, f_, wr, wc, li, lq);                                      \
-        __builtin_amdgcn_sched_barrier(0);                                        \
-        if ((x) + 3 < s1) herk_issue(nxt_stage, SA, SB, off, slice_stride, (x) + 3, gpad, wave); \
-        __builtin_amdgcn_sched_barrier(0);                                        \
-        herk_mfma(f_, acc);                                                       \
-        if (((x) % NKS) == NKS - 1) herk_flush(acc, E);                           \
-        if ((x) + 3 < s1) BGW_WAIT_VM(2 * PIECES);                                \
-        else BGW_WAIT_VM(0);                                                      \
-        stage_barrier();                                                          \
-    }
-    herk_issue(stage0, SA, SB, off, slice_stride, s0, gpad, wave);
-    herk_issue(stage1, SA, SB, off, slice_stride, s0 + 1, gpad, wave);
-    herk_issue(stage2, SA, SB, off, slice_stride, s0 + 2, gpad, wave);
-    BGW_WAIT_VM(2 * PIECES);
-    stage_barrier();
-    ChunkExp E;
-    for (long long s = s0; s < s1; s += NSTAGE) {
-        if (s % NKS == 0) herk_exp_load(E, EA, EB, s / NKS, gpad, G0, H0, wr, wc, li, lq);
-        BGW_STEP(stage0, stage3, s);
-        BGW_STEP(stage1, stage0, s + 1);
-        BGW_STEP(stage2, stage1, s + 2);
-        BGW_STEP(stage3, stage2, s + 3);
-    }
-#undef BGW_STEP
-}
+
+// Upper tiles of the 64-row x 128-column tiling of an ng x ng matrix: tile
+// (I, J) holds some G <= H iff 64 I <= 128 J + 127, i.e. I <= 2 J + 1.
 }  // namespace
 
-// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
-// With nsplit a multiple of 8, XCD x works through splits x, x + 8, ... one
-// after another, and within a split through the tiles in grouped order, so
-// the blocks resident on an XCD stream one range of chunks through its L2
-// and share most of their rows.  Otherwise block b takes split b % nsplit and
-// grouped tile b / nsplit.
-// The k-steps run through four LDS stages filled by direct global->LDS
-// loads: the slices of the next three steps stream in while the current one
-// feeds the MFMAs.
-// part[split][ng][ng] (+)= chunk sums in FP64 (no prefactor).
-__global__ __launch_bounds__(HT) void k_herk_split(const unsigned short *__restrict__ SA,
-                                                   const int *__restrict__ EA,
-                                                   const unsigned short *__restrict__ SB,
-                                                   const int *__restrict__ EB, int ng, int gpad, int nt,
-                                                   int nchunk, int nsplit, int chunks_per_split,
-                                                   double2 *__restrict__ part, int add) {
-    __shared__ __attribute__((aligned(1024))) unsigned char stage0[STAGE_LDS];
-    __shared__ __attribute__((aligned(1024))) unsigned char stage1[STAGE_LDS];
-    __shared__ __attribute__((aligned(1024))) unsigned char stage2[STAGE_LDS];
-    __shared__ __attribute__((aligned(1024))) unsigned char stage3[STAGE_LDS];
-
-    const int ntiles = nt * (nt + 1) / 2;
-    int split, u;
-    if (nsplit % 8 == 0) {
-        const int x = blockIdx.x % 8, j = blockIdx.x / 8;
-        split = x + 8 * (j / ntiles);
-        u = j % ntiles;
-    } else {
-        split = blockIdx.x % nsplit;
-        u = blockIdx.x / nsplit;
+// One k-step x: stage step x + 2 into `nx2`, slice this lane's row of the
+// weighted side from `cur`, 80 MFMAs over the four column blocks, then wait
+// for step x + 1 (its loads were issued a step earlier; those of x + 2 stay
+// in flight).  The three stages are distinct restrict-qualified buffers, so
+// the compiler knows that the loads in flight into one do not alias the reads
+// of another and inserts no wait for them.
+__device__ __forceinline__ void split_step(const unsigned char *__restrict__ cur, unsigned char *__restrict__ nx2,
+                                           unsigned char *__restrict__ ebuf2, const StageSrc &S, long long x, long long s1,
+                                           long long tbase, long long K, double up, int wave, int lane, int li,
+                                           int lq, SplitAcc &acc) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (x + 2 < s1) stage_issue(nx2, ebuf2, S, tbase + (x + 2) * KSP, x + 2, wave, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    // the weighted side of this lane's row, sliced into digits (pairs >= K weigh 0)
+    uint4 af[NSL], as[NSL];
+    {
+        const long long tp = tbase + x * KSP + 4 * lq;
+        const double *wl = reinterpret_cast<const double *>(cur + W_OFF) + 4 * lq;
+        double sw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sw[j] = tp + j < K ? wl[j] * up : 0.0;
+        slice_frags(cur + (4 * lq) * 1024 + (16 * (wave >> 1) + li) * 16, sw, af, as);
     }
-    int ti, tj;
-    grouped_tile(u, nt, ti, tj);
-    const int G0 = ti * TT, H0 = tj * TT;
-    const int c0 = split * chunks_per_split;
-    const int c1 = min(nchunk, c0 + chunks_per_split);
-    const size_t slice_stride = (size_t)nchunk * NKS * gpad * KS;
+    const unsigned char *Bs = cur + A_LDS;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        uint4 bf[NSL];
+#pragma unroll
+        for (int sl = 0; sl < NSL; ++sl) bf[sl] = bfrag(Bs + sl * B_SLICE_LDS, 64 * (wave & 1) + 16 * cb + li, lq);
+        split_mfma(af, as, bf, acc.g[cb]);
+    }
+    if (x + 2 >= s1) BGW_WAIT_VM(0);
+    else if (wave == 1) BGW_WAIT_VM(PIECES + 1);
+    else if (wave == 0 && (x + 2) % NKS == 0) BGW_WAIT_VM(PIECES + 2);
+    else BGW_WAIT_VM(PIECES);
+    stage_barrier();
+}
+
+// Persistent split-precision chi sum over every (q, weight vector, tile, K
+// split) item of a launch.  Entry q owns the items q.item0 .. q.item0 +
+// q.nitems (a multiple of 8); item i always runs on XCD i % 8 (a grid that
+// is a multiple of 8, workgroups dealt to the XCDs round-robin), and XCD x
+// takes the x-th contiguous eighth of the entry's (split, tile, vector)
+// sequence, vector fastest: the blocks resident on one XCD work on the same
+// tile for consecutive weight vectors (frequencies), reading the same rows of
+// M and the same slices, which their L2 then serves.  With one weight vector
+// the sequence walks the tiles in bands of eight row tiles.
+// Block: 8 waves, two per SIMD; wave w owns rows 16 (w/2) .. +16 and columns
+// 64 (w%2) .. +64 (four column blocks) of the 64 x 128 tile, so each row is
+// sliced by the two waves that share it, and one wave's slicing and LDS
+// reads run under the MFMAs of the other wave on its SIMD.
+// Every k-step (16 pairs) the block stages 16 pair rows of M (the tile's 64
+// columns), the four digit slices of the unweighted side (128 columns) and
+// the 16 weights into LDS with direct global->LDS loads, two steps ahead
+// through three stages; each wave slices its 16 rows of w_t M_t(G) into BF16
+// digits in registers and issues 80 MFMAs.
+// out (+)= raw sums (no prefactor) of every element of the tile inside ng x ng.
+__global__ __launch_bounds__(XT, 1) void k_chi_split(const SplitQ *__restrict__ qs, int nq, long long i0,
+                                                     long long i1) {
+    __shared__ __attribute__((aligned(1024))) unsigned char stage0[STG];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage1[STG];
+    __shared__ __attribute__((aligned(1024))) unsigned char stage2[STG];
+    __shared__ __attribute__((aligned(1024))) unsigned char ebufs[2][E_LDS];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = wave >> 2, wc = wave & 3;
     const int li = lane & 15, lq = lane >> 4;
 
-    // this lane's source offsets (bytes) for its pieces of a stage
-    unsigned off[PIECES];
-#pragma unroll
-    for (int i = 0; i < PIECES; ++i) {
-        const int q = PIECES * wave + i;
-        const int row = 16 * (q & 3) + (lane >> 2);
-        const int seg = (lane & 3) ^ (row & 3);
-        off[i] = (unsigned)((((q >> 2) < NSL ? G0 : H0) + row) * KS * 2 + seg * 16);
-    }
-
-    HerkAcc acc;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc.re[a][r] = acc.im[a][r] = 0.0;
-#pragma unroll
-        for (int p = 0; p < NGR; ++p)
-#pragma unroll
-            for (int ri = 0; ri < 2; ++ri) acc.g[p][ri][a] = (float4_t){0.f, 0.f, 0.f, 0.f};
-    }
-
-    const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;  // s1 - s0: a multiple of NKS (8)
-    herk_pipeline(stage0, stage1, stage2, stage3, SA, SB, EA, EB, off, slice_stride, s0, s1, gpad, G0, H0, wave, wr,
-                  wc, li, lq, acc);
-    double2 *o = part + (size_t)split * ng * ng;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int G = G0 + wr * 32 + 16 * a + 4 * lq + r;
-            const int H = H0 + wc * 16 + li;
-            if (G < ng && H < ng) {
-                double2 v = make_double2(acc.re[a][r], acc.im[a][r]);
-                if (add) v = cadd(v, o[(size_t)G * ng + H]);
-                o[(size_t)G * ng + H] = v;
-            }
+    for (long long item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
+        int lo = 0, hi = nq - 1;  // last entry with item0 <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (qs[mid].item0 <= item) lo = mid;
+            else hi = mid - 1;
         }
+        const SplitQ &Q = qs[lo];
+        const long long local = item - Q.item0;
+        const long long per = Q.nitems / 8;  // items per XCD
+        const long long u = (local % 8) * per + local / 8;
+        const long long total = (long long)Q.ntiles * Q.ns * Q.nvec;
+        if (u >= total) continue;  // padding item
+        const int v = (int)(u % Q.nvec);
+        const long long r0 = u / Q.nvec;
+        const int tile = (int)(r0 % Q.ntiles);
+        const int split = (int)(r0 / Q.ntiles);
+        const unsigned tw = Q.tiles[tile];
+        const int G0 = (int)(tw & 0xffff) * TR, H0 = (int)(tw >> 16) * TC;
+        const int c0 = (int)((long long)split * Q.nch / Q.ns);
+        const int c1 = (int)((long long)(split + 1) * Q.nch / Q.ns);
+        const int ng = Q.ng, gpad = Q.gpad;
+        const size_t slice_stride = (size_t)Q.nch * NKS * gpad * KS;
+
+        StageSrc S;
+        S.a_base = reinterpret_cast<const char *>(Q.M + min(G0 + lane, ng - 1));
+        S.a_row_bytes = (long long)ng * 16;
+        S.kmax = Q.K - 1;
+        {
+            const int row = 64 * (wave & 1) + (lane >> 2);
+            const int seg = (lane & 3) ^ (row & 3);
+            S.b_base = reinterpret_cast<const char *>(Q.SB + (wave >> 1) * slice_stride) +
+                       ((size_t)(H0 + row) * KS * 2 + seg * 16);
+        }
+        S.b_step_bytes = (size_t)gpad * KS * 2;
+        S.w = Q.w + (size_t)v * Q.wstride;
+        S.eb = Q.EB;
+        S.ea = Q.EA + (size_t)v * Q.nch * gpad;
+        S.gpad = gpad;
+        S.G0 = G0;
+        S.H0 = H0;
+
+        SplitAcc acc;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc.re[cb][r] = acc.im[cb][r] = 0.0;
+
+        // k-steps [s0, s1) of the launch's chunk range; pair of step x: (chunk0 * 8 + x) * 16
+        const long long s0 = (long long)c0 * NKS, s1 = (long long)c1 * NKS;
+        const long long tbase = (long long)Q.chunk0 * SKP;
+        const long long K = Q.K;
+        const bool in = G0 + 16 * (wave >> 1) + li < ng;  // this lane's slicing row is inside the matrix
+
+        // steps s0 and s0 + 1 (s1 - s0 >= NKS > 2; s0 + 1 is not a chunk start)
+        stage_issue(stage0, ebufs[c0 & 1], S, tbase + s0 * KSP, s0, wave, lane);
+        stage_issue(stage1, ebufs[c0 & 1], S, tbase + (s0 + 1) * KSP, s0 + 1, wave, lane);
+        if (wave == 1) BGW_WAIT_VM(PIECES + 1);
+        else BGW_WAIT_VM(PIECES);
+        stage_barrier();
+
+        for (int ch = c0; ch < c1; ++ch) {
+            const int *E = reinterpret_cast<const int *>(ebufs[ch & 1]);
+            unsigned char *En = ebufs[(ch + 1) & 1];
+            // slicing scale of this lane's row: 2^(8 - eA)
+            const double up =
+                in ? pow2(8 - (int)reinterpret_cast<const signed char *>(E)[512 + 16 * (wave >> 1) + li]) : 0.0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int p = 0; p < NGR; ++p)
+#pragma unroll
+                    for (int ri = 0; ri < 2; ++ri) acc.g[cb][p][ri] = (float4_t){0.f, 0.f, 0.f, 0.f};
+            const long long xb = (long long)ch * NKS;  // a multiple of 3: step xb uses stage0
+#pragma unroll 1
+            for (int ks = 0; ks < NKS; ks += 3) {
+                split_step(stage0, stage2, En, S, xb + ks, s1, tbase, K, up, wave, lane, li, lq, acc);
+                split_step(stage1, stage0, En, S, xb + ks + 1, s1, tbase, K, up, wave, lane, li, lq, acc);
+                split_step(stage2, stage1, En, S, xb + ks + 2, s1, tbase, K, up, wave, lane, li, lq, acc);
+            }
+            split_flush(acc, E, wave, li, lq);
+        }
+
+        double2 *o = Q.out + (size_t)v * Q.vstride + (size_t)split * ng * ng;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int G = G0 + 16 * (wave >> 1) + 4 * lq + r;
+                const int H = H0 + 64 * (wave & 1) + 16 * cb + li;
+                if (G < ng && H < ng) {
+                    double2 val = make_double2(acc.re[cb][r], acc.im[cb][r]);
+                    if (Q.add) val = cadd(val, o[(size_t)G * ng + H]);
+                    o[(size_t)G * ng + H] = val;
+                }
+            }
+        __syncthreads();  // the stages and exponent buffers are reused by the block's next item
+    }
 }
 
-// FP64 head row: hw[s][H] = sum_{t in split s} w_t conj(M_t(head)) M_t(H)
-__global__ void k_headwing(const double2 *__restrict__ M, long long K, int ng, int head,
-                           const double *__restrict__ w, long long kper, double2 *__restrict__ hw) {
+// FP64 head rows of every weight vector of one q in one pass over M:
+// hw[s][v][H] = sum_{t in K range s} w_v[t] conj(M_t(head)) M_t(H), for the
+// vectors [v0, v0 + nv) (at most kHeadVec).  grid: (ng / 256, ranges).
+constexpr int kHeadVec = 16;
+__global__ __launch_bounds__(256) void k_headwing(const double2 *__restrict__ M, long long K, int ng, int head,
+                                                  const double *__restrict__ w, long long wstride, int v0, int nv,
+                                                  long long kper, double2 *__restrict__ hw, int nvec) {
     const int H = blockIdx.x * blockDim.x + threadIdx.x;
     if (H >= ng) return;
     const long long k0 = blockIdx.y * kper, k1 = min(K, k0 + kper);
-    double2 s = make_double2(0.0, 0.0);
-    // eight pairs' loads in flight at a time; the sum keeps the order of t
-    constexpr int U = 8;
+    double sr[kHeadVec], si[kHeadVec];
+#pragma unroll
+    for (int v = 0; v < kHeadVec; ++v) sr[v] = si[v] = 0.0;
+    // four pairs' loads in flight at a time; every sum keeps the order of t
+    constexpr int U = 4;
     for (long long t0 = k0; t0 < k1; t0 += U) {
-        double2 a[U], b[U];
-        double wt[U];
+        double2 p[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const long long t = t0 + u;
-            const bool in = t < k1;
-            a[u] = in ? M[t * ng + head] : make_double2(0.0, 0.0);
-            b[u] = in ? M[t * ng + H] : make_double2(0.0, 0.0);
-            wt[u] = in ? w[t] : 0.0;
+            if (t < k1) {
+                const double2 a = M[t * ng + head], b = M[t * ng + H];
+                p[u] = make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);  // conj(a) b
+            } else {
+                p[u] = make_double2(0.0, 0.0);
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            s.x += wt[u] * (a[u].x * b[u].x + a[u].y * b[u].y);
-            s.y += wt[u] * (a[u].x * b[u].y - a[u].y * b[u].x);
+        for (int v = 0; v < kHeadVec; ++v) {
+            if (v < nv) {
+                const double *wv = w + (size_t)(v0 + v) * wstride;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double wt = t0 + u < k1 ? wv[t0 + u] : 0.0;
+                    sr[v] = fma(wt, p[u].x, sr[v]);
+                    si[v] = fma(wt, p[u].y, si[v]);
+                }
+            }
         }
     }
-    hw[(size_t)blockIdx.y * ng + H] = s;
+#pragma unroll
+    for (int v = 0; v < kHeadVec; ++v)
+        if (v < nv) hw[((size_t)blockIdx.y * nvec + v0 + v) * ng + H] = make_double2(sr[v], si[v]);
 }
 
-// chi[head][H] (+)= pf sum_s hw[s][H]; chi[H][head] (+)= conj of it; chi[head][head] real.
-__global__ void k_headwing_write(const double2 *__restrict__ hw, int nsplit, int ng, int head, double pf,
-                                 double2 *__restrict__ chi, int accumulate) {
+// Row and column `head` of every output matrix of one q: with A from vector
+// va and (real frequency axis) B from vector vb = va + 1,
+// chi[head][H] (+)= pf (A_H + i B_H), chi[H][head] (+)= pf (conj A_H + i conj B_H),
+// where A_H = sum_s hw[s][va][H]; without B, chi is Hermitian and its head
+// diagonal exactly real.  grid: (ng / 256, output matrices).
+__global__ void k_headwing_write(const double2 *__restrict__ hw, int nsplit, int nvec, int ng, int head, double pf,
+                                 double2 *__restrict__ chi, int two, int accumulate) {
     const int H = blockIdx.x * blockDim.x + threadIdx.x;
     if (H >= ng) return;
-    double2 s = make_double2(0.0, 0.0);
-    for (int p = 0; p < nsplit; ++p) s = cadd(s, hw[(size_t)p * ng + H]);
-    double2 v = make_double2(pf * s.x, pf * s.y);
-    if (H == head) v.y = 0.0;
+    const int f = blockIdx.y;
+    const int va = two ? 2 * f : f;
+    double2 a = make_double2(0.0, 0.0), b = make_double2(0.0, 0.0);
+    for (int p = 0; p < nsplit; ++p) a = cadd(a, hw[((size_t)p * nvec + va) * ng + H]);
+    if (two)
+        for (int p = 0; p < nsplit; ++p) b = cadd(b, hw[((size_t)p * nvec + va + 1) * ng + H]);
+    if (H == head) {
+        a.y = 0.0;
+        b.y = 0.0;
+    }
+    // row: A_H + i B_H; column: conj(A_H) + i conj(B_H)
+    const double2 vr = make_double2(pf * (a.x - b.y), pf * (a.y + b.x));
+    const double2 vc = make_double2(pf * (a.x + b.y), pf * (-a.y + b.x));
+    double2 *cm = chi + (size_t)f * ng * ng;
     const size_t rowi = (size_t)head * ng + H, coli = (size_t)H * ng + head;
     if (accumulate) {
-        chi[rowi] = cadd(chi[rowi], v);
-        if (H != head) chi[coli] = cadd(chi[coli], make_double2(v.x, -v.y));
+        cm[rowi] = cadd(cm[rowi], vr);
+        if (H != head) cm[coli] = cadd(cm[coli], vc);
     } else {
-        chi[rowi] = v;
-        if (H != head) chi[coli] = make_double2(v.x, -v.y);
+        cm[rowi] = vr;
+        if (H != head) cm[coli] = vc;
     }
 }
 
@@ -505,124 +650,62 @@ int device_cus() {
     return cus;
 }
 
-namespace {
-struct SplitPlan {
-    int gpad, nt;
-    long long tiles;
-    long long sc_pairs;  // pairs per super-chunk (multiple of 128)
-    int nsplit;
-    size_t slice_bytes;  // one side, one super-chunk
-};
+int split_gpad(int ng) { return (ng + TC - 1) / TC * TC; }
 
-// Splits of the chunk range: a multiple of the XCD count (8) when there are
-// enough chunks, chosen so that tiles * nsplit fills whole waves of one block
-// per CU as evenly as possible.
-int choose_nsplit(long long tiles, long long nch) {
-    const long long cus = device_cus();
-    if (nch < 8) return (int)std::max<long long>(1, nch);
-    int best = 8;
-    double best_eff = 0.0;
-    for (int ns = 8; ns <= 64 && ns <= nch; ns += 8) {
-        const long long cps = (nch + ns - 1) / ns;
-        const long long used = (nch + cps - 1) / cps;
-        if (used != ns) continue;  // keep the XCD-aligned mapping
-        const long long blocks = tiles * used;
-        const long long rounds = (blocks + cus - 1) / cus;
-        // useful chunk-steps over issued block-rounds of the longest block
-        const double eff = (double)(tiles * nch) / (double)(rounds * cus * cps);
-        if (eff > best_eff * 1.02) {
-            best = ns;
-            best_eff = eff;
-        }
+long long split_chunks(long long K) { return (K + SKP - 1) / SKP; }
+
+size_t split_slices_only_bytes(long long nch, int ng) { return (size_t)nch * NSL * SK * split_gpad(ng) * 2; }
+
+size_t split_slice_bytes(long long nch, int ng) {
+    return split_slices_only_bytes(nch, ng) + sizeof(int) * (size_t)nch * split_gpad(ng);
+}
+
+// Upper tiles in walk order: bands of eight row tiles, each band walked
+// column tile by column tile.
+void split_tiles(int ng, std::vector<unsigned> &out) {
+    const int nti = (ng + TR - 1) / TR, ntj = (ng + TC - 1) / TC;
+    out.clear();
+    for (int b0 = 0; b0 < nti; b0 += 8)
+        for (int J = 0; J < ntj; ++J)
+            for (int I = b0; I < std::min(nti, b0 + 8); ++I)
+                if (I <= 2 * J + 1) out.push_back((unsigned)I | ((unsigned)J << 16));
+}
+
+int split_grid() { return device_cus() / 8 * 8; }
+
+int launch_split_slices(const double2 *M, long long K, int ng, long long c0, int nch, unsigned short *S, int *E,
+                        const double *w, long long wstride, int nvec, signed char *EA, hipStream_t st) {
+    const int gpad = split_gpad(ng);
+    hipLaunchKernelGGL(k_split_slice, dim3(gpad / 32, nch), dim3(SLICE_T), 0, st, M, K, ng, gpad, c0, nch, S, E, w,
+                       wstride, nvec, EA);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_chi_split(const SplitQ *qs, int nq, long long nitems, hipStream_t st) {
+    if (nitems <= 0) return BGW_OK;
+    const long long g = std::max<long long>(8, std::min<long long>(nitems, split_grid()));
+    hipLaunchKernelGGL(k_chi_split, dim3((unsigned)g), dim3(XT), 0, st, qs, nq, 0ll, nitems);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_headwing(const double2 *M, long long K, int ng, int head, const double *w, long long wstride, int nvec,
+                    int nsplit, double2 *hw, hipStream_t st) {
+    const long long kper = (K + nsplit - 1) / nsplit;
+    for (int v0 = 0; v0 < nvec; v0 += kHeadVec) {
+        const int nv = std::min(kHeadVec, nvec - v0);
+        hipLaunchKernelGGL(k_headwing, dim3((ng + 255) / 256, nsplit), dim3(256), 0, st, M, K, ng, head, w, wstride,
+                           v0, nv, kper, hw, nvec);
     }
-    return best;
-}
-
-SplitPlan make_plan(long long K, int ng, int nsplit_override) {
-    SplitPlan p;
-    p.gpad = (ng + TT - 1) / TT * TT;
-    p.nt = p.gpad / TT;
-    p.tiles = (long long)p.nt * (p.nt + 1) / 2;
-    const long long nch_total = (K + SKP - 1) / SKP;
-    // slices of one side for a super-chunk: NSL * SK * gpad * 2 bytes per chunk
-    const size_t per_chunk = (size_t)NSL * SK * p.gpad * 2;
-    size_t cap = (size_t)6 << 30;  // 6 GiB per side (BGW_SPLIT_SLICE_BYTES overrides)
-    if (const char *env = std::getenv("BGW_SPLIT_SLICE_BYTES")) cap = std::max<size_t>(1, std::strtoull(env, nullptr, 10));
-    long long nch = std::max<long long>(1, std::min<long long>(nch_total, cap / per_chunk));
-    p.sc_pairs = nch * SKP;
-    p.slice_bytes = per_chunk * nch;
-    p.nsplit = nsplit_override > 0 ? (int)std::min<long long>(nsplit_override, nch) : choose_nsplit(p.tiles, nch);
-    return p;
-}
-
-constexpr int kHeadSplits = 512;  // K ranges of the FP64 head row (enough blocks to stream M at full rate)
-
-size_t al(size_t b) { return (b + 255) / 256 * 256; }
-}  // namespace
-
-int split_workspace_bytes(long long K, int ng, int nsplit_override, size_t *bytes) {
-    const SplitPlan p = make_plan(K, ng, nsplit_override);
-    const long long nch = p.sc_pairs / SKP;
-    size_t b = 0;
-    b += 2 * al(p.slice_bytes);                                     // SA, SB
-    b += 2 * al(sizeof(int) * (size_t)nch * p.gpad);               // EA, EB
-    b += al(sizeof(double2) * (size_t)p.nsplit * ng * ng);          // partial sums
-    b += al(sizeof(double2) * (size_t)kHeadSplits * ng);            // head row partials
-    *bytes = b + 1024;
-    return BGW_OK;
-}
-
-// Phase launchers used by the API (each phase is timed separately there).
-SplitLayout split_layout(long long K, int ng, int nsplit_override, void *ws) {
-    const SplitPlan p = make_plan(K, ng, nsplit_override);
-    SplitLayout L;
-    L.gpad = p.gpad;
-    L.nt = p.nt;
-    L.tiles = p.tiles;
-    L.sc_pairs = p.sc_pairs;
-    L.nsplit = p.nsplit;
-    const long long nch_sc = p.sc_pairs / SKP;
-    char *q = (char *)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-    L.SA = (unsigned short *)q; q += al(p.slice_bytes);
-    L.SB = (unsigned short *)q; q += al(p.slice_bytes);
-    L.EA = (int *)q; q += al(sizeof(int) * (size_t)nch_sc * p.gpad);
-    L.EB = (int *)q; q += al(sizeof(int) * (size_t)nch_sc * p.gpad);
-    L.part = (double2 *)q; q += al(sizeof(double2) * (size_t)p.nsplit * ng * ng);
-    L.hw = (double2 *)q;
-    return L;
-}
-
-int launch_split_slices(const SplitLayout &L, const double2 *M, long long K, int ng, const double *w, long long t0,
-                        int nch, bool with_b, hipStream_t st) {
-    dim3 sg(L.gpad / 32, nch);
-    hipLaunchKernelGGL(k_split_slice, sg, dim3(256), 0, st, M, K, ng, L.gpad, w, t0, nch, L.SA, L.EA,
-                       with_b ? L.SB : (unsigned short *)nullptr, with_b ? L.EB : (int *)nullptr);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
 
-// Writes split slots [0, *used).  With add != 0 the slots [0, add) hold the
-// sums of earlier super-chunks and at most that many are used.
-int launch_split_gemm(const SplitLayout &L, int ng, int nch, int add, int *used, hipStream_t st) {
-    int ns = std::min(L.nsplit, nch);
-    if (nch < L.sc_pairs / SKP) ns = choose_nsplit(L.tiles, nch);  // short last super-chunk
-    ns = std::min(ns, add > 0 ? add : L.nsplit);
-    const int cps = (nch + ns - 1) / ns;
-    const int nsplit_used = (nch + cps - 1) / cps;
-    hipLaunchKernelGGL(k_herk_split, dim3((unsigned)(L.tiles * nsplit_used)), dim3(HT), 0, st, L.SA, L.EA,
-                       L.SB, L.EB, ng, L.gpad, L.nt, nch, nsplit_used, cps, L.part, add > 0 ? 1 : 0);
-    BGW_HIP(hipGetLastError());
-    *used = nsplit_used;
-    return BGW_OK;
-}
-
-int launch_split_headwing(const SplitLayout &L, const double2 *M, long long K, int ng, int head, const double *w,
-                          double pf, double2 *chi, int accumulate, hipStream_t st) {
-    const long long kper = (K + kHeadSplits - 1) / kHeadSplits;
-    hipLaunchKernelGGL(k_headwing, dim3((ng + 255) / 256, kHeadSplits), dim3(256), 0, st, M, K, ng, head, w, kper,
-                       L.hw);
-    hipLaunchKernelGGL(k_headwing_write, dim3((ng + 255) / 256), dim3(256), 0, st, L.hw, kHeadSplits, ng, head, pf,
-                       chi, accumulate);
+int launch_headwing_write(const double2 *hw, int nsplit, int nvec, int ng, int head, double pf, double2 *chi, int nout,
+                          int two, int accumulate, hipStream_t st) {
+    hipLaunchKernelGGL(k_headwing_write, dim3((ng + 255) / 256, nout), dim3(256), 0, st, hw, nsplit, nvec, ng, head,
+                       pf, chi, two, accumulate);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }

@@ -62,7 +62,12 @@ def test_pair_desc_validation_codes():
     assert bgw.pair_desc_check(16, gw, ge, nv=-1) == bgw.BGW_ERR_ARG
     big = synth.gvector_list(8193)
     assert bgw.pair_desc_check(128, big, big) == bgw.BGW_ERR_UNSUPPORTED
-    assert "duplicate" in bgw.lib().bgw_last_error().decode() or True
+    assert "8192" in bgw.lib().bgw_last_error().decode()
+    # the message names the failing check
+    dup = gw.copy()
+    dup[7] = dup[3]
+    assert bgw.pair_desc_check(16, dup, ge) == bgw.BGW_ERR_SHAPE
+    assert "duplicate" in bgw.lib().bgw_last_error().decode()
 
 
 def test_transform_box_is_minimal_alias_free():
@@ -119,6 +124,17 @@ def test_vcoul_bulk_matches_oracle():
     with pytest.raises(bgw.BgwError) as e:
         bgw.vcoul_bulk(s["bmat"], np.zeros(3), q["ge"])
     assert e.value.code == bgw.BGW_ERR_SHAPE
+
+
+def test_vcoul_bulk_non_cubic_cell():
+    """The library's Coulomb helper on a skewed reciprocal basis, against the
+    hand-computed values (q = (0.1, 0.2, -0.3); G = (1, -2, 3) gives
+    |q+G|^2 = 37.1396 and G = 0 gives 0.4996 with rows of B as b_i)."""
+    B = np.array([[1.0, 0.2, 0.0], [0.1, 1.5, 0.3], [0.0, -0.4, 2.0]])
+    ge = np.array([[1, -2, 3], [0, 0, 0]], dtype=np.int32)
+    v = bgw.vcoul_bulk(B, np.array([0.1, 0.2, -0.3]), ge)
+    assert abs(v[0] - 4 * np.pi / 37.1396) <= 1e-14 * v[0]
+    assert abs(v[1] - 4 * np.pi / 0.4996) <= 1e-14 * v[1]
 
 
 def test_generator_is_deterministic():

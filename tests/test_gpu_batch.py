@@ -159,7 +159,7 @@ def test_autotune_and_cache(torch_dev, uneven, tmp_path):
                 assert cfg["tuned"]
                 assert cfg["tile"] in (32, 64) and cfg["items_per_cu"] in (2, 8, 32)
                 if prec == bgw.SPLIT_BF16:
-                    assert cfg["split_nsplit"] in (8, 16, 24, 32)
+                    assert cfg["split_nsplit"] in (1, 2, 4, 8, 16)
             # tuned plans still match the oracle
             chis = h.chi0(ents, uneven["om"], precision=prec)
             torch.cuda.synchronize()
@@ -177,6 +177,47 @@ def test_autotune_and_cache(torch_dev, uneven, tmp_path):
         h2.close()
     finally:
         del os.environ["BGW_TUNE_CACHE"]
+
+
+def test_split_partials_fully_written(torch_dev, tmp_path, monkeypatch):
+    """A K-split count that does not divide the chunk count (7 splits of the
+    10 chunks of K = 960 pairs) on a handle whose workspace already holds an
+    earlier call's partial sums: every partial sum the finalize adds must be
+    written by this call's GEMM."""
+    torch = torch_dev[0]
+    s = synth.small_system(n=16, ngw=300, ng=150, nv=4, nc=60, nk=4, seed=5)
+    q = s["qs"][0]
+    K = s["nk"] * s["nv"] * s["nc"]
+    assert K == 960
+    M = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    pf = 1.0 / (s["nk"] * s["vol"])
+    om = np.array([0.0, 2.0, 20.0])
+    ent = dict(M=dev(torch_dev, M), ev=dev(torch_dev, q["ev"]), ec=dev(torch_dev, s["ec"]), nk=s["nk"], nv=s["nv"],
+               nc=s["nc"], head=0, prefactor=pf)
+    ref = oracle.chi(M, oracle.weights(q["ev"], s["ec"], om), pf)
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("BGW_TUNE_CACHE", str(cache))
+    h = bgw.Handle(0)
+    h.autotune([ent], om, precision=bgw.SPLIT_BF16)
+    h.close()
+    lines = [json.loads(l) for l in cache.read_text().splitlines()]
+    extra = [dict(l, nsplit=7) for l in lines if l["precision"] == bgw.SPLIT_BF16]
+    assert extra
+    with open(cache, "a") as f:
+        for l in extra:
+            f.write(json.dumps(l) + "\n")
+    h2 = bgw.Handle(0)
+    assert h2.tuned_config(bgw.SPLIT_BF16, q["ng"], K)["split_nsplit"] == 7
+    # an accumulating FP64 call leaves its partial sums in the workspace
+    acc = torch.zeros((len(om), q["ng"], q["ng"]), dtype=torch.complex128, device=ent["M"].device)
+    h2.chi0([ent], om, chis=[acc], accumulate=True)
+    for rep in range(2):
+        (c,) = h2.chi0([ent], om, precision=bgw.SPLIT_BF16)
+        torch.cuda.synchronize()
+        c = c.cpu().numpy()
+        for i in range(len(om)):
+            assert rel(c[i], ref[i]) <= SPLIT_TOL, (rep, i)
+    h2.close()
 
 
 def test_many_frequencies_one_launch(torch_dev):

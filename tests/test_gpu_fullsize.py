@@ -119,38 +119,45 @@ def test_supercell_96_full(torch_dev, handle):
 
 
 def test_imag_freq_64_full(torch_dev, handle):
-    """64^3 grid, Ng = 4000, K = 512000, three of the 32 Gauss-Legendre
-    frequencies (first, 16th, last) batched in one call."""
+    """64^3 grid, Ng = 4000, K = 512000: all 32 Gauss-Legendre frequencies in
+    one split-precision call (the workload's precision) against the oracle
+    on sampled blocks of every frequency; FP64 at the first, 16th and last
+    frequency in one batched call, against the oracle and the split result."""
     torch = torch_dev[0]
     s = synth.make_system(synth.WORKLOADS["imag-freq-64"])
     q = s["qs"][0]
     ng = q["ng"]
-    om = s["omega"][[0, 15, 31]]
+    om_all = s["omega"]
+    assert len(om_all) == 32
+    pick = [0, 15, 31]
     M = handle.pair_density(s["n"], s["gw"], q["ge"], dev(torch_dev, q["cv"]), dev(torch_dev, s["cc"]))
     torch.cuda.synchronize()
     check_M_samples(torch_dev, s, q, M, npairs=16, seed=3)
     pf = 1.0 / (s["nk"] * s["vol"])
     ent = [dict(M=M, ev=dev(torch_dev, q["ev"]), ec=dev(torch_dev, s["ec"]), nk=s["nk"], nv=s["nv"], nc=s["nc"],
                 head=0, prefactor=pf)]
-    (c64,) = handle.chi0(ent, om, precision=bgw.FP64)
-    (csp,) = handle.chi0(ent, om, precision=bgw.SPLIT_BF16)
+    (csp,) = handle.chi0(ent, om_all, precision=bgw.SPLIT_BF16)
+    (c64,) = handle.chi0(ent, om_all[pick], precision=bgw.FP64)
     torch.cuda.synchronize()
     rows, cols = sample_index(ng, 21, 4), sample_index(ng, 21, 5)
-    w = oracle.weights(q["ev"], s["ec"], om)
+    w = oracle.weights(q["ev"], s["ec"], om_all)
     ref = oracle_block(torch_dev, M, w, pf, rows, cols)
     ri, ci = torch.from_numpy(rows).to(M.device), torch.from_numpy(cols).to(M.device)
-    for i in range(len(om)):
-        assert rel(c64[i][ri][:, ci].cpu().numpy(), ref[i]) <= TOL
-        assert rel(csp[i][ri][:, ci].cpu().numpy(), ref[i]) <= SPLIT_TOL
-        assert float(torch.linalg.vector_norm(csp[i] - c64[i]) / torch.linalg.vector_norm(c64[i])) <= SPLIT_TOL
+    for i in range(len(om_all)):
+        assert rel(csp[i][ri][:, ci].cpu().numpy(), ref[i]) <= SPLIT_TOL, i
+        assert rel(csp[i][0].cpu().numpy(), csp[i][:, 0].conj().cpu().numpy()) == 0.0
+    for j, i in enumerate(pick):
+        assert rel(c64[j][ri][:, ci].cpu().numpy(), ref[i]) <= TOL
+        assert float(torch.linalg.vector_norm(csp[i] - c64[j]) / torch.linalg.vector_norm(c64[j])) <= SPLIT_TOL
+        assert rel(csp[i][0].cpu().numpy(), c64[j][0].cpu().numpy()) <= 1e-13  # FP64 head row in split mode
     # |chi_GG(i omega)| decreases with omega
-    d = torch.diagonal(c64, dim1=1, dim2=2).abs()
-    assert bool((d[1] <= d[0]).all()) and bool((d[2] <= d[1]).all())
-    del M
+    d = torch.diagonal(csp, dim1=1, dim2=2).abs()
+    assert bool((d[1:] <= d[:-1]).all())
+    del M, c64
     v = dev(torch_dev, bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"]))
     einv, info = handle.eps_inv(v, csp)
     torch.cuda.synchronize()
-    assert int(info.cpu().max()) == 0
+    assert int(info.cpu().max()) == 0 and int(info.cpu().min()) == 0
     check_eps_inv(torch_dev, v, csp, einv)
 
 
