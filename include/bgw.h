@@ -238,6 +238,20 @@ int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const doubl
  * *bytes).  Allocates nothing. */
 int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes);
 
+/* bgw_eps_inv for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels and results as bgw_eps_inv; it calls no hipMalloc,
+ * hipFree or allocating library routine and records no timings.  Its scratch
+ * is a fixed 32 MiB device array inside the library, one per device, held
+ * until the process ends (its address is taken by bgw_create); the matrices
+ * are inverted in launches of as many as that scratch holds.  Fails with
+ * BGW_ERR_UNSUPPORTED if one matrix needs more (not the case for ng <= 8192,
+ * about 0.5 KiB per unit of ng).  Every call on one device shares that
+ * device's scratch: calls that overlap on one device (other streams, other
+ * threads, other handles) race and must be serialised by the caller. */
+int bgw_eps_inv_noalloc(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
+                        double *epsinv, int *info, void *stream);
+
 /* ------------------------------------------------------------------------
  * Per-kernel timing.  When enabled, every kernel launch (or launch group)
  * of the compute calls is bracketed by HIP events recorded on the call's

@@ -38,7 +38,7 @@ EXPORTS = [
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
-    "bgw_ff_grid",
+    "bgw_ff_grid", "bgw_eps_inv_noalloc",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -126,6 +126,7 @@ def lib():
         L.bgw_pair_density.argtypes = [P, ctypes.POINTER(PairDesc), P, P]
         L.bgw_chi0.argtypes = [P, ctypes.POINTER(ChiDesc), P]
         L.bgw_eps_inv.argtypes = [P, I, I, P, P, P, P, P]
+        L.bgw_eps_inv_noalloc.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
         L.bgw_set_timing.argtypes = [P, I]
         L.bgw_get_timing.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
@@ -141,7 +142,7 @@ def lib():
         for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
-                  "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid"):
+                  "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -385,4 +386,17 @@ class Handle:
             info = torch.empty(nw, dtype=torch.int32, device=chi.device)
         _check(lib().bgw_eps_inv(self._h, ng, nw, _dptr(vcoul.contiguous()), _dptr(chi), _dptr(epsinv),
                                  _dptr(info), _stream()))
+        return epsinv, info
+
+    def eps_inv_noalloc(self, vcoul, chi, epsinv, info):
+        """bgw_eps_inv_noalloc: epsilon^-1 into caller-owned epsinv and info, with the
+        library's fixed device scratch (no allocation by the library)."""
+        import torch
+        nw, ng, _ = chi.shape
+        assert chi.dtype == torch.complex128 and chi.is_contiguous()
+        assert epsinv.shape == chi.shape and epsinv.dtype == chi.dtype and epsinv.is_contiguous()
+        assert vcoul.dtype == torch.float64 and vcoul.numel() == ng and vcoul.is_contiguous()
+        assert info.dtype == torch.int32 and info.numel() == nw
+        _check(lib().bgw_eps_inv_noalloc(self._h, ng, nw, _dptr(vcoul), _dptr(chi), _dptr(epsinv), _dptr(info),
+                                         _stream()))
         return epsinv, info

@@ -52,6 +52,17 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
 namespace {
 thread_local std::string g_err;
 constexpr size_t kLdsBudget = 150 * 1024;
+
+// Fixed device scratch of the allocation-free inversion (bgw_eps_inv_noalloc).
+// Each device that loads the library holds its own copy until the process
+// ends.  In host code `scratch` is only the symbol's host stand-in: its
+// device address is looked up once per device (scratch_setup, called from
+// bgw_create with the device current) and only that address is passed on.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
 }  // namespace
 
 void set_error(const std::string &msg) { g_err = msg; }
@@ -415,6 +426,24 @@ int set_device(bgw_handle_t h) {
 
 }  // namespace bgw
 
+namespace {
+// Device address of `scratch` on device dev, looked up once with dev current.
+int scratch_setup(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return BGW_OK;
+    int prev = 0;
+    BGW_HIP(hipGetDevice(&prev));
+    BGW_HIP(hipSetDevice(dev));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr)
+        return fail(BGW_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    return BGW_OK;
+}
+}  // namespace
+
 extern "C" int bgw_create(bgw_handle_t *h, int hip_device) {
     clear_error();
     if (!h) return fail(BGW_ERR_ARG, "null handle pointer");
@@ -422,6 +451,8 @@ extern "C" int bgw_create(bgw_handle_t *h, int hip_device) {
     int count = 0;
     BGW_HIP(hipGetDeviceCount(&count));
     if (hip_device < 0 || hip_device >= count) return fail(BGW_ERR_ARG, "no such HIP device");
+    if (hip_device >= kMaxDevices) return fail(BGW_ERR_UNSUPPORTED, "device index beyond 63");
+    BGW_TRY(scratch_setup(hip_device));
     auto *hh = new (std::nothrow) bgw_handle_s();
     if (!hh) return fail(BGW_ERR_NOMEM, "out of host memory");
     hh->device = hip_device;
@@ -617,6 +648,37 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
     for (int w0 = 0; w0 < nw; w0 += group) {
         const int gn = std::min(group, nw - w0);
         BGW_TRY(launch_gje_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, info + w0, h->ws.p, ipiv, st));
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_eps_inv_noalloc(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
+                                   double *epsinv, int *info, void *stream) {
+    clear_error();
+    if (!h || ng < 1 || nw < 1 || !vcoul || !chi || !epsinv || !info)
+        return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_noalloc");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    BGW_TRY(set_device(h));
+    void *ws = g_scratch_ptr[h->device];
+    if (!ws) return fail(BGW_ERR_HIP, "no scratch address for this device");
+    hipStream_t st = (hipStream_t)stream;
+    // as many matrices per launch as bgw_eps_inv takes, cut to what the scratch holds
+    int group = 0;
+    size_t gws = 0, need = 0;
+    eps_plan(ng, nw, &group, &gws, &need);
+    while (group > 1 && need > kNoAllocScratchBytes) {
+        const int fewer = group - 1;
+        eps_plan(ng, fewer, &group, &gws, &need);
+    }
+    if (need > kNoAllocScratchBytes)
+        return fail(BGW_ERR_UNSUPPORTED, "bgw_eps_inv_noalloc: one matrix of ng = " + std::to_string(ng) + " needs " +
+                                             std::to_string(need) + " bytes of scratch, more than the fixed " +
+                                             std::to_string(kNoAllocScratchBytes));
+    int *ipiv = (int *)((char *)ws + ((gws + 255) / 256) * 256);
+    BGW_TRY(launch_eps_build((const double2 *)chi, vcoul, ng, nw, (double2 *)epsinv, st));
+    for (int w0 = 0; w0 < nw; w0 += group) {
+        const int gn = std::min(group, nw - w0);
+        BGW_TRY(launch_gje_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, info + w0, ws, ipiv, st));
     }
     return BGW_OK;
 }
