@@ -4,9 +4,13 @@
 One step = one pass of the whole path over the workload's q points: pair
 densities by FFT for every q -> energy weights + chi-sum for all q and all
 frequencies in one batched call -> epsilon and its inverse per q.  The
-default workload is the silicon-like bulk one (48^3 grid, Ng = 1500, Nv = 4,
-Nc = 400, Nk = 64, static, FP64); the other workloads (supercell-96,
-imag-freq-64, uneven-q-48 with a --q-subset) run in their own precision.
+default workload is imaginary-frequency chi0 (64^3 grid, Ng = 4000,
+K = 512,000 pairs, 32 frequencies, split-BF16 chi-sum, FP64 eps^-1): the
+largest configuration whose steps fit a run of a few minutes on one GPU.
+The other workloads run in their own precision; the uneven-q one streams
+its 64 q through the GPU in batches whose pair densities fit
+--m-budget-gb, one chi0 call per batch (--graph replays each batch's
+captured graph, --autotune tunes every size class first).
 Inputs are generated once (seeded, synthetic) and are resident in HBM before
 the timed region; W untimed warm-up steps, then exactly K timed steps
 bracketed by torch.cuda.synchronize().
@@ -37,24 +41,31 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2516.6
+SPLIT_PRODUCTS = 10  # BF16 slice products per FP64-equivalent product in the split form
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="silicon-like-48")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="imag-freq-64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-pairs", type=int, default=6400)
-    ap.add_argument("--split-reps", type=int, default=3)
+    ap.add_argument("--split-reps", type=int, default=2)
+    ap.add_argument("--split-omegas", type=int, default=4,
+                    help="frequencies of the split-vs-FP64 comparison (evenly spread subset; 0 = all)")
     ap.add_argument("--no-split", action="store_true")
     ap.add_argument("--no-full-grid", action="store_true")
-    ap.add_argument("--q-subset", default="spread4",
-                    help="uneven-q workloads: comma-separated q indices, or spreadN (N q spanning the Ng range)")
+    ap.add_argument("--q-subset", default="all",
+                    help="uneven-q workloads: all, comma-separated q indices, or spreadN (N q spanning the Ng range)")
+    ap.add_argument("--m-budget-gb", type=float, default=96.0,
+                    help="device memory for the pair densities of one q batch; the q are streamed in batches")
+    ap.add_argument("--autotune", action="store_true", help="run the autotuner on every q batch before the warm-up")
     ap.add_argument("--precision", choices=["fp64", "split"], default=None,
                     help="chi-sum precision of the step (default: the workload's)")
     ap.add_argument("--graph", action="store_true", help="chi0 through HIP-graph replay")
+    ap.add_argument("--no-graph-compare", action="store_true", help="skip the graph-vs-eager comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC byte-counter calibration)")
     return ap.parse_args()
@@ -181,15 +192,12 @@ def split_vs_fp64(torch, h, bgw, ents, omega, chis64, reps):
             err = max(err, float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
             head_err = max(head_err, float(torch.linalg.vector_norm(a[0] - b[0]) / torch.linalg.vector_norm(b[0])))
     nw = len(omega)
-    flops = issued = 0.0
+    flops = 0.0
     for e in ents:
         ng = int(e["M"].shape[1])
         K = int(e["M"].shape[0])
         flops += 4.0 * ng * ng * K * nw
-        gpad = (ng + 63) // 64 * 64
-        tiles = (gpad // 64) * (gpad // 64 + 1) // 2
-        nchunk = (K + 127) // 128
-        issued += tiles * 64.0 * 64.0 * nchunk * 256 * 2 * 20 * nw
+    issued = SPLIT_PRODUCTS * flops  # BF16 MFMA flops of the split form (ten slice products)
     tsp = res["split"][1]
     herk_ms = tsp["split_herk"][0] / reps
     t64 = res["fp64"][0]
@@ -209,7 +217,7 @@ def split_vs_fp64(torch, h, bgw, ents, omega, chis64, reps):
         "fp64_herk_ms": res["fp64"][1]["herk"][0] / reps,
         "split_chi_TFLOPs_fp64_equiv": flops / (tspl * 1e-3) / 1e12,
         "fp64_chi_TFLOPs": flops / (t64 * 1e-3) / 1e12,
-        "split_herk_bf16_issued_TFLOPs": issued / (herk_ms * 1e-3) / 1e12,
+        "split_herk_bf16_TFLOPs": issued / (herk_ms * 1e-3) / 1e12,
         "split_herk_frac_bf16_peak": issued / (herk_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
     }
 
@@ -262,7 +270,7 @@ def main():
         return
     wl = synth.WORKLOADS[args.workload]
     q_subset = None
-    if wl.nq > 1:
+    if wl.nq > 1 and args.q_subset != "all":
         if args.q_subset.startswith("spread"):
             cnt = int(args.q_subset[len("spread"):] or 4)
             sizes = synth.uneven_q_sizes(wl)
@@ -289,35 +297,78 @@ def main():
         ng = q["ng"]
         Q.append(dict(q=q, ng=ng, cv=torch.from_numpy(q["cv"]).to(dev), ev=torch.from_numpy(q["ev"]).to(dev),
                       v=torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev),
-                      M=torch.empty((K, ng), dtype=torch.complex128, device=dev),
                       chi=torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev),
                       einv=torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev),
                       info=torch.empty(nw, dtype=torch.int32, device=dev)))
-    ents = [dict(M=x["M"], ev=x["ev"], ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf) for x in Q]
-    chis = [x["chi"] for x in Q]
+    # q batches whose pair densities fit the M budget (one batch unless the q must be streamed);
+    # each batch's M live in one pool, reused by the next batch
+    budget = int(args.m_budget_gb * (1 << 30))
+    batches, cur, cur_b = [], [], 0
+    for i, x in enumerate(Q):
+        b = K * x["ng"] * 16
+        if cur and cur_b + b > budget:
+            batches.append(cur)
+            cur, cur_b = [], 0
+        cur.append(i)
+        cur_b += b
+    batches.append(cur)
+    pool_elems = max(sum(K * Q[i]["ng"] for i in bt) for bt in batches)
+    pool = torch.empty(pool_elems, dtype=torch.complex128, device=dev)
+    for bt in batches:
+        off = 0
+        for i in bt:
+            Q[i]["M"] = pool[off:off + K * Q[i]["ng"]].view(K, Q[i]["ng"])
+            off += K * Q[i]["ng"]
+    bents = [[dict(M=Q[i]["M"], ev=Q[i]["ev"], ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf) for i in bt]
+             for bt in batches]
+    bchis = [[Q[i]["chi"] for i in bt] for bt in batches]
+    ents, chis = bents[0], bchis[0]  # the first batch serves the split and graph comparisons
+    if len(batches) > 1:
+        print(f"[bench] {len(Q)} q streamed in {len(batches)} batches", file=sys.stderr, flush=True)
 
-    def step():
-        for x in Q:
-            h.pair_density(n, s["gw"], x["q"]["ge"], x["cv"], cc, M=x["M"])
-        h.chi0(ents, omega, precision=precision, chis=chis, use_graph=args.graph)
-        for x in Q:
-            h.eps_inv(x["v"], x["chi"], epsinv=x["einv"], info=x["info"])
+    def step(graph):
+        for bt, be, bc in zip(batches, bents, bchis):
+            for i in bt:
+                x = Q[i]
+                h.pair_density(n, s["gw"], x["q"]["ge"], x["cv"], cc, M=x["M"])
+            h.chi0(be, omega, precision=precision, chis=bc, use_graph=graph)
+            for i in bt:
+                x = Q[i]
+                h.eps_inv(x["v"], x["chi"], epsinv=x["einv"], info=x["info"])
 
+    if args.autotune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        for bt, be in zip(batches, bents):
+            for i in bt:
+                h.pair_density(n, s["gw"], Q[i]["q"]["ge"], Q[i]["cv"], cc, M=Q[i]["M"])
+            h.autotune(be, omega, precision=precision)
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        step()
+        step(args.graph)
     torch.cuda.synchronize()
+    if args.graph:
+        # the timed steps replay graphs (no per-kernel events inside them): one eager
+        # step first gives the per-kernel durations of the roofline entry
+        h.reset_timing()
+        h.set_timing(True)
+        step(False)
+        torch.cuda.synchronize()
+        h.set_timing(False)
+        tm = h.timing()
+        tm_steps = 1
     h.reset_timing()
-    h.set_timing(True)
+    h.set_timing(not args.graph)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(args.graph)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     h.set_timing(False)
-    tm = h.timing()
+    if not args.graph:
+        tm = h.timing()
+        tm_steps = args.steps
     for x in Q:
         assert int(x["info"].cpu().max()) == 0 and int(x["info"].cpu().min()) == 0
 
@@ -332,8 +383,8 @@ def main():
     fft_bytes_nominal = sum(K * 16.0 * (N + g) for g in ngs)
     lu_flops = sum(8.0 * g ** 3 * nw for g in ngs)
 
-    per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
-    launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
+    per_step = {k: tm[k][0] / tm_steps for k in tm if tm[k][1]}
+    launches = {k: tm[k][1] / tm_steps for k in tm if tm[k][1]}
     pair_t = per_step.get("pair", 0) + per_step.get("pair_x", 0)
     herk_key = "herk" if precision == bgw.FP64 else "split_herk"
     chi_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize", "split_slice", "split_herk",
@@ -352,6 +403,11 @@ def main():
         / (pair_t * 1e-3) / 1e12,
         "eps_inv_TFLOPs": lu_flops / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
     }
+    ptr = load_traffic(f"pair_{wl.name}", ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"])
+    if ptr is not None and len(Q) == 1 and pair_t > 0:
+        # HBM bytes of one pair-density call counted by rocprofv3 (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+        stages["pair_fft_GBs_counters"] = ptr["pair_bytes_per_step"] / (pair_t * 1e-3) / 1e9
+        stages["pair_fft_counters_source"] = ptr["profile"]
     if precision == bgw.FP64:
         stages["chi_sum_frac_fp64_peak"] = chi_flops / (per_step["herk"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
     kernel_share = {k: per_step[k] / ms_step for k in per_step}
@@ -362,17 +418,15 @@ def main():
         rez = int(np.abs(x["q"]["ge"][:, 2]).max())
         t_bytes += K * 16.0 * b[0] * (2 * rey + 1) * (2 * rez + 1)
     box_bytes = sum(16.0 * b[0] * b[1] * b[2] for b in boxes)
-    split_issued = 0.0
-    for g in ngs:
-        gpad = (g + 63) // 64 * 64
-        split_issued += (gpad // 64) * (gpad // 64 + 1) // 2 * 64.0 * 64.0 * ((K + 127) // 128) * 256 * 2 * 20 * nw
+    split_bf16 = SPLIT_PRODUCTS * chi_flops  # BF16 MFMA flops of the split form: ten products of 4 Ng^2 K
     work = {
         "pair": ("k_pair_yz (product + z/y FFT)", "hbm", K * box_bytes + t_bytes, "GB/s", HBM_PEAK_GBS),
         "pair_x": ("k_pair_x (x transform + sphere gather)", "hbm", t_bytes + K * 16.0 * sum(ngs), "GB/s",
                    HBM_PEAK_GBS),
         "band": ("k_band_to_real3", "hbm", (nk * (nv + nc)) * box_bytes, "GB/s", HBM_PEAK_GBS),
         "herk": ("k_herk_f64", "mfma", chi_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
-        "split_herk": ("k_herk_split (BF16 MFMA issued)", "mfma", split_issued, "TFLOP/s", BF16_PEAK_TFLOPS),
+        "split_herk": ("k_chi_split (BF16 MFMA, 10 x 4 Ng^2 K per frequency)", "mfma", split_bf16, "TFLOP/s",
+                       BF16_PEAK_TFLOPS),
         "invert": ("Gauss-Jordan inversion (k_gje_*)", "mfma", lu_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
     }
     dominant = max(work, key=lambda k: per_step.get(k, 0))
@@ -424,14 +478,28 @@ def main():
                                                         fft_bytes_nominal)
     if not args.no_split:
         print("[bench] split vs fp64", file=sys.stderr, flush=True)
-        out["split"] = split_vs_fp64(torch, h, bgw, ents, omega, [torch.empty_like(c) for c in chis],
-                                     args.split_reps)
-    if (len(Q) > 1 or nw > 1) and chi_ms < 1000.0:
-        out["batch_graph"] = graph_vs_eager(torch, h, bgw, ents, omega, chis, precision, reps=2)
+        sub = omega
+        if 0 < args.split_omegas < nw:
+            sub = omega[np.unique(np.round(np.linspace(0, nw - 1, args.split_omegas)).astype(int))]
+        out["split"] = split_vs_fp64(torch, h, bgw, ents, sub,
+                                     [torch.empty((len(sub),) + tuple(c.shape[1:]), dtype=c.dtype, device=c.device)
+                                      for c in chis], args.split_reps)
+        out["split"]["omegas"] = [float(x) for x in sub]
+    if (len(Q) > 1 or nw > 1) and not args.no_graph_compare:
+        print("[bench] graph vs eager", file=sys.stderr, flush=True)
+        out["batch_graph"] = graph_vs_eager(torch, h, bgw, ents, omega, chis, precision,
+                                            reps=1 if chi_ms > 1000.0 else 3)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_pairs, chi_flops)
     h.close()
+    # release the device memory before the interpreter's own teardown
+    x = None
+    del Q, bents, bchis, ents, chis, pool, cc, ec
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

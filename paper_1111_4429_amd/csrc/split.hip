@@ -198,8 +198,9 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // LDS stage of one k-step: the weighted side as FP64 complex, [16 pairs][64
 // columns] (16 B each, 1 KB per pair row); the unweighted side's four digit
 // slices, [slice][128 rows][64 B] with the four 16-B segments of row r stored
-// in the order seg ^ (r & 3) (conflict-free 16-B fragment reads); the
-// step's 16 weights.  Besides the three stages, two exponent buffers hold a
+// in the order seg ^ ((r >> 1) & 3), so that the eight rows one 16-B read
+// phase touches fall in distinct bank groups; the step's 16 weights.
+// Besides the two stages, two exponent buffers hold a
 // chunk's 128 column exponents (int32, bytes 0..511) and 64 row exponents of
 // the weighted side (int8, bytes 512..575): chunk c in buffer c % 2, staged
 // with the chunk's first step and read when the chunk starts and when it ends.
@@ -211,8 +212,6 @@ constexpr int E_LDS = 1024;
 constexpr int NWAVE = XT / 64;
 constexpr int PA = KSP / NWAVE;               // 1-KB pieces of the A part per wave: 2
 constexpr int PB = NSL * B_SLICE_LDS / 1024 / NWAVE;  // of the B part: 4
-constexpr int PIECES = PA + PB;               // direct loads per wave and k-step (wave 1: one more, the weights;
-                                              // wave 0 on chunk-start steps: two more, the exponents)
 
 // vmcnt(n) alone (expcnt and lgkmcnt left at their maxima); vmcnt is split
 // over bits 3:0 and 15:14 of the immediate
@@ -275,7 +274,7 @@ __device__ __forceinline__ void stage_issue(unsigned char *__restrict__ stage, u
 
 
 __device__ __forceinline__ uint4 bfrag(const unsigned char *slice, int row, int lq) {
-    return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ (row & 3)));
+    return *reinterpret_cast<const uint4 *>(slice + row * 64 + 16 * (lq ^ ((row >> 1) & 3)));
 }
 
 constexpr int NCB = TC / 32;  // column blocks of a wave (each wave spans 64 of the 128 columns)
@@ -389,18 +388,17 @@ __device__ __forceinline__ void split_flush(SplitAcc &acc, const int *E, int wav
 // (I, J) holds some G <= H iff 64 I <= 128 J + 127, i.e. I <= 2 J + 1.
 }  // namespace
 
-// One k-step x: stage step x + 2 into `nx2`, slice this lane's row of the
+// One k-step x: stage step x + 1 into `nxt`, slice this lane's row of the
 // weighted side from `cur`, 80 MFMAs over the four column blocks, then wait
-// for step x + 1 (its loads were issued a step earlier; those of x + 2 stay
-// in flight).  The three stages are distinct restrict-qualified buffers, so
-// the compiler knows that the loads in flight into one do not alias the reads
-// of another and inserts no wait for them.
-__device__ __forceinline__ void split_step(const unsigned char *__restrict__ cur, unsigned char *__restrict__ nx2,
-                                           unsigned char *__restrict__ ebuf2, const StageSrc &S, long long x, long long s1,
-                                           long long tbase, long long K, double up, int wave, int lane, int li,
-                                           int lq, SplitAcc &acc) {
+// for step x + 1's loads and meet the block at the barrier.  The two stages
+// are distinct restrict-qualified buffers, so the compiler knows that the
+// loads in flight into one do not alias the reads of the other.
+__device__ __forceinline__ void split_step(const unsigned char *__restrict__ cur, unsigned char *__restrict__ nxt,
+                                           unsigned char *__restrict__ ebuf1, const StageSrc &S, long long x,
+                                           long long s1, long long tbase, long long K, double up, int wave, int lane,
+                                           int li, int lq, SplitAcc &acc) {
     __builtin_amdgcn_sched_barrier(0);
-    if (x + 2 < s1) stage_issue(nx2, ebuf2, S, tbase + (x + 2) * KSP, x + 2, wave, lane);
+    if (x + 1 < s1) stage_issue(nxt, ebuf1, S, tbase + (x + 1) * KSP, x + 1, wave, lane);
     __builtin_amdgcn_sched_barrier(0);
     // the weighted side of this lane's row, sliced into digits (pairs >= K weigh 0)
     uint4 af[NSL], as[NSL];
@@ -420,10 +418,7 @@ __device__ __forceinline__ void split_step(const unsigned char *__restrict__ cur
         for (int sl = 0; sl < NSL; ++sl) bf[sl] = bfrag(Bs + sl * B_SLICE_LDS, 64 * (wave & 1) + 16 * cb + li, lq);
         split_mfma(af, as, bf, acc.g[cb]);
     }
-    if (x + 2 >= s1) BGW_WAIT_VM(0);
-    else if (wave == 1) BGW_WAIT_VM(PIECES + 1);
-    else if (wave == 0 && (x + 2) % NKS == 0) BGW_WAIT_VM(PIECES + 2);
-    else BGW_WAIT_VM(PIECES);
+    BGW_WAIT_VM(0);
     stage_barrier();
 }
 
@@ -442,15 +437,14 @@ __device__ __forceinline__ void split_step(const unsigned char *__restrict__ cur
 // reads run under the MFMAs of the other wave on its SIMD.
 // Every k-step (16 pairs) the block stages 16 pair rows of M (the tile's 64
 // columns), the four digit slices of the unweighted side (128 columns) and
-// the 16 weights into LDS with direct global->LDS loads, two steps ahead
-// through three stages; each wave slices its 16 rows of w_t M_t(G) into BF16
+// the 16 weights into LDS with direct global->LDS loads, one step ahead
+// through two stages; each wave slices its 16 rows of w_t M_t(G) into BF16
 // digits in registers and issues 80 MFMAs.
 // out (+)= raw sums (no prefactor) of every element of the tile inside ng x ng.
 __global__ __launch_bounds__(XT, 1) void k_chi_split(const SplitQ *__restrict__ qs, int nq, long long i0,
                                                      long long i1) {
     __shared__ __attribute__((aligned(1024))) unsigned char stage0[STG];
     __shared__ __attribute__((aligned(1024))) unsigned char stage1[STG];
-    __shared__ __attribute__((aligned(1024))) unsigned char stage2[STG];
     __shared__ __attribute__((aligned(1024))) unsigned char ebufs[2][E_LDS];
 
     const int tid = threadIdx.x, lane = tid & 63;
@@ -487,7 +481,7 @@ __global__ __launch_bounds__(XT, 1) void k_chi_split(const SplitQ *__restrict__ 
         S.kmax = Q.K - 1;
         {
             const int row = 64 * (wave & 1) + (lane >> 2);
-            const int seg = (lane & 3) ^ (row & 3);
+            const int seg = (lane & 3) ^ ((row >> 1) & 3);
             S.b_base = reinterpret_cast<const char *>(Q.SB + (wave >> 1) * slice_stride) +
                        ((size_t)(H0 + row) * KS * 2 + seg * 16);
         }
@@ -511,11 +505,8 @@ __global__ __launch_bounds__(XT, 1) void k_chi_split(const SplitQ *__restrict__ 
         const long long K = Q.K;
         const bool in = G0 + 16 * (wave >> 1) + li < ng;  // this lane's slicing row is inside the matrix
 
-        // steps s0 and s0 + 1 (s1 - s0 >= NKS > 2; s0 + 1 is not a chunk start)
         stage_issue(stage0, ebufs[c0 & 1], S, tbase + s0 * KSP, s0, wave, lane);
-        stage_issue(stage1, ebufs[c0 & 1], S, tbase + (s0 + 1) * KSP, s0 + 1, wave, lane);
-        if (wave == 1) BGW_WAIT_VM(PIECES + 1);
-        else BGW_WAIT_VM(PIECES);
+        BGW_WAIT_VM(0);
         stage_barrier();
 
         for (int ch = c0; ch < c1; ++ch) {
@@ -530,12 +521,11 @@ __global__ __launch_bounds__(XT, 1) void k_chi_split(const SplitQ *__restrict__ 
                 for (int p = 0; p < NGR; ++p)
 #pragma unroll
                     for (int ri = 0; ri < 2; ++ri) acc.g[cb][p][ri] = (float4_t){0.f, 0.f, 0.f, 0.f};
-            const long long xb = (long long)ch * NKS;  // a multiple of 3: step xb uses stage0
+            const long long xb = (long long)ch * NKS;  // even: step xb uses stage0
 #pragma unroll 1
-            for (int ks = 0; ks < NKS; ks += 3) {
-                split_step(stage0, stage2, En, S, xb + ks, s1, tbase, K, up, wave, lane, li, lq, acc);
+            for (int ks = 0; ks < NKS; ks += 2) {
+                split_step(stage0, stage1, En, S, xb + ks, s1, tbase, K, up, wave, lane, li, lq, acc);
                 split_step(stage1, stage0, En, S, xb + ks + 1, s1, tbase, K, up, wave, lane, li, lq, acc);
-                split_step(stage2, stage1, En, S, xb + ks + 2, s1, tbase, K, up, wave, lane, li, lq, acc);
             }
             split_flush(acc, E, wave, li, lq);
         }
