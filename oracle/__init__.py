@@ -18,6 +18,8 @@ it follows:
 * ``weights_real``  the complex weights of that equation at real E with
   broadening delta (retarded or advanced), for the full-frequency chi.
 * ``ff_grid``       the real-frequency grid of the full-frequency run.
+* ``bse_kx``        the Bethe-Salpeter exchange kernel (optical-properties
+  section, exchange-term equation), G = 0 left out.
 * ``chi``           the chi sum, compensated, any block of (G, G').
 * ``vcoul``         bulk bare Coulomb 4 pi/|q+G|^2.
 * ``eps``           epsilon = 1 - v chi (asymmetric Coulomb form).
@@ -69,8 +71,9 @@ def lib():
         L.orc_weights_real.argtypes = [I, I, I, P, P, I, P, D, I, P]
         L.orc_chi_cw.argtypes = [Lg, I, P, I, P, D, I, P, I, P, P]
         L.orc_ff_grid.argtypes = [D, D, D, D, I, P]
+        L.orc_bse_kx.argtypes = [Lg, I, P, P, I, D, I, P, P]
         for f in (L.orc_pair_density, L.orc_weights, L.orc_chi, L.orc_vcoul, L.orc_eps, L.orc_inverse,
-                  L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid):
+                  L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid, L.orc_bse_kx):
             f.restype = I
         _lib = L
     return _lib
@@ -181,6 +184,21 @@ def chi(M: np.ndarray, w: np.ndarray, pf: float, rows: Optional[Sequence[int]] =
                        ncl, None if c is None else _p(c), _p(out))
     if rc != 0:
         raise RuntimeError(f"orc_chi failed: {rc}")
+    return out
+
+
+def bse_kx(M: np.ndarray, v: np.ndarray, head: int, pf: float, rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Kx[t][t'] = pf sum_{G != head} conj(M_t(G)) v(G) M_t'(G): rows `rows` (all if None) x all K columns."""
+    M = np.ascontiguousarray(M, dtype=np.complex128)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    K, ng = M.shape
+    assert v.shape == (ng,)
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nr = K if r is None else r.size
+    out = np.zeros((nr, K), dtype=np.complex128)
+    rc = lib().orc_bse_kx(K, ng, _p(M), _p(v), int(head), float(pf), nr, None if r is None else _p(r), _p(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_bse_kx failed: {rc}")
     return out
 
 

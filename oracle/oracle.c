@@ -318,6 +318,47 @@ int orc_chi(long K, int ng, const double *M, int nw, const double *w, double pf,
  * bvec: reciprocal lattice vectors as rows (bohr^-1), q in crystal units,
  * ge: Miller triples.  Returns -3 if some |q+G| is zero.
  */
+/*
+ * Exchange kernel of the Bethe-Salpeter equation (optical-properties
+ * section, exchange-term equation): for pairs t = (k, v, c) and t',
+ *     Kx[t][t'] = pf * sum over G != G0 of conj(M_t(G)) v(q+G) M_t'(G),
+ * the G = 0 term (index `head`, or none when head < 0) left out.  Rows
+ * `rows` (all if NULL) of the K x K result; compensated summation over G.
+ */
+int orc_bse_kx(long K, int ng, const double *M, const double *v, int head, double pf,
+               int nrow, const long *rows, double *kx)
+{
+    if (K <= 0 || ng <= 0) return -1;
+    if (!rows) nrow = (int)K;
+#pragma omp parallel
+    {
+        double *acc = (double *)malloc(sizeof(double) * 4 * K);
+#pragma omp for schedule(dynamic, 1)
+        for (int r = 0; r < nrow; ++r) {
+            long t = rows ? rows[r] : r;
+            const double *mt = M + 2 * t * ng;
+            memset(acc, 0, sizeof(double) * 4 * K);
+            for (int g = 0; g < ng; ++g) {
+                if (g == head) continue;
+                double ar = mt[2 * g] * v[g], ai = -mt[2 * g + 1] * v[g]; /* v(G) conj(M_t(G)) */
+                for (long t2 = 0; t2 < K; ++t2) {
+                    double br = M[2 * (t2 * ng + g)], bi = M[2 * (t2 * ng + g) + 1];
+                    double *s = acc + 4 * t2;
+                    neu_add(&s[0], &s[1], ar * br - ai * bi);
+                    neu_add(&s[2], &s[3], ar * bi + ai * br);
+                }
+            }
+            double *out = kx + 2 * (long)r * K;
+            for (long t2 = 0; t2 < K; ++t2) {
+                out[2 * t2] = pf * (acc[4 * t2] + acc[4 * t2 + 1]);
+                out[2 * t2 + 1] = pf * (acc[4 * t2 + 2] + acc[4 * t2 + 3]);
+            }
+        }
+        free(acc);
+    }
+    return 0;
+}
+
 int orc_vcoul(const double *bvec, const double *q, int ng, const int *ge, double *v)
 {
     for (int g = 0; g < ng; ++g) {

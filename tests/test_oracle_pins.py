@@ -493,3 +493,68 @@ def test_eps_inverse_real_axis(c1_ff, c1):
     for i in range(e.shape[0]):
         assert rel(einv[i], np.linalg.inv(e[i])) < 1e-11
         assert np.linalg.norm(e[i] @ einv[i] - np.eye(n)) / np.sqrt(n) < 1e-12
+
+
+# ---------------------------------------------------------------- BSE exchange kernel
+
+
+@pytest.fixture(scope="module")
+def c1_kx(c1):
+    q = c1["qs"][0]
+    M = oracle.pair_density(c1["gw"], q["ge"], q["cv"], c1["cc"])
+    v = oracle.vcoul(c1["bmat"], q["q"], q["ge"])
+    pf = 1.0 / (c1["nk"] * c1["vol"])
+    return M, v, pf, oracle.bse_kx(M, v, 0, pf)
+
+
+def test_bse_kx_gram_duality_and_psd(c1_kx):
+    """Kx = pf A^H A with A[G][t] = sqrt(v(G)) M_t(G) over G != 0, so it is
+    Hermitian positive semidefinite and its nonzero eigenvalues are those of
+    the Ng-1 x Ng-1 matrix pf A A^H (formed here by numpy in the other order)."""
+    M, v, pf, kx = c1_kx
+    K = M.shape[0]
+    assert np.abs(kx - kx.conj().T).max() <= 1e-15 * np.abs(kx).max()
+    lam = np.linalg.eigvalsh(kx)
+    assert lam.min() >= -1e-13 * lam.max()
+    A = (np.sqrt(v)[:, None] * M.T)[1:]
+    mu = np.linalg.eigvalsh(pf * A @ A.conj().T)
+    top = np.sort(mu)[-K:]
+    assert np.allclose(np.sort(lam), top, rtol=0, atol=1e-12 * lam.max())
+
+
+def test_bse_kx_phase_closed_form():
+    """M_t(G) = exp(i phi_t) r_t(G) with real r: Kx[t][t'] = exp(i (phi_t' - phi_t))
+    pf sum_G v r_t r_t' exactly (pins which pair is conjugated)."""
+    rng = np.random.default_rng(11)
+    K, ng = 5, 9
+    r = rng.standard_normal((K, ng))
+    phi = rng.uniform(0, 2 * np.pi, K)
+    M = np.exp(1j * phi)[:, None] * r
+    v = rng.uniform(0.5, 2.0, ng)
+    kx = oracle.bse_kx(M, v, 3, 0.7)
+    keep = np.arange(ng) != 3
+    for t in range(K):
+        for t2 in range(K):
+            mag = 0.7 * float(np.sum(v[keep] * r[t, keep] * r[t2, keep]))
+            want = mag * np.exp(1j * (phi[t2] - phi[t]))
+            assert abs(kx[t, t2] - want) <= 1e-14 * max(1.0, abs(mag))
+
+
+def test_bse_kx_head_exclusion_and_rank_one():
+    """With v nonzero only at the head index the kernel vanishes; with no
+    head left out (head = -1) it is the rank-one pf v conj(M_t(h)) M_t'(h)."""
+    rng = np.random.default_rng(12)
+    K, ng, h = 6, 8, 2
+    M = rng.standard_normal((K, ng)) + 1j * rng.standard_normal((K, ng))
+    v = np.zeros(ng)
+    v[h] = 3.0
+    assert np.all(oracle.bse_kx(M, v, h, 1.0) == 0.0)
+    kx = oracle.bse_kx(M, v, -1, 0.5)
+    assert np.allclose(kx, 0.5 * 3.0 * np.outer(M[:, h].conj(), M[:, h]), rtol=0, atol=1e-14)
+
+
+def test_bse_kx_rows_block(c1_kx):
+    """A row subset is exactly those rows of the full kernel."""
+    M, v, pf, kx = c1_kx
+    rows = [7, 0, 63, 31]
+    assert np.array_equal(oracle.bse_kx(M, v, 0, pf, rows=rows), kx[rows])
