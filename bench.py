@@ -246,6 +246,123 @@ def _cpu_model():
     return None
 
 
+def bench_kx(args, wl):
+    """Bethe-Salpeter exchange kernel: one step = pair densities of the K pairs
+    -> Kx = pf sum_{G != 0} conj(M_t(G)) v(G) M_t'(G) (4 K^2 Ng flops, FP64 or
+    split precision), timed like the chi0 steps; the split form against FP64."""
+    import torch
+
+    from paper_1111_4429_amd import bgw, synth
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    s = synth.make_system(wl)
+    q = s["qs"][0]
+    n, K, ng = s["n"], wl.npairs, q["ng"]
+    pf = 1.0 / (s["nk"] * s["vol"])
+    precision = bgw.SPLIT_BF16 if args.precision == "split" else bgw.FP64
+    h = bgw.Handle(0)
+    cc = torch.from_numpy(s["cc"]).to(dev)
+    cv = torch.from_numpy(q["cv"]).to(dev)
+    v = torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev)
+    M = torch.empty((K, ng), dtype=torch.complex128, device=dev)
+    kx = torch.empty((K, K), dtype=torch.complex128, device=dev)
+
+    def step(prec):
+        h.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
+        h.bse_kx(M, v, head=0, prefactor=pf, precision=prec, kx=kx)
+
+    for _ in range(args.warmup):
+        step(precision)
+    torch.cuda.synchronize()
+    h.reset_timing()
+    h.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(precision)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    h.set_timing(False)
+    tm = h.timing()
+    ms_step = elapsed * 1e3 / args.steps
+    flops = 4.0 * K * K * ng
+    per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
+    launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
+    key = "herk" if precision == bgw.FP64 else "split_herk"
+    if precision == bgw.FP64:
+        name, work, peak = "k_herk_f64 (Kx, 4 K^2 Ng)", flops, FP64_PEAK_TFLOPS
+    else:
+        name, work, peak = "k_chi_split (Kx, BF16 MFMA, 10 x 4 K^2 Ng)", SPLIT_PRODUCTS * flops, BF16_PEAK_TFLOPS
+    nl = launches.get(key, 1)
+    avg = per_step[key] / nl
+    ach = work / nl / (avg * 1e-3) / 1e12
+    kx_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize", "split_slice", "split_herk"))
+    out = {
+        "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if precision == bgw.FP64 else "bf16-split/f32-acc/f64-recombined",
+        "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies)",
+        "config": {"workload": wl.name, "quantity": "Bethe-Salpeter exchange kernel Kx", "grid": f"{n}^3",
+                   "ng": ng, "nv": wl.nv, "nc": wl.nc, "nk": wl.nk, "npairs": K,
+                   "precision": "fp64" if precision == bgw.FP64 else "split"},
+        "stages": {"pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
+                   "kx_ms": kx_ms, "kx_TFLOPs": flops / (kx_ms * 1e-3) / 1e12},
+        "roofline": {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None, "algorithmic_per_launch": work / nl, "avg_launch_ms": avg,
+                     "launches_per_step": nl},
+        "split": None,
+        "cpu_baseline": None,
+    }
+    if not args.no_split:
+        res = {}
+        k64 = None
+        for nm, prec in (("fp64", bgw.FP64), ("split", bgw.SPLIT_BF16)):
+            step(prec)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.split_reps):
+                h.bse_kx(M, v, head=0, prefactor=pf, precision=prec, kx=kx)
+            e1.record()
+            torch.cuda.synchronize()
+            res[nm] = e0.elapsed_time(e1) / args.split_reps
+            if nm == "fp64":
+                k64 = kx.clone()
+        err = float(torch.linalg.vector_norm(kx - k64) / torch.linalg.vector_norm(k64))
+        out["split"] = {"fp64_kx_ms": res["fp64"], "split_kx_ms": res["split"], "speedup": res["fp64"] / res["split"],
+                        "rel_err_vs_fp64": err, "bar": 1e-9, "meets_bar": err <= 1e-9}
+        del k64
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        import oracle
+
+        Mh = M.cpu().numpy()
+        rows = np.arange(0, K, max(1, K // 32))[:32]
+        t0 = time.perf_counter()
+        oracle.bse_kx(Mh, v.cpu().numpy(), 0, pf, rows=rows)
+        t_kx = (time.perf_counter() - t0) * K / len(rows)
+        rng = np.random.default_rng(123)
+        pairs = np.sort(rng.choice(K, size=64, replace=False))
+        t0 = time.perf_counter()
+        oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
+        t_m = (time.perf_counter() - t0) * K / len(pairs)
+        out["cpu_baseline"] = {"value": flops / (t_kx + t_m) / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle Kx rows {len(rows)} of {K} ({t_kx * len(rows) / K:.2f} s) and M by "
+                                         f"convolution for 64 of {K} pairs, extrapolated linearly in rows and pairs: "
+                                         f"{t_kx + t_m:.1f} s per step", "cpu": _cpu_model()}
+    h.close()
+    del M, kx, cv, cc, v
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -269,6 +386,9 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": 3}))
         return
     wl = synth.WORKLOADS[args.workload]
+    if wl.name.startswith("bse-kx"):
+        bench_kx(args, wl)
+        return
     q_subset = None
     if wl.nq > 1 and args.q_subset != "all":
         if args.q_subset.startswith("spread"):

@@ -215,6 +215,42 @@ int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
 int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cfg);
 
 /* ------------------------------------------------------------------------
+ * Exchange kernel of the Bethe-Salpeter equation
+ *
+ *   Kx[t][t'] = prefactor * sum over G != G0 of conj(M_t(G)) v(q+G) M_t'(G)
+ *
+ * (optical-properties section, exchange-term equation) for the pairs
+ * t = (k, v, c) of the matrix elements M_vc(k, q, G) of bgw_pair_density.
+ * It is the chi sum with the roles of pairs and G exchanged: M is
+ * transposed into the workspace (G becomes the contraction index, the G0
+ * row zeroed) and the chi-sum kernels run with the weights v, FP64 or split
+ * BF16 as in bgw_chi0.  Kx is Hermitian positive semidefinite for v > 0.
+ * The split form scales its digits per run of 96 consecutive G vectors, so a
+ * term orders of magnitude above its neighbours (v(q0+0) ~ 1/q0^2 at small q
+ * with head = -1) costs digits of the whole run: leave G = 0 out through
+ * `head`, or use FP64, when v has such a term.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const double *M;     /* DEVICE complex128 [K][ng], e.g. from bgw_pair_density */
+    long long K;         /* pairs, 1 .. 65536 */
+    int ng;              /* G vectors, >= 1 */
+    int head;            /* index of G = 0 in the G list (its term is left out), -1: keep all */
+    const double *v;     /* DEVICE f64 [ng]: v(q+G), e.g. from bgw_vcoul_bulk */
+    double prefactor;    /* scale of the sum */
+    int precision;       /* BGW_FP64 or BGW_SPLIT_BF16 */
+    int pad;             /* unused, 0 */
+    double *kx;          /* DEVICE complex128 [K][K], output, written in full */
+} bgw_kx_desc;
+
+/* Work is ordered on `stream`; the handle's workspace holds the transposed M
+ * (16 K ng bytes) and what the chi sum needs.  Errors as bgw_chi0. */
+int bgw_bse_kx(bgw_handle_t h, const bgw_kx_desc *d, void *stream);
+
+/* Device workspace bgw_bse_kx(h, d, ...) needs, in bytes (HOST *bytes).
+ * Allocates nothing. */
+int bgw_bse_kx_workspace(bgw_handle_t h, const bgw_kx_desc *d, size_t *bytes);
+
+/* ------------------------------------------------------------------------
  * Dielectric matrix and its inverse
  *
  * epsilon_GG'(omega) = delta_GG' - v(q+G) chi_GG'(omega)   (epsilon section,

@@ -38,7 +38,7 @@ EXPORTS = [
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
-    "bgw_ff_grid", "bgw_eps_inv_noalloc",
+    "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -95,6 +95,20 @@ class ChiDesc(ctypes.Structure):
     ]
 
 
+class KxDesc(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_void_p),
+        ("K", ctypes.c_longlong),
+        ("ng", ctypes.c_int),
+        ("head", ctypes.c_int),
+        ("v", ctypes.c_void_p),
+        ("prefactor", ctypes.c_double),
+        ("precision", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("kx", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -127,6 +141,8 @@ def lib():
         L.bgw_chi0.argtypes = [P, ctypes.POINTER(ChiDesc), P]
         L.bgw_eps_inv.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_eps_inv_noalloc.argtypes = [P, I, I, P, P, P, P, P]
+        L.bgw_bse_kx.argtypes = [P, ctypes.POINTER(KxDesc), P]
+        L.bgw_bse_kx_workspace.argtypes = [P, ctypes.POINTER(KxDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
         L.bgw_set_timing.argtypes = [P, I]
         L.bgw_get_timing.argtypes = [P, I, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
@@ -142,7 +158,8 @@ def lib():
         for f in ("bgw_create", "bgw_destroy", "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0",
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
-                  "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc"):
+                  "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx",
+                  "bgw_bse_kx_workspace"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -387,6 +404,37 @@ class Handle:
         _check(lib().bgw_eps_inv(self._h, ng, nw, _dptr(vcoul.contiguous()), _dptr(chi), _dptr(epsinv),
                                  _dptr(info), _stream()))
         return epsinv, info
+
+    # ---------------------------------------------------------------- BSE exchange kernel
+    def _kx_desc(self, M, v, head, prefactor, precision, kx):
+        import torch
+        K, ng = M.shape
+        assert M.dtype == torch.complex128 and M.is_contiguous()
+        assert v.dtype == torch.float64 and v.numel() == ng and v.is_contiguous()
+        assert kx.shape == (K, K) and kx.dtype == torch.complex128 and kx.is_contiguous()
+        return KxDesc(M=_dptr(M), K=K, ng=ng, head=int(head), v=_dptr(v), prefactor=float(prefactor),
+                      precision=int(precision), pad=0, kx=_dptr(kx))
+
+    def bse_kx(self, M, v, head=0, prefactor=1.0, precision=FP64, kx=None):
+        """Kx[t][t'] = prefactor sum_{G != head} conj(M_t(G)) v(G) M_t'(G) (device complex128 [K][K])."""
+        import torch
+        if kx is None:
+            kx = torch.empty((M.shape[0], M.shape[0]), dtype=torch.complex128, device=M.device)
+        d = self._kx_desc(M, v, head, prefactor, precision, kx)
+        _check(lib().bgw_bse_kx(self._h, ctypes.byref(d), _stream()))
+        return kx
+
+    def bse_kx_workspace(self, M, v, head=0, prefactor=1.0, precision=FP64, kx=None) -> int:
+        import torch
+        if kx is None:
+            kx = torch.empty((1, 1), dtype=torch.complex128, device=M.device).expand(M.shape[0], M.shape[0])
+            d = KxDesc(M=_dptr(M), K=M.shape[0], ng=M.shape[1], head=int(head), v=_dptr(v),
+                       prefactor=float(prefactor), precision=int(precision), pad=0, kx=_dptr(kx))
+        else:
+            d = self._kx_desc(M, v, head, prefactor, precision, kx)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_bse_kx_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
+        return int(out.value)
 
     def eps_inv_noalloc(self, vcoul, chi, epsinv, info):
         """bgw_eps_inv_noalloc: epsilon^-1 into caller-owned epsinv and info, with the

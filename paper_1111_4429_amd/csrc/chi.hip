@@ -35,7 +35,9 @@ __global__ void k_weights(const WProb *__restrict__ probs) {
         const long long k = kv / P.nv;
         const double d = (P.ev[kv] - P.ec[k * P.nc + c]) / kHartreeEv;
         double w;
-        if (P.kind == kWeightImag) {
+        if (P.kind == kWeightGiven) {
+            w = P.ev[t];
+        } else if (P.kind == kWeightImag) {
             w = d / (d * d + P.omega_ha * P.omega_ha);
         } else {
             const double a = d - P.omega_ha, b = d + P.omega_ha, dl = P.delta_ha;
@@ -235,7 +237,40 @@ __global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
     }
 }
 
+// MT[G][t] = M[t][G] for the K x ng matrix M (pairs x G), row `head` of MT
+// zeroed (head < 0: none): the contraction over G of the Bethe-Salpeter
+// exchange kernel becomes the contraction over the leading index that the
+// chi-sum kernels perform.  32 x 32 tiles through LDS, both sides coalesced;
+// grid (ceil(ng / 32), ceil(K / 32)), block (32, 8).
+__global__ __launch_bounds__(256) void k_transpose_pairs(const double2 *__restrict__ M, long long K, int ng,
+                                                         int head, double2 *__restrict__ MT) {
+    __shared__ double2 tile[32][33];
+    const int g0 = blockIdx.x * 32;
+    const long long t0 = (long long)blockIdx.y * 32;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const long long t = t0 + threadIdx.y + 8 * r;
+        const int g = g0 + threadIdx.x;
+        tile[threadIdx.y + 8 * r][threadIdx.x] = (t < K && g < ng) ? M[t * ng + g] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int g = g0 + threadIdx.y + 8 * r;
+        const long long t = t0 + threadIdx.x;
+        if (g < ng && t < K)
+            MT[(size_t)g * K + t] = g == head ? make_double2(0.0, 0.0) : tile[threadIdx.x][threadIdx.y + 8 * r];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+
+int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t st) {
+    hipLaunchKernelGGL(k_transpose_pairs, dim3((ng + 31) / 32, (unsigned)((K + 31) / 32)), dim3(32, 8), 0, st, M, K,
+                       ng, head, MT);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
 
 int launch_weights_batch(const WProb *probs, int nprob, long long maxK, hipStream_t st) {
     const int blocks = (int)std::max<long long>(1, std::min<long long>((maxK + 255) / 256, 1024));

@@ -244,7 +244,12 @@ long long choose_splits(long long base_items, long long slots, int ipc, long lon
     return ns;
 }
 
-int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile, int force_ipc, int force_nsplit) {
+// prefix: workspace bytes kept free at the start (the Bethe-Salpeter exchange
+// kernel keeps its transposed pair matrix there); given: the q entries' ev
+// arrays are the weights themselves (one vector per q, imaginary axis, one
+// frequency).
+int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile, int force_ipc, int force_nsplit,
+              size_t prefix = 0, bool given = false) {
     ChiState *s = state(h);
     load_cache(s);
     P.precision = d->precision;
@@ -254,7 +259,7 @@ int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile,
     P.nout = d->nq * d->nw;
     const bool real_axis = d->axis != BGW_AXIS_IMAG;
     const int cus = device_cus();
-    size_t off = 0;
+    size_t off = al256(prefix);
     // weight vectors
     for (int iq = 0; iq < d->nq; ++iq) {
         const bgw_chi_q &q = d->q[iq];
@@ -272,7 +277,8 @@ int make_plan(bgw_handle_t h, const bgw_chi_desc *d, ChiPlan &P, int force_tile,
                 wp.nk = q.nk;
                 wp.nv = q.nv;
                 wp.nc = q.nc;
-                wp.kind = !real_axis ? kWeightImag
+                wp.kind = given ? kWeightGiven
+                          : !real_axis ? kWeightImag
                                      : (part == 0 ? kWeightRealRe
                                                   : (d->axis == BGW_AXIS_RETARDED ? kWeightRetIm : kWeightAdvIm));
                 P.wts.push_back(wp);
@@ -767,6 +773,83 @@ extern "C" int bgw_chi0_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t 
     BGW_TRY(make_plan(h, d, P, 0, 0, 0));
     *bytes = P.ws_bytes;
     return BGW_OK;
+}
+
+namespace bgw {
+namespace {
+constexpr long long kMaxKxPairs = 65536;
+
+int check_kx_desc(const bgw_kx_desc *d) {
+    if (!d || !d->M || !d->v || !d->kx) return fail(BGW_ERR_ARG, "bad exchange-kernel descriptor");
+    if (d->K < 1 || d->K > kMaxKxPairs) return fail(BGW_ERR_UNSUPPORTED, "exchange kernel: K outside 1 .. 65536");
+    if (d->ng < 1) return fail(BGW_ERR_ARG, "exchange kernel: ng must be >= 1");
+    if (d->head < -1 || d->head >= d->ng) return fail(BGW_ERR_ARG, "exchange kernel: head index out of range");
+    if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16) return fail(BGW_ERR_ARG, "unknown precision");
+    return BGW_OK;
+}
+
+// The chi-sum problem of the exchange kernel: "pairs" are the ng G vectors
+// of the transposed MT [ng][K], the output index runs over the K pairs, the
+// weights are v (given), and no output row needs the FP64 head treatment.
+struct KxProblem {
+    bgw_chi_q q;
+    bgw_chi_desc cd;
+    double omega = 0.0;
+    void set(const bgw_kx_desc *d, const void *MT) {
+        std::memset(&q, 0, sizeof(q));
+        q.ng = (int)d->K;
+        q.nk = 1;
+        q.nv = 1;
+        q.nc = d->ng;
+        q.M = (const double *)MT;
+        q.ev = d->v;
+        q.ec = d->v;
+        q.head = -1;
+        q.prefactor = d->prefactor;
+        q.chi = d->kx;
+        std::memset(&cd, 0, sizeof(cd));
+        cd.nq = 1;
+        cd.q = &q;
+        cd.nw = 1;
+        cd.omega = &omega;
+        cd.precision = d->precision;
+        cd.axis = BGW_AXIS_IMAG;
+    }
+};
+}  // namespace
+}  // namespace bgw
+
+extern "C" int bgw_bse_kx_workspace(bgw_handle_t h, const bgw_kx_desc *d, size_t *bytes) {
+    clear_error();
+    BGW_TRY(check_kx_desc(d));
+    if (!h || !bytes) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    KxProblem kp;
+    kp.set(d, d->M);  // any non-null placeholder: sizes only
+    ChiPlan P;
+    BGW_TRY(make_plan(h, &kp.cd, P, 0, 0, 0, sizeof(double2) * (size_t)d->K * d->ng, true));
+    *bytes = P.ws_bytes;
+    return BGW_OK;
+}
+
+extern "C" int bgw_bse_kx(bgw_handle_t h, const bgw_kx_desc *d, void *stream) {
+    clear_error();
+    BGW_TRY(check_kx_desc(d));
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t mt_bytes = sizeof(double2) * (size_t)d->K * d->ng;
+    KxProblem kp;
+    ChiPlan P0;
+    kp.set(d, d->M);
+    BGW_TRY(make_plan(h, &kp.cd, P0, 0, 0, 0, mt_bytes, true));
+    BGW_TRY(ensure_ws(h, P0.ws_bytes, st));
+    double2 *MT = (double2 *)h->ws.p;  // the plan keeps the first mt_bytes free
+    BGW_TRY(launch_transpose_pairs((const double2 *)d->M, d->K, d->ng, d->head, MT, st));
+    kp.set(d, MT);
+    ChiPlan P;
+    BGW_TRY(make_plan(h, &kp.cd, P, 0, 0, 0, mt_bytes, true));
+    return run_eager(h, &kp.cd, P, st);
 }
 
 extern "C" int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {

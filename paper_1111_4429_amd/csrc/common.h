@@ -168,11 +168,13 @@ struct FinProb {
 //   imaginary axis   w = Delta / (Delta^2 + omega^2)   (omega = 0: static 1 / Delta)
 //   real axis        w = (1/2) [1/(Delta - E -+ i delta) + 1/(Delta + E +- i delta)]
 //                    (upper signs retarded, lower advanced), as its real part and
-//                    its imaginary part, each a real weight vector.
-enum WeightKind { kWeightImag = 0, kWeightRealRe = 1, kWeightRetIm = 2, kWeightAdvIm = 3 };
+//                    its imaginary part, each a real weight vector;
+//   given            w = a weight array passed in (the Coulomb factor of the
+//                    Bethe-Salpeter exchange kernel).
+enum WeightKind { kWeightImag = 0, kWeightRealRe = 1, kWeightRetIm = 2, kWeightAdvIm = 3, kWeightGiven = 4 };
 
 struct WProb {
-    const double *ev;  // [nk][nv] eV
+    const double *ev;  // [nk][nv] eV (kWeightGiven: the weights themselves, [K])
     const double *ec;  // [nk][nc] eV
     double *w;         // [K]
     double omega_ha;   // |omega| (imaginary axis) or E (real axis), hartree

@@ -101,6 +101,7 @@ int herk_blocks_per_cu();
 int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long i1, int tile, int grid,
                       hipStream_t);
 int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_t);
+int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t);
 
 // ---- split-precision launchers (split.hip)
 int split_gpad(int ng);                         // columns of the digit slices (multiple of 128)

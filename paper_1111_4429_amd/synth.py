@@ -76,6 +76,8 @@ WORKLOADS: Dict[str, Workload] = {
                              nw=32, freq="gauss-legendre-0-100eV", precision="split"),
     "uneven-q-48": Workload("uneven-q-48", n=48, ng=6000, ngw=6000, nv=32, nc=600, nk=27,
                             nq=64, ng_range=(500, 6000), precision="split"),
+    # Bethe-Salpeter exchange kernel over K = 4 x 64 x 64 = 16384 pairs of the silicon-like cell
+    "bse-kx-48": Workload("bse-kx-48", n=48, ng=1500, ngw=1500, nv=4, nc=64, nk=64),
 }
 
 
