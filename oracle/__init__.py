@@ -20,6 +20,9 @@ it follows:
 * ``ff_grid``       the real-frequency grid of the full-frequency run.
 * ``bse_kx``        the Bethe-Salpeter exchange kernel (optical-properties
   section, exchange-term equation), G = 0 left out.
+* ``sigma``         static self-energy matrix elements of one q: bare exchange
+  (hf-x equation), screened exchange (cohsex-sx) and the Coulomb hole in its
+  sum form (cohsex-ch-sum).
 * ``chi``           the chi sum, compensated, any block of (G, G').
 * ``vcoul``         bulk bare Coulomb 4 pi/|q+G|^2.
 * ``eps``           epsilon = 1 - v chi (asymmetric Coulomb form).
@@ -72,8 +75,9 @@ def lib():
         L.orc_chi_cw.argtypes = [Lg, I, P, I, P, D, I, P, I, P, P]
         L.orc_ff_grid.argtypes = [D, D, D, D, I, P]
         L.orc_bse_kx.argtypes = [Lg, I, P, P, I, D, I, P, P]
+        L.orc_sigma.argtypes = [I, I, I, I, P, I, P, P, D, P]
         for f in (L.orc_pair_density, L.orc_weights, L.orc_chi, L.orc_vcoul, L.orc_eps, L.orc_inverse,
-                  L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid, L.orc_bse_kx):
+                  L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid, L.orc_bse_kx, L.orc_sigma):
             f.restype = I
         _lib = L
     return _lib
@@ -199,6 +203,28 @@ def bse_kx(M: np.ndarray, v: np.ndarray, head: int, pf: float, rows: Optional[Se
     rc = lib().orc_bse_kx(K, ng, _p(M), _p(v), int(head), float(pf), nr, None if r is None else _p(r), _p(out))
     if rc != 0:
         raise RuntimeError(f"orc_bse_kx failed: {rc}")
+    return out
+
+
+SIGMA_KINDS = {"x": 0, "sx": 1, "ch": 2}
+
+
+def sigma(kind: str, M: np.ndarray, v: np.ndarray, pf: float, einv: Optional[np.ndarray] = None,
+          head: int = -1) -> np.ndarray:
+    """Self-energy matrix [nouter][nouter] of one q from M[ninner][nouter][ng] (inner x outer pairs):
+    kind "x" (bare exchange, G = head left out), "sx" (screened exchange) or "ch" (Coulomb hole, sum form)."""
+    M = np.ascontiguousarray(M, dtype=np.complex128)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    ni, no, ng = M.shape
+    e = None
+    if kind != "x":
+        e = np.ascontiguousarray(einv, dtype=np.complex128)
+        assert e.shape == (ng, ng)
+    out = np.zeros((no, no), dtype=np.complex128)
+    rc = lib().orc_sigma(SIGMA_KINDS[kind], ni, no, ng, _p(M), int(head), _p(v), None if e is None else _p(e),
+                         float(pf), _p(out))
+    if rc != 0:
+        raise ValueError(f"orc_sigma failed: {rc}")
     return out
 
 

@@ -359,6 +359,78 @@ int orc_bse_kx(long K, int ng, const double *M, const double *v, int head, doubl
     return 0;
 }
 
+/*
+ * Static self-energy matrix elements of one q (self-energy section): with
+ * M[i][n][G] = M_{n''n}(G) for inner states i = n'' and outer states n,
+ *   kind 0, bare exchange (hf-x equation):
+ *     S[n][n'] = -pf sum_i sum_{G != head} conj(M[i][n][G]) v(G) M[i][n'][G]
+ *   kind 1, screened exchange (cohsex-sx equation):
+ *     S[n][n'] = -pf sum_i sum_{G,G'} conj(M[i][n][G]) einv[G][G'] v(G') M[i][n'][G']
+ *   kind 2, Coulomb hole, sum form (cohsex-ch-sum equation):
+ *     S[n][n'] = pf/2 sum_i sum_{G,G'} conj(M[i][n][G]) (einv[G][G'] - delta) v(G') M[i][n'][G']
+ * (the inner states summed over are the occupied ones for kinds 0 and 1 and
+ * all of them for kind 2: the caller passes that set).  Compensated sums.
+ */
+int orc_sigma(int kind, int ninner, int nouter, int ng, const double *M, int head, const double *v,
+              const double *einv, double pf, double *S)
+{
+    if (ninner <= 0 || nouter <= 0 || ng <= 0 || kind < 0 || kind > 2) return -1;
+    if (kind > 0 && !einv) return -1;
+    const double scale = kind == 2 ? 0.5 * pf : -pf;
+#pragma omp parallel
+    {
+        double *y = (double *)malloc(sizeof(double) * 2 * ng);
+        double *acc = (double *)malloc(sizeof(double) * 4 * nouter);
+#pragma omp for schedule(dynamic, 1)
+        for (int n = 0; n < nouter; ++n) {
+            memset(acc, 0, sizeof(double) * 4 * nouter);
+            for (int i = 0; i < ninner; ++i) {
+                const double *mn = M + 2 * ((long)i * nouter + n) * ng;
+                /* y[G'] = sum_G conj(M[i][n][G]) Weff[G][G'] (a row vector) */
+                for (int g2 = 0; g2 < ng; ++g2) {
+                    double yr = 0.0, yi = 0.0;
+                    if (kind == 0) {
+                        if (g2 != head) {
+                            yr = mn[2 * g2] * v[g2];
+                            yi = -mn[2 * g2 + 1] * v[g2];
+                        }
+                    } else {
+                        double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+                        for (int g = 0; g < ng; ++g) {
+                            double er = einv[2 * ((long)g * ng + g2)], ei = einv[2 * ((long)g * ng + g2) + 1];
+                            if (kind == 2 && g == g2) er -= 1.0;
+                            double ar = mn[2 * g], ai = -mn[2 * g + 1]; /* conj(M) */
+                            neu_add(&sr, &cr, ar * er - ai * ei);
+                            neu_add(&si, &ci, ar * ei + ai * er);
+                        }
+                        yr = (sr + cr) * v[g2];
+                        yi = (si + ci) * v[g2];
+                    }
+                    y[2 * g2] = yr;
+                    y[2 * g2 + 1] = yi;
+                }
+                for (int n2 = 0; n2 < nouter; ++n2) {
+                    const double *mm = M + 2 * ((long)i * nouter + n2) * ng;
+                    double *s = acc + 4 * n2;
+                    for (int g2 = 0; g2 < ng; ++g2) {
+                        double br = mm[2 * g2], bi = mm[2 * g2 + 1];
+                        neu_add(&s[0], &s[1], y[2 * g2] * br - y[2 * g2 + 1] * bi);
+                        neu_add(&s[2], &s[3], y[2 * g2] * bi + y[2 * g2 + 1] * br);
+                    }
+                }
+            }
+            double *out = S + 2 * (long)n * nouter;
+            for (int n2 = 0; n2 < nouter; ++n2) {
+                out[2 * n2] = scale * (acc[4 * n2] + acc[4 * n2 + 1]);
+                out[2 * n2 + 1] = scale * (acc[4 * n2 + 2] + acc[4 * n2 + 3]);
+            }
+        }
+        free(acc);
+        free(y);
+    }
+    return 0;
+}
+
 int orc_vcoul(const double *bvec, const double *q, int ng, const int *ge, double *v)
 {
     for (int g = 0; g < ng; ++g) {

@@ -558,3 +558,69 @@ def test_bse_kx_rows_block(c1_kx):
     M, v, pf, kx = c1_kx
     rows = [7, 0, 63, 31]
     assert np.array_equal(oracle.bse_kx(M, v, 0, pf, rows=rows), kx[rows])
+
+
+# ---------------------------------------------------------------- static self-energy
+
+
+@pytest.fixture(scope="module")
+def c1_sigma(c1, c1_eps):
+    """Pair elements of the 4 valence states (inner, at k+q) with the first 6
+    conduction states (outer), and the physical eps^-1 of the same q."""
+    q = c1["qs"][0]
+    M = oracle.pair_density(c1["gw"], q["ge"], q["cv"], c1["cc"][:, :6]).reshape(4, 6, -1)
+    v, chi, eps, einv, info = c1_eps
+    pf = 1.0 / (c1["nk"] * c1["vol"])
+    return M, v, einv[0], pf
+
+
+def test_sigma_sx_with_delta_is_bare_exchange(c1_sigma):
+    """The bare exchange is the screened exchange with eps^-1 replaced by the
+    identity (hf-x against cohsex-sx), and the Coulomb hole then vanishes."""
+    M, v, einv, pf = c1_sigma
+    ng = M.shape[2]
+    eye = np.eye(ng, dtype=np.complex128)
+    sx = oracle.sigma("sx", M, v, pf, einv=eye)
+    x = oracle.sigma("x", M, v, pf, head=-1)
+    assert rel(sx, x) < 1e-14
+    assert np.all(oracle.sigma("ch", M, v, pf, einv=eye) == 0.0)
+
+
+def test_sigma_numpy_and_hermitian(c1_sigma):
+    """Screened exchange against numpy products sum_i A_i^H (eps^-1 v) A_i;
+    with a Hermitian W = eps^-1 v it is Hermitian, and the bare exchange is
+    Hermitian negative semidefinite."""
+    M, v, einv, pf = c1_sigma
+    sx = oracle.sigma("sx", M, v, pf, einv=einv)
+    W = einv * v[None, :]
+    ref = -pf * sum(M[i].conj() @ W @ M[i].T for i in range(M.shape[0]))
+    assert rel(sx, ref) < 1e-13
+    assert np.abs(sx - sx.conj().T).max() <= 1e-12 * np.abs(sx).max()
+    x = oracle.sigma("x", M, v, pf, head=0)
+    assert np.abs(x - x.conj().T).max() <= 1e-15 * np.abs(x).max()
+    assert np.linalg.eigvalsh(x).max() <= 1e-14 * np.abs(x).max()
+
+
+def test_sigma_ch_is_half_the_screening_correction(c1_sigma):
+    """With the same inner states, the Coulomb hole (sum form) is minus half of
+    the screened minus the bare exchange: both carry (eps^-1 - 1) v."""
+    M, v, einv, pf = c1_sigma
+    ch = oracle.sigma("ch", M, v, pf, einv=einv)
+    sx = oracle.sigma("sx", M, v, pf, einv=einv)
+    x = oracle.sigma("x", M, v, pf, head=-1)
+    assert rel(ch, -0.5 * (sx - x)) < 1e-12
+
+
+def test_sigma_bare_exchange_closed_form():
+    """One inner state and plane-wave-like elements M[0][n][G] = delta_{G, g(n)}:
+    the bare exchange is diagonal, -pf v(g(n)), except where g(n) is the
+    left-out head."""
+    ng, no = 7, 5
+    gsel = [1, 3, 0, 6, 4]
+    M = np.zeros((1, no, ng), dtype=np.complex128)
+    for n, g in enumerate(gsel):
+        M[0, n, g] = 1.0
+    v = np.linspace(1.0, 2.2, ng)
+    x = oracle.sigma("x", M, v, 0.5, head=0)
+    want = np.diag([0.0 if g == 0 else -0.5 * v[g] for g in gsel]).astype(np.complex128)
+    assert np.array_equal(x, want)
