@@ -251,6 +251,52 @@ int bgw_bse_kx(bgw_handle_t h, const bgw_kx_desc *d, void *stream);
 int bgw_bse_kx_workspace(bgw_handle_t h, const bgw_kx_desc *d, size_t *bytes);
 
 /* ------------------------------------------------------------------------
+ * Static self-energy matrix elements of one q (self-energy section)
+ *
+ * With M[i][n][G] = M_{n''n}(G) for inner states i = n'' and outer states n
+ * (bgw_pair_density with nk = 1, the inner states as its "valence" set at
+ * k - q and the outer states as its "conduction" set at k, on the G list
+ * that carries the sign convention of the equations):
+ *   BGW_SIGMA_X   bare exchange (hf-x equation)
+ *       S[n][n'] = -pf sum_i sum_{G != head} conj(M[i][n][G]) v(G) M[i][n'][G]
+ *   BGW_SIGMA_SX  screened exchange (cohsex-sx equation)
+ *       S[n][n'] = -pf sum_i sum_{G,G'} conj(M[i][n][G]) einv[G][G'] v(G') M[i][n'][G']
+ *   BGW_SIGMA_CH  Coulomb hole, sum over states (cohsex-ch-sum equation)
+ *       S[n][n'] = pf/2 sum_i sum_{G,G'} conj(M[i][n][G]) (einv[G][G'] - delta) v(G') M[i][n'][G']
+ * The caller passes the occupied inner states for X and SX, all inner states
+ * for CH, and sums the q terms (accumulate).  X runs on the chi-sum kernels
+ * (contraction over (i, G), FP64 or split BF16); SX and CH form W M with an
+ * FP64 MFMA product, regroup it by inner state and contract over (i, G).
+ * ---------------------------------------------------------------------- */
+#define BGW_SIGMA_X 0
+#define BGW_SIGMA_SX 1
+#define BGW_SIGMA_CH 2
+
+typedef struct {
+    const double *M;      /* DEVICE complex128 [ninner][nouter][ng] */
+    int ninner, nouter;   /* inner states (>= 1), outer states (1 .. 65536) */
+    int ng;               /* G vectors, 1 .. 8192 */
+    int kind;             /* BGW_SIGMA_X, BGW_SIGMA_SX or BGW_SIGMA_CH */
+    int head;             /* BGW_SIGMA_X: index of G = 0 left out, -1 none; ignored otherwise */
+    int precision;        /* BGW_SIGMA_X: BGW_FP64 or BGW_SPLIT_BF16; SX and CH: BGW_FP64 */
+    const double *v;      /* DEVICE f64 [ng]: v(q+G) */
+    const double *epsinv; /* DEVICE complex128 [ng][ng]: eps^-1(q; 0) for SX and CH, NULL for X */
+    double prefactor;     /* pf */
+    int accumulate;       /* 0: sigma = term; 1: sigma += term */
+    int pad;              /* unused, 0 */
+    double *sigma;        /* DEVICE complex128 [nouter][nouter], output */
+} bgw_sigma_desc;
+
+/* Work is ordered on `stream`; the handle's workspace holds the operands.
+ * Errors as bgw_chi0 (BGW_ERR_ARG for a bad kind, size or null pointer,
+ * BGW_ERR_UNSUPPORTED for split precision with SX or CH). */
+int bgw_sigma(bgw_handle_t h, const bgw_sigma_desc *d, void *stream);
+
+/* Device workspace bgw_sigma(h, d, ...) needs, in bytes (HOST *bytes).
+ * Allocates nothing. */
+int bgw_sigma_workspace(bgw_handle_t h, const bgw_sigma_desc *d, size_t *bytes);
+
+/* ------------------------------------------------------------------------
  * Dielectric matrix and its inverse
  *
  * epsilon_GG'(omega) = delta_GG' - v(q+G) chi_GG'(omega)   (epsilon section,

@@ -38,7 +38,8 @@ EXPORTS = [
     "bgw_pair_desc_check", "bgw_pair_density", "bgw_chi0", "bgw_eps_inv", "bgw_vcoul_bulk",
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
-    "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace",
+    "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace", "bgw_sigma",
+    "bgw_sigma_workspace",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -109,6 +110,28 @@ class KxDesc(ctypes.Structure):
     ]
 
 
+SIGMA_X, SIGMA_SX, SIGMA_CH = 0, 1, 2
+_SIGMA = {"x": SIGMA_X, "sx": SIGMA_SX, "ch": SIGMA_CH}
+
+
+class SigmaDesc(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_void_p),
+        ("ninner", ctypes.c_int),
+        ("nouter", ctypes.c_int),
+        ("ng", ctypes.c_int),
+        ("kind", ctypes.c_int),
+        ("head", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("v", ctypes.c_void_p),
+        ("epsinv", ctypes.c_void_p),
+        ("prefactor", ctypes.c_double),
+        ("accumulate", ctypes.c_int),
+        ("pad", ctypes.c_int),
+        ("sigma", ctypes.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -142,6 +165,8 @@ def lib():
         L.bgw_eps_inv.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_eps_inv_noalloc.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_bse_kx.argtypes = [P, ctypes.POINTER(KxDesc), P]
+        L.bgw_sigma.argtypes = [P, ctypes.POINTER(SigmaDesc), P]
+        L.bgw_sigma_workspace.argtypes = [P, ctypes.POINTER(SigmaDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_bse_kx_workspace.argtypes = [P, ctypes.POINTER(KxDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
         L.bgw_set_timing.argtypes = [P, I]
@@ -159,7 +184,7 @@ def lib():
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
                   "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx",
-                  "bgw_bse_kx_workspace"):
+                  "bgw_bse_kx_workspace", "bgw_sigma", "bgw_sigma_workspace"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -434,6 +459,37 @@ class Handle:
             d = self._kx_desc(M, v, head, prefactor, precision, kx)
         out = ctypes.c_size_t()
         _check(lib().bgw_bse_kx_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
+        return int(out.value)
+
+    # ---------------------------------------------------------------- static self-energy
+    def _sigma_desc(self, kind, M, v, epsinv, head, prefactor, precision, accumulate, sigma):
+        import torch
+        ni, no, ng = M.shape
+        assert M.dtype == torch.complex128 and M.is_contiguous()
+        assert v.dtype == torch.float64 and v.numel() == ng and v.is_contiguous()
+        if epsinv is not None:
+            assert epsinv.shape == (ng, ng) and epsinv.dtype == torch.complex128 and epsinv.is_contiguous()
+        assert sigma.shape == (no, no) and sigma.dtype == torch.complex128 and sigma.is_contiguous()
+        return SigmaDesc(M=_dptr(M), ninner=ni, nouter=no, ng=ng, kind=_SIGMA[kind], head=int(head),
+                         precision=int(precision), v=_dptr(v), epsinv=_dptr(epsinv), prefactor=float(prefactor),
+                         accumulate=1 if accumulate else 0, pad=0, sigma=_dptr(sigma))
+
+    def sigma(self, kind, M, v, prefactor, epsinv=None, head=-1, precision=FP64, accumulate=False, sigma=None):
+        """Self-energy matrix [nouter][nouter] of one q from M[ninner][nouter][ng]: kind "x", "sx" or "ch"."""
+        import torch
+        if sigma is None:
+            sigma = torch.zeros((M.shape[1], M.shape[1]), dtype=torch.complex128, device=M.device)
+        d = self._sigma_desc(kind, M, v, epsinv, head, prefactor, precision, accumulate, sigma)
+        _check(lib().bgw_sigma(self._h, ctypes.byref(d), _stream()))
+        return sigma
+
+    def sigma_workspace(self, kind, M, v, prefactor, epsinv=None, head=-1, precision=FP64, sigma=None) -> int:
+        import torch
+        if sigma is None:
+            sigma = torch.zeros((M.shape[1], M.shape[1]), dtype=torch.complex128, device=M.device)
+        d = self._sigma_desc(kind, M, v, epsinv, head, prefactor, precision, False, sigma)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_sigma_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
         return int(out.value)
 
     def eps_inv_noalloc(self, vcoul, chi, epsinv, info):

@@ -59,13 +59,17 @@ constexpr int KR = 2 * KC;   // real contraction rows per stage
 constexpr int LDA = 64 + 16; // padded LDS row (doubles): the two half-waves of a 64-bit MFMA operand
                              // read hit disjoint bank halves
 
-// One T x T output tile over pairs [k0, k1): 4 waves in a 2 x 2 layout, each
-// owning a (T/2) x (T/2) block of 16 x 16 MFMA tiles.  Raw sums (no prefactor)
-// are stored to o (tile rows/cols beyond ng are dropped).
-template <int T>
-__device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng, const double *__restrict__ w,
-                                          int G0, int H0, long long k0, long long k1, double2 *__restrict__ o,
-                                          double (*As)[LDA], double (*Bs)[LDA]) {
+// One T x T tile of sum_t conj(P[t][G]) w_t Q[t][H] over t in [k0, k1) (w_t
+// = 1 without weights): 4 waves in a 2 x 2 layout, each owning a (T/2) x
+// (T/2) block of 16 x 16 MFMA tiles.  P has rows of ldp values of which the
+// first m are used, Q rows of ldq with n used.  Raw sums (no prefactor) are
+// stored to o, rows of ldo (tile rows >= m or columns >= n are dropped).
+template <int T, bool W>
+__device__ __forceinline__ void pq_tile(const double2 *__restrict__ P, long long ldp, int m,
+                                        const double2 *__restrict__ Q, long long ldq, int n,
+                                        const double *__restrict__ w, int G0, int H0, long long k0, long long k1,
+                                        double2 *__restrict__ o, long long ldo, double (*As)[LDA],
+                                        double (*Bs)[LDA]) {
     constexpr int NB = T / 32;    // MFMA tiles per wave side
     constexpr int WT = T / 2;     // wave block edge
     constexpr int LR = 256 / T;   // loader rows per sweep
@@ -96,9 +100,9 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
         for (int s = 0; s < SL; ++s) {
             const long long t = kk + lrow + LR * s;
             const bool in = t < k1;
-            wt[s] = in ? w[t] : 0.0;
-            a[s] = (in && G0 + lcol < ng) ? M[t * ng + G0 + lcol] : make_double2(0.0, 0.0);
-            b[s] = (in && H0 + lcol < ng) ? M[t * ng + H0 + lcol] : make_double2(0.0, 0.0);
+            wt[s] = in ? (W ? w[t] : 1.0) : 0.0;
+            a[s] = (in && G0 + lcol < m) ? P[t * ldp + G0 + lcol] : make_double2(0.0, 0.0);
+            b[s] = (in && H0 + lcol < n) ? Q[t * ldq + H0 + lcol] : make_double2(0.0, 0.0);
         }
     };
     load_stage(k0);
@@ -145,8 +149,16 @@ __device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng,
             for (int r = 0; r < 4; ++r) {
                 const int G = G0 + wr * WT + 16 * a + 4 * r + lk;
                 const int H = H0 + wc * WT + 16 * b + li;
-                if (G < ng && H < ng) o[(size_t)G * ng + H] = make_double2(cre[a][b][r], cim[a][b][r]);
+                if (G < m && H < n) o[(size_t)G * ldo + H] = make_double2(cre[a][b][r], cim[a][b][r]);
             }
+}
+
+// The chi-sum tile: P = Q = M, rows of ng, weights w.
+template <int T>
+__device__ __forceinline__ void herk_tile(const double2 *__restrict__ M, int ng, const double *__restrict__ w,
+                                          int G0, int H0, long long k0, long long k1, double2 *__restrict__ o,
+                                          double (*As)[LDA], double (*Bs)[LDA]) {
+    pq_tile<T, true>(M, ng, ng, M, ng, ng, w, G0, H0, k0, k1, o, ng, As, Bs);
 }
 }  // namespace
 
@@ -237,14 +249,45 @@ __global__ void k_chi_finalize(const FinProb *__restrict__ probs) {
     }
 }
 
+// C = P^H Q (rows t of P and Q contracted) for one problem, all T x T tiles of
+// the m x n result, the contraction cut into ns ranges: raw sums of range s
+// to out + s m n.  A persistent grid strides over the (range, tile) items.
+template <int T>
+__global__ __launch_bounds__(256, 3) void k_gemm_phq(const GemmProb G) {
+    __shared__ double As[KR][LDA];
+    __shared__ double Bs[KR][LDA];
+    const long long ntile = (long long)G.ntr * G.ntc;
+    for (long long item = blockIdx.x; item < ntile * G.ns; item += gridDim.x) {
+        const long long split = item / ntile, tile = item % ntile;
+        const int tr = (int)(tile / G.ntc), tc = (int)(tile % G.ntc);
+        const long long k0 = split * G.kper, k1 = min(G.K, k0 + G.kper);
+        pq_tile<T, false>(G.P, G.ldp, G.m, G.Q, G.ldq, G.n, nullptr, tr * T, tc * T, k0, k1,
+                          G.out + (size_t)split * G.m * G.n, G.n, As, Bs);
+    }
+}
+
+// C (+)= scale * sum over s < ns of part[s] (m x n, complex).
+__global__ void k_gemm_finalize(const double2 *__restrict__ part, int ns, long long mn, double scale,
+                                double2 *__restrict__ C, int accumulate) {
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mn; e += (long long)gridDim.x * blockDim.x) {
+        double2 a = make_double2(0.0, 0.0);
+        for (int p = 0; p < ns; ++p) a = cadd(a, part[p * mn + e]);
+        a = make_double2(scale * a.x, scale * a.y);
+        C[e] = accumulate ? cadd(C[e], a) : a;
+    }
+}
+
 // MT[G][t] = M[t][G] for the K x ng matrix M (pairs x G), row `head` of MT
 // zeroed (head < 0: none): the contraction over G of the Bethe-Salpeter
 // exchange kernel becomes the contraction over the leading index that the
-// chi-sum kernels perform.  32 x 32 tiles through LDS, both sides coalesced;
-// grid (ceil(ng / 32), ceil(K / 32)), block (32, 8).
+// chi-sum kernels perform.  grid.z batches: matrix z starts at M + z K ng and
+// MT + z ng K.  32 x 32 tiles through LDS, both sides coalesced; grid
+// (ceil(ng / 32), ceil(K / 32), batches), block (32, 8).
 __global__ __launch_bounds__(256) void k_transpose_pairs(const double2 *__restrict__ M, long long K, int ng,
                                                          int head, double2 *__restrict__ MT) {
     __shared__ double2 tile[32][33];
+    M += (size_t)blockIdx.z * K * ng;
+    MT += (size_t)blockIdx.z * K * ng;
     const int g0 = blockIdx.x * 32;
     const long long t0 = (long long)blockIdx.y * 32;
 #pragma unroll
@@ -263,11 +306,61 @@ __global__ __launch_bounds__(256) void k_transpose_pairs(const double2 *__restri
     }
 }
 
+// Self-energy operands.  w[i ng + G] = v[G] for i < ninner (the bare
+// exchange's weights along the contraction index (i, G)).
+__global__ void k_sigma_weights(const double *__restrict__ v, int ng, int ninner, double *__restrict__ w) {
+    const long long n = (long long)ng * ninner;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        w[e] = v[e % ng];
+}
+
+// WT[k][g] = conj(W[g][k]) with W[g][k] = (einv[g][k] - ch delta_gk) v[k]: the
+// screened interaction (ch = 0) or its screening part (ch = 1), transposed
+// and conjugated so that sum_k conj(WT[k][g]) A[k] = (W A)[g].  32 x 32 tiles
+// through LDS; grid (ceil(ng / 32), ceil(ng / 32)), block (32, 8).
+__global__ __launch_bounds__(256) void k_sigma_wt(const double2 *__restrict__ einv, const double *__restrict__ v,
+                                                  int ng, int ch, double2 *__restrict__ WT) {
+    __shared__ double2 tile[32][33];
+    const int k0 = blockIdx.x * 32, g0 = blockIdx.y * 32;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int g = g0 + threadIdx.y + 8 * r, k = k0 + threadIdx.x;
+        double2 e = make_double2(0.0, 0.0);
+        if (g < ng && k < ng) {
+            e = einv[(size_t)g * ng + k];
+            if (ch && g == k) e.x -= 1.0;
+            e = make_double2(e.x * v[k], -e.y * v[k]);
+        }
+        tile[threadIdx.y + 8 * r][threadIdx.x] = e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = k0 + threadIdx.y + 8 * r, g = g0 + threadIdx.x;
+        if (k < ng && g < ng) WT[(size_t)k * ng + g] = tile[threadIdx.x][threadIdx.y + 8 * r];
+    }
+}
+
+// B2[i ng + G][n] = B[G][i nouter + n]: the rows of W M regrouped by inner
+// state, so that the last contraction runs over (i, G).
+__global__ void k_sigma_regroup(const double2 *__restrict__ B, int ng, int ninner, int nouter,
+                                double2 *__restrict__ B2) {
+    const long long total = (long long)ng * ninner * nouter;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int n = (int)(e % nouter);
+        const long long r = e / nouter;
+        const int G = (int)(r % ng), i = (int)(r / ng);
+        B2[e] = B[((size_t)G * ninner + i) * nouter + n];
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
-int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t st) {
-    hipLaunchKernelGGL(k_transpose_pairs, dim3((ng + 31) / 32, (unsigned)((K + 31) / 32)), dim3(32, 8), 0, st, M, K,
-                       ng, head, MT);
+int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t st,
+                           int batches) {
+    hipLaunchKernelGGL(k_transpose_pairs, dim3((ng + 31) / 32, (unsigned)((K + 31) / 32), batches), dim3(32, 8), 0,
+                       st, M, K, ng, head, MT);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
@@ -297,6 +390,47 @@ int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long 
     const long long g = std::max<long long>(1, std::min<long long>(i1 - i0, grid));
     if (tile == 64) hipLaunchKernelGGL(k_herk_f64<64>, dim3((unsigned)g), dim3(256), 0, st, probs, nprob, i0, i1);
     else hipLaunchKernelGGL(k_herk_f64<32>, dim3((unsigned)g), dim3(256), 0, st, probs, nprob, i0, i1);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int device_cus();
+
+int launch_gemm_phq(const GemmProb &G, int tile, hipStream_t st) {
+    const long long items = (long long)G.ntr * G.ntc * G.ns;
+    const long long g = std::max<long long>(1, std::min<long long>(items, (long long)device_cus() * 3));
+    if (tile == 64) hipLaunchKernelGGL(k_gemm_phq<64>, dim3((unsigned)g), dim3(256), 0, st, G);
+    else hipLaunchKernelGGL(k_gemm_phq<32>, dim3((unsigned)g), dim3(256), 0, st, G);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_gemm_finalize(const double2 *part, int ns, long long mn, double scale, double2 *C, int accumulate,
+                         hipStream_t st) {
+    const int blocks = (int)std::max<long long>(1, std::min<long long>((mn + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_gemm_finalize, dim3(blocks), dim3(256), 0, st, part, ns, mn, scale, C, accumulate);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_sigma_weights(const double *v, int ng, int ninner, double *w, hipStream_t st) {
+    const long long n = (long long)ng * ninner;
+    hipLaunchKernelGGL(k_sigma_weights, dim3((unsigned)std::min<long long>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                       v, ng, ninner, w);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_sigma_wt(const double2 *einv, const double *v, int ng, int ch, double2 *WT, hipStream_t st) {
+    hipLaunchKernelGGL(k_sigma_wt, dim3((ng + 31) / 32, (ng + 31) / 32), dim3(32, 8), 0, st, einv, v, ng, ch, WT);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_sigma_regroup(const double2 *B, int ng, int ninner, int nouter, double2 *B2, hipStream_t st) {
+    const long long n = (long long)ng * ninner * nouter;
+    hipLaunchKernelGGL(k_sigma_regroup, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0, st,
+                       B, ng, ninner, nouter, B2);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }

@@ -852,6 +852,179 @@ extern "C" int bgw_bse_kx(bgw_handle_t h, const bgw_kx_desc *d, void *stream) {
     return run_eager(h, &kp.cd, P, st);
 }
 
+namespace bgw {
+namespace {
+int check_sigma_desc(const bgw_sigma_desc *d) {
+    if (!d || !d->M || !d->v || !d->sigma) return fail(BGW_ERR_ARG, "bad self-energy descriptor");
+    if (d->kind != BGW_SIGMA_X && d->kind != BGW_SIGMA_SX && d->kind != BGW_SIGMA_CH)
+        return fail(BGW_ERR_ARG, "unknown self-energy kind");
+    if (d->ninner < 1 || d->nouter < 1 || d->nouter > 65536 || d->ng < 1)
+        return fail(BGW_ERR_ARG, "self-energy: sizes out of range");
+    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "self-energy: ng > 8192");
+    if ((long long)d->ninner * d->ng > 0x7fffffffll) return fail(BGW_ERR_UNSUPPORTED, "self-energy: ninner * ng too large");
+    if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16) return fail(BGW_ERR_ARG, "unknown precision");
+    if (d->kind != BGW_SIGMA_X) {
+        if (!d->epsinv) return fail(BGW_ERR_ARG, "self-energy: screened kinds need eps^-1");
+        if (d->precision != BGW_FP64) return fail(BGW_ERR_UNSUPPORTED, "self-energy: SX and CH are FP64 only");
+    } else if (d->head < -1 || d->head >= d->ng) {
+        return fail(BGW_ERR_ARG, "self-energy: head index out of range");
+    }
+    return BGW_OK;
+}
+
+// The bare exchange as a chi-sum: "pairs" are the (inner state, G) rows of
+// MT2[i ng + G][n] = M[i][n][G], the weights v(G) repeated per inner state,
+// the output over the outer states, prefactor -pf.
+struct SigmaXProblem {
+    bgw_chi_q q;
+    bgw_chi_desc cd;
+    double omega = 0.0;
+    void set(const bgw_sigma_desc *d, const void *MT2, const double *w) {
+        std::memset(&q, 0, sizeof(q));
+        q.ng = d->nouter;
+        q.nk = 1;
+        q.nv = 1;
+        q.nc = d->ninner * d->ng;
+        q.M = (const double *)MT2;
+        q.ev = w;
+        q.ec = w;
+        q.head = -1;
+        q.prefactor = -d->prefactor;
+        q.chi = d->sigma;
+        std::memset(&cd, 0, sizeof(cd));
+        cd.nq = 1;
+        cd.q = &q;
+        cd.nw = 1;
+        cd.omega = &omega;
+        cd.precision = d->precision;
+        cd.accumulate = d->accumulate;
+        cd.axis = BGW_AXIS_IMAG;
+    }
+};
+
+// One P^H Q product: tile edge, K-split count and the split ranges.
+GemmProb gemm_plan(const double2 *P, long long ldp, int m, const double2 *Q, long long ldq, int n, long long K,
+                   int &tile) {
+    GemmProb g;
+    std::memset(&g, 0, sizeof(g));
+    tile = std::min(m, n) >= 64 ? 64 : 32;
+    g.P = P;
+    g.Q = Q;
+    g.K = K;
+    g.ldp = ldp;
+    g.ldq = ldq;
+    g.m = m;
+    g.n = n;
+    g.ntr = (m + tile - 1) / tile;
+    g.ntc = (n + tile - 1) / tile;
+    const long long tiles = (long long)g.ntr * g.ntc;
+    long long ns = std::max<long long>(1, (3LL * device_cus() + tiles - 1) / tiles);
+    ns = std::min<long long>(ns, std::max<long long>(1, K / 64));
+    ns = std::min<long long>(ns, 256);
+    long long kper = (K + ns - 1) / ns;
+    kper = (kper + 15) / 16 * 16;
+    g.kper = kper;
+    g.ns = (int)((K + kper - 1) / kper);
+    return g;
+}
+
+// Workspace carve-up of the screened kinds: WT, M^T, W M, the regrouped
+// operands and the partial sums of the two products.
+struct SigmaWLayout {
+    size_t wt = 0, mt = 0, b = 0, mt2 = 0, b2 = 0, p1 = 0, p2 = 0, total = 0;
+    int tile1 = 64, tile2 = 32;
+    GemmProb g1, g2;
+};
+
+SigmaWLayout sigma_w_layout(const bgw_sigma_desc *d, char *ws) {
+    SigmaWLayout L;
+    const long long ng = d->ng, K = (long long)d->ninner * d->nouter;
+    size_t off = 0;
+    L.wt = off;
+    off += al256(sizeof(double2) * ng * ng);
+    L.mt = off;
+    off += al256(sizeof(double2) * ng * K);
+    L.b = off;
+    off += al256(sizeof(double2) * ng * K);
+    L.mt2 = off;
+    off += al256(sizeof(double2) * ng * K);
+    L.b2 = off;
+    off += al256(sizeof(double2) * ng * K);
+    L.g1 = gemm_plan((const double2 *)(ws + L.wt), ng, d->ng, (const double2 *)(ws + L.mt), K, (int)K, ng, L.tile1);
+    L.p1 = off;
+    if (L.g1.ns > 1) off += al256(sizeof(double2) * (size_t)L.g1.ns * ng * K);
+    L.g1.out = (double2 *)(ws + (L.g1.ns > 1 ? L.p1 : L.b));
+    L.g2 = gemm_plan((const double2 *)(ws + L.mt2), d->nouter, d->nouter, (const double2 *)(ws + L.b2), d->nouter,
+                     d->nouter, (long long)d->ninner * ng, L.tile2);
+    L.p2 = off;
+    off += al256(sizeof(double2) * (size_t)L.g2.ns * d->nouter * d->nouter);
+    L.g2.out = (double2 *)(ws + L.p2);
+    L.total = off + 256;
+    return L;
+}
+}  // namespace
+}  // namespace bgw
+
+extern "C" int bgw_sigma_workspace(bgw_handle_t h, const bgw_sigma_desc *d, size_t *bytes) {
+    clear_error();
+    BGW_TRY(check_sigma_desc(d));
+    if (!h || !bytes) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    if (d->kind == BGW_SIGMA_X) {
+        const size_t pre = al256(sizeof(double2) * (size_t)d->ninner * d->ng * d->nouter) +
+                           al256(sizeof(double) * (size_t)d->ninner * d->ng);
+        SigmaXProblem sp;
+        sp.set(d, d->M, d->v);
+        ChiPlan P;
+        BGW_TRY(make_plan(h, &sp.cd, P, 0, 0, 0, pre, true));
+        *bytes = P.ws_bytes;
+    } else {
+        *bytes = sigma_w_layout(d, nullptr).total;
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_sigma(bgw_handle_t h, const bgw_sigma_desc *d, void *stream) {
+    clear_error();
+    BGW_TRY(check_sigma_desc(d));
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    const long long ng = d->ng, ni = d->ninner, no = d->nouter;
+    if (d->kind == BGW_SIGMA_X) {
+        const size_t mt2 = al256(sizeof(double2) * (size_t)ni * ng * no);
+        const size_t pre = mt2 + al256(sizeof(double) * (size_t)ni * ng);
+        SigmaXProblem sp;
+        ChiPlan P0;
+        sp.set(d, d->M, d->v);
+        BGW_TRY(make_plan(h, &sp.cd, P0, 0, 0, 0, pre, true));
+        BGW_TRY(ensure_ws(h, P0.ws_bytes, st));
+        char *ws = (char *)h->ws.p;
+        double2 *MT2 = (double2 *)ws;
+        double *w = (double *)(ws + mt2);
+        BGW_TRY(launch_transpose_pairs((const double2 *)d->M, no, d->ng, d->head, MT2, st, d->ninner));
+        BGW_TRY(launch_sigma_weights(d->v, d->ng, d->ninner, w, st));
+        sp.set(d, MT2, w);
+        ChiPlan P;
+        BGW_TRY(make_plan(h, &sp.cd, P, 0, 0, 0, pre, true));
+        return run_eager(h, &sp.cd, P, st);
+    }
+    BGW_TRY(ensure_ws(h, sigma_w_layout(d, nullptr).total, st));
+    char *ws = (char *)h->ws.p;
+    SigmaWLayout L = sigma_w_layout(d, ws);
+    const double2 *M = (const double2 *)d->M;
+    BGW_TRY(launch_sigma_wt((const double2 *)d->epsinv, d->v, d->ng, d->kind == BGW_SIGMA_CH, (double2 *)(ws + L.wt), st));
+    BGW_TRY(launch_transpose_pairs(M, ni * no, d->ng, -1, (double2 *)(ws + L.mt), st));
+    BGW_TRY(launch_gemm_phq(L.g1, L.tile1, st));
+    if (L.g1.ns > 1)
+        BGW_TRY(launch_gemm_finalize(L.g1.out, L.g1.ns, ng * ni * no, 1.0, (double2 *)(ws + L.b), 0, st));
+    BGW_TRY(launch_sigma_regroup((const double2 *)(ws + L.b), d->ng, d->ninner, d->nouter, (double2 *)(ws + L.b2), st));
+    BGW_TRY(launch_transpose_pairs(M, no, d->ng, -1, (double2 *)(ws + L.mt2), st, d->ninner));
+    BGW_TRY(launch_gemm_phq(L.g2, L.tile2, st));
+    const double scale = d->kind == BGW_SIGMA_CH ? 0.5 * d->prefactor : -d->prefactor;
+    return launch_gemm_finalize(L.g2.out, L.g2.ns, no * no, scale, (double2 *)d->sigma, d->accumulate, st);
+}
+
 extern "C" int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
     clear_error();
     BGW_TRY(check_chi_desc(d));

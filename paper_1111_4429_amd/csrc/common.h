@@ -149,6 +149,17 @@ struct HerkProb {
     int ns;            // K splits
 };
 
+// One product C = P^H Q (k_gemm_phq): P [K][ldp] (first m columns used), Q
+// [K][ldq] (first n used); raw sums of the ns contraction ranges to
+// out[ns][m][n].
+struct GemmProb {
+    const double2 *P;
+    const double2 *Q;
+    double2 *out;
+    long long K, kper, ldp, ldq;
+    int m, n, ntr, ntc, ns, pad;
+};
+
 // One output matrix of a chi0 call: chi = pf * (A + i B) where A (and, on
 // the real frequency axis, B) are the Hermitian chi sums of one weight
 // vector each, held as raw upper-triangle sums.

@@ -101,7 +101,14 @@ int herk_blocks_per_cu();
 int launch_herk_batch(const HerkProb *probs, int nprob, long long i0, long long i1, int tile, int grid,
                       hipStream_t);
 int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_t);
-int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t);
+int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t,
+                           int batches = 1);
+int launch_gemm_phq(const GemmProb &G, int tile, hipStream_t);
+int launch_sigma_weights(const double *v, int ng, int ninner, double *w, hipStream_t);
+int launch_sigma_wt(const double2 *einv, const double *v, int ng, int ch, double2 *WT, hipStream_t);
+int launch_sigma_regroup(const double2 *B, int ng, int ninner, int nouter, double2 *B2, hipStream_t);
+int launch_gemm_finalize(const double2 *part, int ns, long long mn, double scale, double2 *C, int accumulate,
+                         hipStream_t);
 
 // ---- split-precision launchers (split.hip)
 int split_gpad(int ng);                         // columns of the digit slices (multiple of 128)
