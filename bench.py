@@ -363,6 +363,101 @@ def bench_kx(args, wl):
     print(json.dumps(out), flush=True)
 
 
+def bench_sigma(args, wl, nouter=64):
+    """Static self-energy of one q: one step = pair densities of all inner x
+    outer states -> bare exchange (occupied inner states) -> screened exchange
+    (occupied) -> Coulomb hole (all inner states), with a given eps^-1 (a
+    generic dense stand-in: the step times the self-energy contractions)."""
+    import torch
+
+    from paper_1111_4429_amd import bgw, synth
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    s = synth.make_system(wl)
+    q = s["qs"][0]
+    n, ng, nocc = s["n"], q["ng"], wl.nv
+    ninner = wl.nv + wl.nc
+    pf = 1.0 / (s["nk"] * s["vol"])
+    h = bgw.Handle(0)
+    inner = torch.from_numpy(np.ascontiguousarray(np.concatenate([q["cv"], s["cc"]], axis=1))).to(dev)
+    outer = torch.from_numpy(np.ascontiguousarray(s["cc"][:, :nouter])).to(dev)
+    v = torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev)
+    rng = np.random.default_rng(0)
+    W = torch.from_numpy(np.eye(ng) + 0.01 * (rng.standard_normal((ng, ng)) + 1j * rng.standard_normal((ng, ng)))).to(dev)
+    Mflat = torch.empty((ninner * nouter, ng), dtype=torch.complex128, device=dev)
+    M = Mflat.view(ninner, nouter, ng)
+    occ = M[:nocc]
+    sig = {k: torch.empty((nouter, nouter), dtype=torch.complex128, device=dev) for k in ("x", "sx", "ch")}
+
+    def step():
+        h.pair_density(n, s["gw"], q["ge"], inner, outer, M=Mflat)
+        h.sigma("x", occ, v, pf, head=0, sigma=sig["x"])
+        h.sigma("sx", occ, v, pf, epsinv=W, sigma=sig["sx"])
+        h.sigma("ch", M, v, pf, epsinv=W, sigma=sig["ch"])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    # CH alone, events on the launch stream: the dominant product W M
+    e0.record()
+    for _ in range(args.steps):
+        h.sigma("ch", M, v, pf, epsinv=W, sigma=sig["ch"])
+    e1.record()
+    torch.cuda.synchronize()
+    ch_ms = e0.elapsed_time(e1) / args.steps
+    f_x = 4.0 * nouter * nouter * nocc * ng
+    f_w = lambda ni: 8.0 * ng * ng * ni * nouter + 8.0 * nouter * nouter * ni * ng
+    flops = f_x + f_w(nocc) + f_w(ninner)
+    out = {
+        "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies; "
+                "eps^-1 a seeded dense stand-in)",
+        "config": {"workload": wl.name, "quantity": "static self-energy (X, SX, CH sum form) of one q",
+                   "grid": f"{n}^3", "ng": ng, "ninner": ninner, "nocc": nocc, "nouter": nouter},
+        "stages": {"coulomb_hole_ms": ch_ms, "coulomb_hole_TFLOPs": f_w(ninner) / (ch_ms * 1e-3) / 1e12},
+        "roofline": {"kernel": "k_gemm_phq (W M and the (i, G) contraction of the Coulomb hole)", "bound": "mfma",
+                     "achieved": f_w(ninner) / (ch_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": f_w(ninner) / (ch_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "algorithmic_per_launch": f_w(ninner), "avg_launch_ms": ch_ms, "launches_per_step": 1,
+                     "note": "per bgw_sigma call of the Coulomb hole (its two products, regrouping and finalize)"},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        import oracle
+
+        Mh, vh, Wh = M.cpu().numpy(), v.cpu().numpy(), W.cpu().numpy()
+        sel = list(range(0, nouter, nouter // 4))[:4]
+        t0 = time.perf_counter()
+        oracle.sigma("ch", Mh[:, sel], vh, pf, einv=Wh)
+        t_s = time.perf_counter() - t0
+        t_ch = t_s * nouter / len(sel)  # the oracle's cost is linear in the outer states (ninner Ng^2 each)
+        out["cpu_baseline"] = {"value": f_w(ninner) / t_ch / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle Coulomb hole on {len(sel)} of {nouter} outer states "
+                                         f"({t_s:.1f} s), extrapolated linearly in the outer states: "
+                                         f"{t_ch:.0f} s per call", "cpu": _cpu_model()}
+    h.close()
+    del M, Mflat, occ, W, inner, outer, v, sig
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -388,6 +483,9 @@ def main():
     wl = synth.WORKLOADS[args.workload]
     if wl.name.startswith("bse-kx"):
         bench_kx(args, wl)
+        return
+    if wl.name.startswith("sigma"):
+        bench_sigma(args, wl)
         return
     q_subset = None
     if wl.nq > 1 and args.q_subset != "all":

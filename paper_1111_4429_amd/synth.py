@@ -78,6 +78,8 @@ WORKLOADS: Dict[str, Workload] = {
                             nq=64, ng_range=(500, 6000), precision="split"),
     # Bethe-Salpeter exchange kernel over K = 4 x 64 x 64 = 16384 pairs of the silicon-like cell
     "bse-kx-48": Workload("bse-kx-48", n=48, ng=1500, ngw=1500, nv=4, nc=64, nk=64),
+    # static self-energy of the silicon-like cell: 404 inner states (4 occupied), 64 outer states, one q
+    "sigma-48": Workload("sigma-48", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=1),
 }
 
 
