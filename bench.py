@@ -458,6 +458,122 @@ def bench_sigma(args, wl, nouter=64):
     print(json.dumps(out), flush=True)
 
 
+def bench_real(args, wl):
+    """Real flavor (real coefficients): one step = real pair densities of every
+    pair -> real symmetric chi-sum (FP64 MFMA, Ng^2 K flops per frequency: the
+    half of the real product that symmetry leaves).  The complex FP64 chi-sum
+    of the same M is timed beside it: both give the same chi."""
+    import torch
+
+    from paper_1111_4429_amd import bgw, synth
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    s = synth.make_system(wl)
+    q = s["qs"][0]
+    n, nk, nv, nc, ng = s["n"], s["nk"], s["nv"], s["nc"], q["ng"]
+    K = nk * nv * nc
+    omega = s["omega"]
+    nw = len(omega)
+    pf = 1.0 / (nk * s["vol"])
+    h = bgw.Handle(0)
+    cv = torch.from_numpy(q["cv"]).to(dev)
+    cc = torch.from_numpy(s["cc"]).to(dev)
+    ev = torch.from_numpy(q["ev"]).to(dev)
+    ec = torch.from_numpy(s["ec"]).to(dev)
+    M = torch.empty((K, ng), dtype=torch.float64, device=dev)
+    chi = torch.empty((nw, ng, ng), dtype=torch.float64, device=dev)
+    ent = dict(M=M, ev=ev, ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf)
+
+    def step():
+        h.pair_density_real(n, s["gw"], q["ge"], cv, cc, M=M)
+        h.chi0_real([ent], omega, chis=[chi])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.reset_timing()
+    h.set_timing(True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    h.set_timing(False)
+    tm = h.timing()
+    per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
+    launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
+    flops = float(ng) * ng * K * nw
+    chi_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize"))
+    syrk_ms = per_step["herk"] / launches["herk"]
+    # the complex FP64 chi-sum of the same (real) M, cast to complex
+    Mc = M.to(torch.complex128)
+    chic = torch.empty((nw, ng, ng), dtype=torch.complex128, device=dev)
+    centry = [dict(ent, M=Mc)]
+    h.chi0(centry, omega, chis=[chic])
+    torch.cuda.synchronize()
+    h.reset_timing()
+    h.set_timing(True)
+    for _ in range(args.steps):
+        h.chi0(centry, omega, chis=[chic])
+    torch.cuda.synchronize()
+    h.set_timing(False)
+    tc = h.timing()
+    cplx_ms = sum(tc[k][0] for k in ("weights", "herk", "finalize") if tc[k][1]) / args.steps
+    agree = float(torch.linalg.vector_norm(chi - chic.real) / torch.linalg.vector_norm(chic.real))
+    del Mc, chic
+    out = {
+        "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator: real orthonormal plane-wave coefficients, uniform band energies)",
+        "config": {"workload": wl.name, "flavor": "real", "grid": f"{n}^3", "ng": ng, "nv": nv, "nc": nc,
+                   "nk": nk, "npairs": K, "nw": nw,
+                   "flops": "Ng^2 K per frequency (real symmetric rank-K update)"},
+        "stages": {"pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
+                   "chi_ms": chi_ms, "syrk_ms": per_step["herk"],
+                   "chi_sum_TFLOPs": flops / (chi_ms * 1e-3) / 1e12,
+                   "complex_fp64_chi_ms_same_M": cplx_ms,
+                   "real_vs_complex_chi_speedup": cplx_ms / chi_ms,
+                   "real_vs_complex_chi_rel_diff": agree},
+        "roofline": {"kernel": "k_syrk_f64 (real symmetric rank-K update)", "bound": "mfma",
+                     "achieved": flops / launches["herk"] / (syrk_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s",
+                     "frac": flops / launches["herk"] / (syrk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "traffic": None, "algorithmic_per_launch": flops / launches["herk"], "avg_launch_ms": syrk_ms,
+                     "launches_per_step": launches["herk"]},
+        "kernel_share": {k: per_step[k] / ms_step for k in per_step},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        import oracle
+
+        sample = int(max(16, min(args.cpu_sample_pairs, K, 2e11 / (8.0 * ng * ng * nw))))
+        pairs = np.sort(np.random.default_rng(123).choice(K, size=sample, replace=False))
+        t0 = time.perf_counter()
+        Ms = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
+        t_m = time.perf_counter() - t0
+        w = oracle.weights(q["ev"], s["ec"], omega)[:, pairs]
+        t0 = time.perf_counter()
+        oracle.chi(Ms, w, pf)
+        t_c = time.perf_counter() - t0
+        t_step = (t_m + t_c) * K / sample
+        out["cpu_baseline"] = {"value": flops / t_step / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle on {sample} of {K} pairs: M by convolution ({t_m:.2f} s) and chi "
+                                         f"over all {ng}x{ng} entries ({t_c:.2f} s), extrapolated x{K / sample:.0f}: "
+                                         f"{t_step:.0f} s per step", "cpu": _cpu_model()}
+    h.close()
+    del M, chi, cv, cc, ev, ec, ent
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -486,6 +602,9 @@ def main():
         return
     if wl.name.startswith("sigma"):
         bench_sigma(args, wl)
+        return
+    if wl.flavor == "real":
+        bench_real(args, wl)
         return
     q_subset = None
     if wl.nq > 1 and args.q_subset != "all":

@@ -215,6 +215,33 @@ int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
 int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cfg);
 
 /* ------------------------------------------------------------------------
+ * Real flavor (section on real and complex flavors)
+ *
+ * With inversion and time-reversal symmetry the plane-wave coefficients can
+ * be chosen real; the pair densities M_vc(G) are then real and the chi sum
+ * is a real symmetric rank-K update (four times fewer flops than the complex
+ * one, half the memory for M and chi).
+ * ---------------------------------------------------------------------- */
+/* bgw_pair_density for real coefficients: d->cv and d->cc point to DEVICE
+ * f64 [nk][nv][ngw] and [nk][nc][ngw]; M is DEVICE f64 [K][ng].  The
+ * transforms run in the complex pipeline (its workspace as for
+ * bgw_pair_density) on complex copies held, with the complex M, in a second
+ * handle buffer of 16 (nk (nv + nc) ngw + K ng) bytes.  Errors as
+ * bgw_pair_density. */
+int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream);
+
+/* bgw_chi0 for real M: q[i].M is DEVICE f64 [K][ng], q[i].chi DEVICE f64
+ * [nw][ng][ng] (real symmetric, written in full); FP64 on the imaginary axis
+ * only (BGW_ERR_UNSUPPORTED otherwise), no graph capture, `head` ignored.
+ * One weights launch, one persistent real rank-K-update launch over every
+ * (q, frequency, K range, 64 x 64 upper tile) item, one finalize. */
+int bgw_chi0_real(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
+
+/* Device workspace bgw_chi0_real(h, d, ...) needs, in bytes (HOST *bytes).
+ * Allocates nothing. */
+int bgw_chi0_real_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t *bytes);
+
+/* ------------------------------------------------------------------------
  * Exchange kernel of the Bethe-Salpeter equation
  *
  *   Kx[t][t'] = prefactor * sum over G != G0 of conj(M_t(G)) v(q+G) M_t'(G)

@@ -39,7 +39,7 @@ EXPORTS = [
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
     "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace", "bgw_sigma",
-    "bgw_sigma_workspace",
+    "bgw_sigma_workspace", "bgw_pair_density_real", "bgw_chi0_real", "bgw_chi0_real_workspace",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -166,6 +166,9 @@ def lib():
         L.bgw_eps_inv_noalloc.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_bse_kx.argtypes = [P, ctypes.POINTER(KxDesc), P]
         L.bgw_sigma.argtypes = [P, ctypes.POINTER(SigmaDesc), P]
+        L.bgw_pair_density_real.argtypes = [P, ctypes.POINTER(PairDesc), P, P]
+        L.bgw_chi0_real.argtypes = [P, ctypes.POINTER(ChiDesc), P]
+        L.bgw_chi0_real_workspace.argtypes = [P, ctypes.POINTER(ChiDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_sigma_workspace.argtypes = [P, ctypes.POINTER(SigmaDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_bse_kx_workspace.argtypes = [P, ctypes.POINTER(KxDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
@@ -184,7 +187,8 @@ def lib():
                   "bgw_eps_inv", "bgw_vcoul_bulk", "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing",
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
                   "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx",
-                  "bgw_bse_kx_workspace", "bgw_sigma", "bgw_sigma_workspace"):
+                  "bgw_bse_kx_workspace", "bgw_sigma", "bgw_sigma_workspace", "bgw_pair_density_real",
+                  "bgw_chi0_real", "bgw_chi0_real_workspace"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -343,10 +347,27 @@ class Handle:
         _check(lib().bgw_pair_density(self._h, ctypes.byref(d), _dptr(M), _stream()))
         return M
 
+    def pair_density_real(self, n, gw, ge, cv, cc, M=None):
+        """Real flavor: real coefficients (float64 [nk][nv|nc][ngw]) -> real M[t][G] (float64)."""
+        import torch
+        assert cv.dtype == torch.float64 and cc.dtype == torch.float64
+        assert cv.is_contiguous() and cc.is_contiguous()
+        nk, nv, ngw = cv.shape
+        nc = cc.shape[1]
+        assert cc.shape == (nk, nc, ngw) and len(gw) == ngw
+        ng = len(ge)
+        if M is None:
+            M = torch.empty((nk * nv * nc, ng), dtype=torch.float64, device=cv.device)
+        assert M.shape == (nk * nv * nc, ng) and M.is_contiguous() and M.dtype == torch.float64
+        d = make_pair_desc(n, gw, ge, cv, cc)
+        _check(lib().bgw_pair_density_real(self._h, ctypes.byref(d), _dptr(M), _stream()))
+        return M
+
     # ---------------------------------------------------------------- chi0
     def _chi_desc(self, qs: Sequence[dict], omega: Sequence[float], precision: int, accumulate: bool,
-                  chis: Optional[List], use_graph: bool, axis="imag", broadening: float = 0.0):
+                  chis: Optional[List], use_graph: bool, axis="imag", broadening: float = 0.0, real=False):
         import torch
+        dt = torch.float64 if real else torch.complex128
         om = np.ascontiguousarray(omega, dtype=np.float64).reshape(-1)
         arr = (ChiQ * len(qs))()
         outs = []
@@ -355,15 +376,15 @@ class Handle:
             M = q["M"]
             ng = int(M.shape[1])
             K = int(q["nk"]) * int(q["nv"]) * int(q["nc"])
-            assert M.shape[0] == K and M.dtype == torch.complex128 and M.is_contiguous()
+            assert M.shape[0] == K and M.dtype == dt and M.is_contiguous()
             ev = q["ev"].contiguous()
             ec = q["ec"].contiguous()
             assert ev.dtype == torch.float64 and ec.dtype == torch.float64
             assert ev.numel() == q["nk"] * q["nv"] and ec.numel() == q["nk"] * q["nc"]
             chi = None if chis is None else chis[i]
             if chi is None:
-                chi = torch.empty((om.size, ng, ng), dtype=torch.complex128, device=M.device)
-            assert chi.shape == (om.size, ng, ng) and chi.is_contiguous()
+                chi = torch.empty((om.size, ng, ng), dtype=dt, device=M.device)
+            assert chi.shape == (om.size, ng, ng) and chi.is_contiguous() and chi.dtype == dt
             keep += [ev, ec]
             arr[i].ng = ng
             arr[i].nk, arr[i].nv, arr[i].nc = int(q["nk"]), int(q["nv"]), int(q["nc"])
@@ -398,6 +419,21 @@ class Handle:
         _check(lib().bgw_chi0(self._h, ctypes.byref(d), _stream()))
         del keep
         return outs
+
+    def chi0_real(self, qs: Sequence[dict], omega: Sequence[float], accumulate: bool = False,
+                  chis: Optional[List] = None):
+        """Real flavor: qs as for chi0 with real M (float64 [K][ng]); returns real chi [nw][ng][ng]."""
+        d, outs, keep = self._chi_desc(qs, omega, FP64, accumulate, chis, False, real=True)
+        _check(lib().bgw_chi0_real(self._h, ctypes.byref(d), _stream()))
+        del keep
+        return outs
+
+    def chi0_real_workspace(self, qs: Sequence[dict], omega: Sequence[float]) -> int:
+        d, outs, keep = self._chi_desc(qs, omega, FP64, False, None, False, real=True)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_chi0_real_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
+        del keep
+        return int(out.value)
 
     def autotune(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64,
                  chis: Optional[List] = None):

@@ -604,6 +604,39 @@ extern "C" int bgw_pair_density(bgw_handle_t h, const bgw_pair_desc *d, double *
     return BGW_OK;
 }
 
+extern "C" int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream) {
+    BGW_TRY(bgw_pair_desc_check(d));
+    if (!h || !M) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    // complex copies of the real coefficients and the complex M in the second buffer
+    const long long nvw = (long long)d->nk * d->nv * d->ngw, ncw = (long long)d->nk * d->nc * d->ngw;
+    const long long nm = (long long)d->nk * d->nv * d->nc * d->ng;
+    auto al256 = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t off_cc = al256(sizeof(double2) * nvw), off_m = off_cc + al256(sizeof(double2) * ncw);
+    const size_t need = off_m + al256(sizeof(double2) * nm);
+    if (h->aux.bytes < need) {
+        if (need > env_limit()) return fail(BGW_ERR_NOMEM, "real-flavor staging exceeds BGW_WORKSPACE_LIMIT");
+        BGW_HIP(hipStreamSynchronize(st));
+        if (h->aux.p) BGW_HIP(hipFree(h->aux.p));
+        h->aux.p = nullptr;
+        h->aux.bytes = 0;
+        if (hipMalloc(&h->aux.p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(BGW_ERR_NOMEM, "real-flavor staging allocation failed (" + std::to_string(need) + " bytes)");
+        }
+        h->aux.bytes = need;
+    }
+    char *a = (char *)h->aux.p;
+    BGW_TRY(launch_real_to_complex(d->cv, nvw, (double2 *)a, st));
+    BGW_TRY(launch_real_to_complex(d->cc, ncw, (double2 *)(a + off_cc), st));
+    bgw_pair_desc dc = *d;
+    dc.cv = (const double *)a;
+    dc.cc = (const double *)(a + off_cc);
+    BGW_TRY(bgw_pair_density(h, &dc, (double *)(a + off_m), stream));
+    return launch_complex_real_part((const double2 *)(a + off_m), nm, M, st);
+}
+
 
 namespace bgw {
 // Matrices inverted per cooperative launch and the workspace the inversion needs.

@@ -1025,6 +1025,156 @@ extern "C" int bgw_sigma(bgw_handle_t h, const bgw_sigma_desc *d, void *stream) 
     return launch_gemm_finalize(L.g2.out, L.g2.ns, no * no, scale, (double2 *)d->sigma, d->accumulate, st);
 }
 
+namespace bgw {
+namespace {
+// Everything one real-flavor chi0 call launches: weights, the persistent real
+// rank-K update over every (vector, K split, upper tile) item, the finalize.
+struct RealChiPlan {
+    std::vector<WProb> wts;
+    std::vector<SyrkProb> sy;
+    std::vector<SyrkFin> fin;
+    std::vector<size_t> w_off, part_off;  // per vector ((size_t)-1: in place)
+    size_t off_tab = 0, ws_bytes = 0, tab_bytes = 0;
+    long long maxK = 0, nitems = 0;
+    int maxng = 0, grid = 0;
+};
+
+int check_chi_real(const bgw_chi_desc *d) {
+    BGW_TRY(check_chi_desc(d));
+    if (d->precision != BGW_FP64) return fail(BGW_ERR_UNSUPPORTED, "real flavor: FP64 only");
+    if (d->axis != BGW_AXIS_IMAG) return fail(BGW_ERR_UNSUPPORTED, "real flavor: imaginary axis only");
+    if (d->use_graph) return fail(BGW_ERR_UNSUPPORTED, "real flavor: no graph capture");
+    return BGW_OK;
+}
+
+void make_real_plan(const bgw_chi_desc *d, RealChiPlan &P) {
+    constexpr int RT = kSyrkTile, RKC = kSyrkK;
+    const int nvec = d->nq * d->nw;
+    size_t off = 0;
+    long long total_tiles = 0;
+    for (int iq = 0; iq < d->nq; ++iq) {
+        const bgw_chi_q &q = d->q[iq];
+        P.maxK = std::max(P.maxK, q_pairs(q));
+        P.maxng = std::max(P.maxng, q.ng);
+        const long long nt = (q.ng + RT - 1) / RT;
+        total_tiles += nt * (nt + 1) / 2 * d->nw;
+        for (int iw = 0; iw < d->nw; ++iw) {
+            WProb wp;
+            wp.ev = q.ev;
+            wp.ec = q.ec;
+            wp.w = nullptr;
+            wp.omega_ha = d->omega[iw] / kHartreeEv;
+            wp.delta_ha = 0.0;
+            wp.nk = q.nk;
+            wp.nv = q.nv;
+            wp.nc = q.nc;
+            wp.kind = kWeightImag;
+            P.wts.push_back(wp);
+            P.w_off.push_back(off);
+            off += al256(sizeof(double) * q_pairs(q));
+        }
+    }
+    const long long slots = (long long)device_cus() * syrk_blocks_per_cu();
+    const long long ns = choose_splits(total_tiles, slots, 8, 64);
+    long long item0 = 0;
+    for (int v = 0; v < nvec; ++v) {
+        const int iq = v / d->nw, iw = v % d->nw;
+        const bgw_chi_q &q = d->q[iq];
+        const long long K = q_pairs(q);
+        long long nsp = std::min<long long>(ns, std::max<long long>(1, K / (8 * RKC)));
+        long long kper = (K + nsp - 1) / nsp;
+        kper = (kper + RKC - 1) / RKC * RKC;
+        nsp = (K + kper - 1) / kper;
+        const bool inplace = nsp == 1 && !d->accumulate;
+        SyrkProb sp;
+        std::memset(&sp, 0, sizeof(sp));
+        sp.M = q.M;
+        sp.K = K;
+        sp.kper = kper;
+        sp.ng = q.ng;
+        sp.nt = (q.ng + RT - 1) / RT;
+        sp.ns = (int)nsp;
+        sp.item0 = item0;
+        sp.nitems = ((long long)sp.nt * (sp.nt + 1) / 2 * nsp + 7) / 8 * 8;
+        item0 += sp.nitems;
+        SyrkFin f;
+        std::memset(&f, 0, sizeof(f));
+        f.chi = q.chi + (size_t)iw * q.ng * q.ng;
+        f.pf = q.prefactor;
+        f.ns = (int)nsp;
+        f.ng = q.ng;
+        f.accumulate = d->accumulate;
+        f.inplace = inplace ? 1 : 0;
+        if (inplace) {
+            P.part_off.push_back((size_t)-1);
+        } else {
+            P.part_off.push_back(off);
+            off += al256(sizeof(double) * (size_t)nsp * q.ng * q.ng);
+        }
+        P.sy.push_back(sp);
+        P.fin.push_back(f);
+    }
+    P.nitems = item0;
+    P.grid = (int)(slots / 8 * 8);
+    P.off_tab = off;
+    P.tab_bytes = al256(sizeof(SyrkProb) * P.sy.size()) + al256(sizeof(SyrkFin) * P.fin.size()) +
+                  al256(sizeof(WProb) * P.wts.size());
+    P.ws_bytes = off + P.tab_bytes + 256;
+}
+}  // namespace
+}  // namespace bgw
+
+extern "C" int bgw_chi0_real_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t *bytes) {
+    clear_error();
+    BGW_TRY(check_chi_real(d));
+    if (!h || !bytes) return fail(BGW_ERR_ARG, "null handle or output");
+    BGW_TRY(set_device(h));
+    RealChiPlan P;
+    make_real_plan(d, P);
+    *bytes = P.ws_bytes;
+    return BGW_OK;
+}
+
+extern "C" int bgw_chi0_real(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
+    clear_error();
+    BGW_TRY(check_chi_real(d));
+    if (!h) return fail(BGW_ERR_ARG, "null handle");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    RealChiPlan P;
+    make_real_plan(d, P);
+    BGW_TRY(ensure_ws(h, P.ws_bytes, st));
+    char *ws = (char *)h->ws.p;
+    for (size_t v = 0; v < P.sy.size(); ++v) {
+        double *w = (double *)(ws + P.w_off[v]);
+        P.wts[v].w = w;
+        P.sy[v].w = w;
+        double *part = P.part_off[v] == (size_t)-1 ? P.fin[v].chi : (double *)(ws + P.part_off[v]);
+        P.sy[v].out = part;
+        P.fin[v].part = part;
+    }
+    // device tables: copied from host memory, then the host copies may go
+    std::vector<char> host(P.tab_bytes, 0);
+    const size_t o_fin = al256(sizeof(SyrkProb) * P.sy.size());
+    const size_t o_w = o_fin + al256(sizeof(SyrkFin) * P.fin.size());
+    std::memcpy(host.data(), P.sy.data(), sizeof(SyrkProb) * P.sy.size());
+    std::memcpy(host.data() + o_fin, P.fin.data(), sizeof(SyrkFin) * P.fin.size());
+    std::memcpy(host.data() + o_w, P.wts.data(), sizeof(WProb) * P.wts.size());
+    char *tab = ws + P.off_tab;
+    BGW_HIP(hipMemcpyAsync(tab, host.data(), P.tab_bytes, hipMemcpyHostToDevice, st));
+    BGW_HIP(hipStreamSynchronize(st));
+    {
+        Timed tm(h, BGW_KERNEL_WEIGHTS, st);
+        BGW_TRY(launch_weights_batch((const WProb *)(tab + o_w), (int)P.wts.size(), P.maxK, st));
+    }
+    {
+        Timed tm(h, BGW_KERNEL_HERK, st);
+        BGW_TRY(launch_syrk_batch((const SyrkProb *)tab, (int)P.sy.size(), P.nitems, P.grid, st));
+    }
+    Timed tm(h, BGW_KERNEL_FINALIZE, st);
+    return launch_syrk_finalize((const SyrkFin *)(tab + o_fin), (int)P.fin.size(), P.maxng, st);
+}
+
 extern "C" int bgw_autotune(bgw_handle_t h, const bgw_chi_desc *d, void *stream) {
     clear_error();
     BGW_TRY(check_chi_desc(d));

@@ -160,6 +160,26 @@ struct GemmProb {
     int m, n, ntr, ntc, ns, pad;
 };
 
+// Real flavor: one real rank-K update problem (one weight vector) and its
+// output matrix, as HerkProb / FinProb for real M and chi.  Output tiles are
+// kSyrkTile square; the contraction advances kSyrkK pairs per LDS stage.
+constexpr int kSyrkTile = 128;
+constexpr int kSyrkK = 16;
+struct SyrkProb {
+    const double *M;   // [K][ng] real
+    const double *w;   // [K]
+    double *out;       // [ns][ng][ng] raw upper-tile sums (or chi itself, ns == 1, in place)
+    long long K, kper, item0, nitems;
+    int ng, nt, ns, pad;
+};
+
+struct SyrkFin {
+    const double *part;  // [ns][ng][ng]
+    double *chi;         // [ng][ng] output
+    double pf;
+    int ns, ng, accumulate, inplace;
+};
+
 // One output matrix of a chi0 call: chi = pf * (A + i B) where A (and, on
 // the real frequency axis, B) are the Hermitian chi sums of one weight
 // vector each, held as raw upper-triangle sums.

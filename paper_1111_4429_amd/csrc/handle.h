@@ -37,6 +37,7 @@ void chi_state_free(ChiState *);
 struct bgw_handle_s {
     int device = 0;
     bgw::DevBuf ws;
+    bgw::DevBuf aux;  // real flavor: complex copies of real coefficients and M
     std::map<std::string, std::unique_ptr<bgw::FFTPlan>> plans;
     bgw::ChiState *chi = nullptr;
     bool capturing = false;  // a chi0 call is being captured into a HIP graph
@@ -104,6 +105,12 @@ int launch_finalize_batch(const FinProb *probs, int nprob, int maxng, hipStream_
 int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, double2 *MT, hipStream_t,
                            int batches = 1);
 int launch_gemm_phq(const GemmProb &G, int tile, hipStream_t);
+// ---- real flavor (real.hip)
+int launch_real_to_complex(const double *src, long long n, double2 *dst, hipStream_t);
+int launch_complex_real_part(const double2 *src, long long n, double *dst, hipStream_t);
+int launch_syrk_batch(const SyrkProb *probs, int nprob, long long nitems, int grid, hipStream_t);
+int syrk_blocks_per_cu();
+int launch_syrk_finalize(const SyrkFin *probs, int nprob, int maxng, hipStream_t);
 int launch_sigma_weights(const double *v, int ng, int ninner, double *w, hipStream_t);
 int launch_sigma_wt(const double2 *einv, const double *v, int ng, int ch, double2 *WT, hipStream_t);
 int launch_sigma_regroup(const double2 *B, int ng, int ninner, int nouter, double2 *B2, hipStream_t);

@@ -60,6 +60,7 @@ class Workload:
     nq: int = 1
     ng_range: Optional[tuple] = None  # uneven q batch: Ng_q ~ U{lo..hi}
     precision: str = "fp64"
+    flavor: str = "complex"  # "real": real coefficients (inversion + time-reversal symmetry)
 
     @property
     def npairs(self) -> int:
@@ -80,6 +81,9 @@ WORKLOADS: Dict[str, Workload] = {
     "bse-kx-48": Workload("bse-kx-48", n=48, ng=1500, ngw=1500, nv=4, nc=64, nk=64),
     # static self-energy of the silicon-like cell: 404 inner states (4 occupied), 64 outer states, one q
     "sigma-48": Workload("sigma-48", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=1),
+    # the silicon-like workload in the real flavor (real coefficients)
+    "silicon-like-48-real": Workload("silicon-like-48-real", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=64,
+                                     flavor="real"),
 }
 
 
@@ -106,8 +110,10 @@ def _envelope(g: np.ndarray) -> np.ndarray:
     return np.sqrt(np.exp(-mm / 8.0) / 2.0)
 
 
-def _draw_coeffs(rng: np.random.Generator, shape: Sequence[int], g: np.ndarray) -> np.ndarray:
+def _draw_coeffs(rng: np.random.Generator, shape: Sequence[int], g: np.ndarray, real: bool = False) -> np.ndarray:
     z = rng.standard_normal(tuple(shape) + (g.shape[0], 2))
+    if real:  # the same variance per coefficient in one real component
+        return z[..., 0] * np.sqrt(2.0) * _envelope(g)
     c = (z[..., 0] + 1j * z[..., 1]) * _envelope(g)
     return c
 
@@ -158,13 +164,15 @@ def make_system(wl: Workload, seed: int = 0, q_subset: Optional[Sequence[int]] =
     rng = np.random.default_rng(seed)
     gw = gvector_list(wl.ngw)
     nb = wl.nv + wl.nc
-    c = _draw_coeffs(rng, (wl.nk, nb), gw)
-    xi = _draw_coeffs(rng, (wl.nk, wl.nv), gw)
+    real = wl.flavor == "real"
+    c = _draw_coeffs(rng, (wl.nk, nb), gw, real)
+    xi = _draw_coeffs(rng, (wl.nk, wl.nv), gw, real)
     ev = np.sort(rng.uniform(-10.0, 0.0, size=(wl.nk, wl.nv)), axis=1)
     ec = np.sort(rng.uniform(1.0, 20.0, size=(wl.nk, wl.nc)), axis=1)
 
-    cv0 = np.empty((wl.nk, wl.nv, wl.ngw), dtype=np.complex128)
-    cc = np.empty((wl.nk, wl.nc, wl.ngw), dtype=np.complex128)
+    ctype = np.float64 if real else np.complex128
+    cv0 = np.empty((wl.nk, wl.nv, wl.ngw), dtype=ctype)
+    cc = np.empty((wl.nk, wl.nc, wl.ngw), dtype=ctype)
     qabs = float(np.linalg.norm(q0))
     for k in range(wl.nk):
         ortho = orthonormalise(c[k])
@@ -191,7 +199,7 @@ def make_system(wl: Workload, seed: int = 0, q_subset: Optional[Sequence[int]] =
                 qs.append(dict(q=qvec[0].copy(), ng=ng, ge=gvector_list(ng), cv=cv0, ev=ev.copy(), iq=0))
                 continue
             rq = np.random.default_rng([seed, iq])
-            cq = _draw_coeffs(rq, (wl.nk, wl.nv), gw)
+            cq = _draw_coeffs(rq, (wl.nk, wl.nv), gw, real)
             cvq = np.stack([orthonormalise(cq[k]) for k in range(wl.nk)])
             evq = np.sort(rq.uniform(-10.0, 0.0, size=(wl.nk, wl.nv)), axis=1)
             qs.append(dict(q=qvec[iq].copy(), ng=ng, ge=gvector_list(ng), cv=cvq, ev=evq, iq=iq))
@@ -217,9 +225,9 @@ def uneven_q_sizes(wl: Workload, seed: int = 0) -> np.ndarray:
 
 
 def small_system(n: int, ngw: int, ng: int, nv: int, nc: int, nk: int = 1, seed: int = 0,
-                 q=Q0_CRYSTAL, nw: int = 1, freq: str = "static") -> dict:
+                 q=Q0_CRYSTAL, nw: int = 1, freq: str = "static", flavor: str = "complex") -> dict:
     """A system of arbitrary (small) size drawn by the same recipe."""
-    wl = Workload("custom", n=n, ng=ng, ngw=ngw, nv=nv, nc=nc, nk=nk, nw=nw, freq=freq)
+    wl = Workload("custom", n=n, ng=ng, ngw=ngw, nv=nv, nc=nc, nk=nk, nw=nw, freq=freq, flavor=flavor)
     return make_system(wl, seed, q0=q)
 
 

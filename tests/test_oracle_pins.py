@@ -624,3 +624,23 @@ def test_sigma_bare_exchange_closed_form():
     x = oracle.sigma("x", M, v, 0.5, head=0)
     want = np.diag([0.0 if g == 0 else -0.5 * v[g] for g in gsel]).astype(np.complex128)
     assert np.array_equal(x, want)
+
+
+# ---------------------------------------------------------------- real flavor
+
+
+def test_real_flavor_pair_density_and_chi_are_real():
+    """Real coefficients (inversion and time-reversal symmetry): the matrix
+    elements are exactly real and chi is real symmetric, so the real flavor's
+    real M and real rank-K update compute the same numbers as the complex
+    definition."""
+    s = synth.small_system(n=16, ngw=200, ng=90, nv=3, nc=7, nk=2, seed=9, flavor="real")
+    q = s["qs"][0]
+    assert s["cc"].dtype == np.float64 and q["cv"].dtype == np.float64
+    M = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    assert np.all(M.imag == 0.0) and np.abs(M.real).max() > 0.1
+    w = oracle.weights(q["ev"], s["ec"], [0.0, 3.0])
+    chi = oracle.chi(M, w, 0.5)
+    assert np.all(chi.imag == 0.0)
+    asym = np.abs(chi.real - np.transpose(chi.real, (0, 2, 1))).max()
+    assert asym <= 1e-14 * np.abs(chi.real).max()
