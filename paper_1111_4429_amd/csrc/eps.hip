@@ -6,17 +6,24 @@
 // the same pivot sequence as LU with partial pivoting (largest |Re|+|Im| in
 // the current column among the rows not yet pivoted, first index on ties),
 // costs the same 8 n^3 real flops as getrf+getri, and puts nearly all of
-// them into one rank-nb update per panel (an FP64 MFMA GEMM).
+// them into rank-nbo updates (FP64 MFMA GEMMs).
 //
-// Per panel of nb columns [k, k+nb):
-//   k_gje_panel      cooperative: R workgroups per matrix each hold a block of
-//                    the panel's rows in LDS; per column one grid barrier
-//                    exchanges the pivot candidates, then every workgroup
-//                    swaps/scales/eliminates its rows (all rows: Gauss-Jordan).
-//                    The panel ends up holding the elimination transform.
-//   k_gje_swap_save  applies the panel's row swaps to the other columns, saves
-//                    their panel rows and zeroes them.
-//   k_gje_update     A[:, other] += P * Rsaved  (complex, FP64 MFMA).
+// Columns are taken in outer blocks of nbo (64 or 128) columns, each
+// factored as panels of nb (16 or 32) columns [ks, ks+nb):
+//   k_gje_panel*     the panel's column steps (pivot search, interchange,
+//                    elimination of every row: Gauss-Jordan) on its nb
+//                    columns; the panel ends up holding its elimination
+//                    transform.  One workgroup per matrix, or cooperative:
+//                    R workgroups each holding a block of rows, one grid
+//                    barrier per column.
+//   k_gje_swap_save  applies the panel's row interchanges to the other
+//                    columns of the outer block, saves their panel rows and
+//                    zeroes them;
+//   k_gje_update     A[:, those columns] += P * Rsaved  (complex, FP64 MFMA).
+// When the outer block is done its columns hold the transform of all its nbo
+// steps (the same numbers an nbo-wide panel would give), and the columns
+// outside it take all its interchanges and one rank-nbo update: the matrix
+// streams through HBM once per nbo columns instead of once per panel.
 // At the end the row interchanges are undone as column interchanges in
 // reverse order (k_gje_colperm).
 //
@@ -425,28 +432,39 @@ __global__ __launch_bounds__(256) void k_gje_panel_reg(double2 *__restrict__ A, 
     }
 }
 
-// For every column outside the panel: apply the panel's row interchanges in
-// order, copy the panel rows to Rs [nb][n - nb] and zero them in A.
-__global__ __launch_bounds__(64) void k_gje_swap_save(double2 *__restrict__ A, int n, int k, int nb,
+// The columns an update touches: [lo, hi) without [ex0, ex1), numbered
+// cp = 0 .. m-1 in increasing order.
+struct GjeCols {
+    int lo, hi, ex0, ex1;
+    __host__ __device__ int count() const { return (hi - lo) - (ex1 - ex0); }
+    __device__ int col(int cp) const {
+        const int c = lo + cp;
+        return c < ex0 ? c : c + (ex1 - ex0);
+    }
+};
+
+// For every column of cs: apply the interchanges ipiv[r0 .. r0+nbr) in order,
+// copy rows r0 .. r0+nbr-1 to Rs [nbr][m] and zero them in A.
+__global__ __launch_bounds__(64) void k_gje_swap_save(double2 *__restrict__ A, int n, int r0, int nbr, GjeCols cs,
                                                       const int *__restrict__ ipiv, double2 *__restrict__ Rs) {
     const int mat = blockIdx.y;
     double2 *Am = A + (size_t)mat * n * n;
     const int *ip = ipiv + (size_t)mat * n;
-    double2 *R = Rs + (size_t)mat * nb * (n - nb);
-    const int m = n - nb;
+    const int m = cs.count();
+    double2 *R = Rs + (size_t)mat * nbr * m;
     for (int cp = blockIdx.x * blockDim.x + threadIdx.x; cp < m; cp += gridDim.x * blockDim.x) {
-        const int c = cp < k ? cp : cp + nb;
-        for (int j = 0; j < nb; ++j) {
-            const int p = ip[k + j];
-            if (p > k + j && p < n) {
-                const double2 t = Am[(size_t)(k + j) * n + c];
-                Am[(size_t)(k + j) * n + c] = Am[(size_t)p * n + c];
+        const int c = cs.col(cp);
+        for (int j = 0; j < nbr; ++j) {
+            const int p = ip[r0 + j];
+            if (p > r0 + j && p < n) {
+                const double2 t = Am[(size_t)(r0 + j) * n + c];
+                Am[(size_t)(r0 + j) * n + c] = Am[(size_t)p * n + c];
                 Am[(size_t)p * n + c] = t;
             }
         }
-        for (int j = 0; j < nb; ++j) {
-            R[(size_t)j * m + cp] = Am[(size_t)(k + j) * n + c];
-            Am[(size_t)(k + j) * n + c] = make_double2(0.0, 0.0);
+        for (int j = 0; j < nbr; ++j) {
+            R[(size_t)j * m + cp] = Am[(size_t)(r0 + j) * n + c];
+            Am[(size_t)(r0 + j) * n + c] = make_double2(0.0, 0.0);
         }
     }
 }
@@ -456,18 +474,19 @@ constexpr int UT = 64;            // update tile (rows and cols)
 constexpr int ULD = UT + 4;       // padded LDS row
 }  // namespace
 
-// A[:, other] += P * R with P = A[:, k:k+nb] (n x nb) and R = Rs (nb x (n-nb)),
+// A[:, cs] += P * R with P = A[:, r0:r0+nbr] (n x nbr) and R = Rs (nbr x m),
 // complex, as two real products over the interleaved index kk = 2j + part:
 //   Re += sum_kk P'[i][kk] Bre[kk][c],  Bre[2j] = Re R, Bre[2j+1] = -Im R
 //   Im += sum_kk P'[i][kk] Bim[kk][c],  Bim[2j] = Im R, Bim[2j+1] =  Re R
-__global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int n, int k, int nb,
+// The panel is staged kPanelMax columns at a time.
+__global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, int n, int r0, int nbr, GjeCols cs,
                                                     const double2 *__restrict__ Rs) {
     __shared__ double Ps[2 * kPanelMax][ULD];
     __shared__ double Rsh[2 * kPanelMax][ULD];
     const int mat = blockIdx.z;
     double2 *Am = A + (size_t)mat * n * n;
-    const int m = n - nb;
-    const double2 *R = Rs + (size_t)mat * nb * m;
+    const int m = cs.count();
+    const double2 *R = Rs + (size_t)mat * nbr * m;
     const int I0 = blockIdx.x * UT, C0 = blockIdx.y * UT;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
@@ -484,32 +503,9 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
                 const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
                 const int cp = C0 + wc * 32 + 16 * b + li;
                 old[a][b][r] = make_double2(0.0, 0.0);
-                if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + (cp < k ? cp : cp + nb)];
+                if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + cs.col(cp)];
             }
 
-    // P and R tiles: all loads issued before the first LDS store, so their
-    // latencies overlap
-    constexpr int SIT = UT * kPanelMax / 256;
-    double2 pv[SIT], rw[SIT];
-#pragma unroll
-    for (int it = 0; it < SIT; ++it) {
-        const int e = tid + 256 * it;
-        const int i = e / kPanelMax, j = e % kPanelMax;  // P tile: row i, panel col j
-        pv[it] = (I0 + i < n && j < nb) ? Am[(size_t)(I0 + i) * n + k + j] : make_double2(0.0, 0.0);
-        const int jr = e / UT, c = e % UT;  // R tile: panel row jr, col c
-        rw[it] = (jr < nb && C0 + c < m) ? R[(size_t)jr * m + C0 + c] : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int it = 0; it < SIT; ++it) {
-        const int e = tid + 256 * it;
-        const int i = e / kPanelMax, j = e % kPanelMax;
-        Ps[2 * j][i] = pv[it].x;
-        Ps[2 * j + 1][i] = pv[it].y;
-        const int jr = e / UT, c = e % UT;
-        Rsh[2 * jr][c] = rw[it].x;
-        Rsh[2 * jr + 1][c] = rw[it].y;
-    }
-    __syncthreads();
     double4_t cre[2][2], cim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -518,28 +514,55 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
             cre[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
             cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
         }
-    const int ksteps = (2 * nb + 3) / 4;
     const double rsign = (lk & 1) ? -1.0 : 1.0;  // kr = 4 s + lk has the parity of lk
-#pragma unroll 4
-    for (int s = 0; s < ksteps; ++s) {
-        const int kr = 4 * s + lk;
-        double av[2], bre[2], bim[2];
+    for (int j0 = 0; j0 < nbr; j0 += kPanelMax) {
+        const int nbc = min(kPanelMax, nbr - j0);
+        if (j0) __syncthreads();  // the previous chunk's LDS reads are done
+        // P and R tiles of this chunk: all loads issued before the first LDS
+        // store, so their latencies overlap
+        constexpr int SIT = UT * kPanelMax / 256;
+        double2 pv[SIT], rw[SIT];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = Ps[kr][wr * 32 + 16 * a + li];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int col = wc * 32 + 16 * b + li;
-            // odd rows (imaginary parts): Bre = -Im R, Bim = Re R; even: Re R, Im R
-            bre[b] = rsign * Rsh[kr][col];
-            bim[b] = Rsh[kr ^ 1][col];
+        for (int it = 0; it < SIT; ++it) {
+            const int e = tid + 256 * it;
+            const int i = e / kPanelMax, j = e % kPanelMax;  // P tile: row i, panel col j
+            pv[it] = (I0 + i < n && j < nbc) ? Am[(size_t)(I0 + i) * n + r0 + j0 + j] : make_double2(0.0, 0.0);
+            const int jr = e / UT, c = e % UT;  // R tile: panel row jr, col c
+            rw[it] = (jr < nbc && C0 + c < m) ? R[(size_t)(j0 + jr) * m + C0 + c] : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int it = 0; it < SIT; ++it) {
+            const int e = tid + 256 * it;
+            const int i = e / kPanelMax, j = e % kPanelMax;
+            Ps[2 * j][i] = pv[it].x;
+            Ps[2 * j + 1][i] = pv[it].y;
+            const int jr = e / UT, c = e % UT;
+            Rsh[2 * jr][c] = rw[it].x;
+            Rsh[2 * jr + 1][c] = rw[it].y;
+        }
+        __syncthreads();
+        const int ksteps = (2 * nbc + 3) / 4;
+#pragma unroll 4
+        for (int s = 0; s < ksteps; ++s) {
+            const int kr = 4 * s + lk;
+            double av[2], bre[2], bim[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = Ps[kr][wr * 32 + 16 * a + li];
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
-                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
+                const int col = wc * 32 + 16 * b + li;
+                // odd rows (imaginary parts): Bre = -Im R, Bim = Re R; even: Re R, Im R
+                bre[b] = rsign * Rsh[kr][col];
+                bim[b] = Rsh[kr ^ 1][col];
             }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
+                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
+                }
+        }
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -549,11 +572,9 @@ __global__ __launch_bounds__(256) void k_gje_update(double2 *__restrict__ A, int
             for (int r = 0; r < 4; ++r) {
                 const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
                 const int cp = C0 + wc * 32 + 16 * b + li;
-                if (i < n && cp < m) {
-                    const int c = cp < k ? cp : cp + nb;
-                    Am[(size_t)i * n + c] =
+                if (i < n && cp < m)
+                    Am[(size_t)i * n + cs.col(cp)] =
                         make_double2(old[a][b][r].x + cre[a][b][r], old[a][b][r].y + cim[a][b][r]);
-                }
             }
 }
 
@@ -889,10 +910,28 @@ size_t gje_scratch_bytes(int nmat, int R) {
 
 static char *align256(char *p) { return (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
 
+// Width of the outer blocks: panels run kWgNb or kPanelMax columns at a time
+// and update only the other columns of their outer block; the rest of the
+// matrix takes one rank-(outer width) update per outer block.
+static int gje_outer_nb(int n) { return n >= 3000 ? 4 * kPanelMax : 2 * kPanelMax; }
+
+// Row interchanges and rank-nbr update of the panel [r0, r0 + nbr) applied to
+// the columns cs: A[:, cs] = swapped, panel rows saved and zeroed, += P Rs.
+static int gje_apply(double2 *A, int n, int nmat, int r0, int nbr, GjeCols cs, const int *ipiv, double2 *Rs,
+                     hipStream_t st) {
+    const int m = cs.count();
+    if (m <= 0) return BGW_OK;
+    hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 63) / 64, nmat), dim3(64), 0, st, A, n, r0, nbr, cs, ipiv, Rs);
+    hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n, r0,
+                       nbr, cs, (const double2 *)Rs);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
 // In-place inversion of `nmat` matrices A[nmat][n][n].  ws: device workspace of
 // at least gje_workspace_bytes(n, nmat, R) bytes.  info: [nmat], zeroed here.
 size_t gje_workspace_bytes(int n, int nmat, int R) {
-    return gje_scratch_bytes(nmat, R) + sizeof(double2) * (size_t)nmat * kPanelMax * n + 256 +
+    return gje_scratch_bytes(nmat, R) + sizeof(double2) * (size_t)nmat * gje_outer_nb(n) * n + 256 +
            sizeof(int) * (size_t)nmat * n * 2 + 512;
 }
 
@@ -920,17 +959,16 @@ static int launch_gje_invert_wg(double2 *A, int n, int nmat, int *ipiv, int *inf
                      : rows == 2 ? (const void *)k_gje_panel_wg<2>
                                  : (const void *)k_gje_panel_wg<3>;
     BGW_HIP(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kWgStageBytes));
-    for (int k = 0; k < n; k += kWgNb) {
-        const int nb = std::min(kWgNb, n - k);
-        void *args[] = {&A, (void *)&n, &k, (void *)&nb, &ipiv, &info};
-        BGW_HIP(hipLaunchKernel(kern, dim3(nmat), dim3(kWgThreads), args, kWgStageBytes, st));
-        const int m = n - nb;
-        if (m > 0) {
-            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 63) / 64, nmat), dim3(64), 0, st, A, n, k, nb, ipiv, Rs);
-            hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n,
-                               k, nb, Rs);
+    const int nbo = gje_outer_nb(n);
+    for (int k = 0; k < n; k += nbo) {
+        const int ke = std::min(n, k + nbo);
+        for (int ks = k; ks < ke; ks += kWgNb) {
+            const int nb = std::min(kWgNb, ke - ks);
+            void *args[] = {&A, (void *)&n, &ks, (void *)&nb, &ipiv, &info};
+            BGW_HIP(hipLaunchKernel(kern, dim3(nmat), dim3(kWgThreads), args, kWgStageBytes, st));
+            BGW_TRY(gje_apply(A, n, nmat, ks, nb, GjeCols{k, ke, ks, ks + nb}, ipiv, Rs, st));
         }
-        BGW_HIP(hipGetLastError());
+        BGW_TRY(gje_apply(A, n, nmat, k, ke - k, GjeCols{0, n, k, ke}, ipiv, Rs, st));
     }
     return BGW_OK;
 }
@@ -949,7 +987,7 @@ int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipi
     sc.cand_rows = (double2 *)p; p = align256(p + sizeof(double2) * nmat * 2 * R * kPanelMax);
     sc.rowbuf = (double2 *)p; p = align256(p + sizeof(double2) * nmat * 2 * kPanelMax);
     sc.bar = (unsigned int *)p; p = align256(p + sizeof(unsigned int) * nmat);
-    double2 *Rs = (double2 *)p; p = align256(p + sizeof(double2) * (size_t)nmat * kPanelMax * n);
+    double2 *Rs = (double2 *)p; p = align256(p + sizeof(double2) * (size_t)nmat * gje_outer_nb(n) * n);
     int *ipiv = ipiv_ws;
     int *idx = ipiv + (size_t)nmat * n;
 
@@ -974,24 +1012,24 @@ static int launch_gje_invert_coop(double2 *A, int n, int nmat, int *info, GjeScr
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_panel<0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     const size_t rlds_panel = gje_panel_reg_lds(R);
     unsigned int bar_done = 0;
-    for (int k = 0; k < n; k += kPanelMax) {
-        const int nb = std::min(kPanelMax, n - k);
-        void *args[] = {&A, (void *)&n, &k, (void *)&nb, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
-        if (nb == kPanelMax) {
-            void *rargs[] = {&A, (void *)&n, &k, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
-            BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel_reg, dim3(R * nmat), dim3(256), rargs,
-                                               rlds_panel, st));
-        } else {
-            BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel<0>, dim3(R * nmat), dim3(256), args, lds, st));
+    const int nbo = gje_outer_nb(n);
+    for (int k = 0; k < n; k += nbo) {
+        const int ke = std::min(n, k + nbo);
+        for (int ks = k; ks < ke; ks += kPanelMax) {
+            const int nb = std::min(kPanelMax, ke - ks);
+            void *args[] = {&A, (void *)&n, &ks, (void *)&nb, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
+            if (nb == kPanelMax) {
+                void *rargs[] = {&A, (void *)&n, &ks, (void *)&rows, (void *)&R, &ipiv, &info, &sc, &bar_done};
+                BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel_reg, dim3(R * nmat), dim3(256), rargs,
+                                                   rlds_panel, st));
+            } else {
+                BGW_HIP(hipLaunchCooperativeKernel((const void *)k_gje_panel<0>, dim3(R * nmat), dim3(256), args, lds,
+                                                   st));
+            }
+            bar_done += nb;
+            BGW_TRY(gje_apply(A, n, nmat, ks, nb, GjeCols{k, ke, ks, ks + nb}, ipiv, Rs, st));
         }
-        bar_done += nb;
-        const int m = n - nb;
-        if (m > 0) {
-            hipLaunchKernelGGL(k_gje_swap_save, dim3((m + 63) / 64, nmat), dim3(64), 0, st, A, n, k, nb, ipiv, Rs);
-            hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n,
-                               k, nb, Rs);
-            BGW_HIP(hipGetLastError());
-        }
+        BGW_TRY(gje_apply(A, n, nmat, k, ke - k, GjeCols{0, n, k, ke}, ipiv, Rs, st));
     }
     return BGW_OK;
 }
