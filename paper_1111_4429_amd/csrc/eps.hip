@@ -478,7 +478,8 @@ constexpr int ULD = UT + 4;       // padded LDS row
 // complex, as two real products over the interleaved index kk = 2j + part:
 //   Re += sum_kk P'[i][kk] Bre[kk][c],  Bre[2j] = Re R, Bre[2j+1] = -Im R
 //   Im += sum_kk P'[i][kk] Bim[kk][c],  Bim[2j] = Im R, Bim[2j+1] =  Re R
-// The panel is staged kPanelMax columns at a time.
+// The panel is staged kPanelMax columns at a time, the next chunk loaded
+// into registers while the current one feeds the MFMAs.
 __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, int n, int r0, int nbr, GjeCols cs,
                                                     const double2 *__restrict__ Rs) {
     __shared__ double Ps[2 * kPanelMax][ULD];
@@ -491,21 +492,6 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1, li = lane & 15, lk = lane >> 4;
 
-    // this lane's elements of the output tile, fetched first so that their
-    // latency overlaps the staging of P and R
-    double2 old[2][2][4];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
-                const int cp = C0 + wc * 32 + 16 * b + li;
-                old[a][b][r] = make_double2(0.0, 0.0);
-                if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + cs.col(cp)];
-            }
-
     double4_t cre[2][2], cim[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -514,14 +500,13 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
             cre[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
             cim[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
         }
-    const double rsign = (lk & 1) ? -1.0 : 1.0;  // kr = 4 s + lk has the parity of lk
-    for (int j0 = 0; j0 < nbr; j0 += kPanelMax) {
+    // P and R tiles of one chunk of kPanelMax panel columns, loaded into
+    // registers one chunk ahead: the loads of chunk j0 + kPanelMax are issued
+    // before the MFMAs of chunk j0
+    constexpr int SIT = UT * kPanelMax / 256;
+    double2 pv[SIT], rw[SIT];
+    auto load_chunk = [&](int j0) {
         const int nbc = min(kPanelMax, nbr - j0);
-        if (j0) __syncthreads();  // the previous chunk's LDS reads are done
-        // P and R tiles of this chunk: all loads issued before the first LDS
-        // store, so their latencies overlap
-        constexpr int SIT = UT * kPanelMax / 256;
-        double2 pv[SIT], rw[SIT];
 #pragma unroll
         for (int it = 0; it < SIT; ++it) {
             const int e = tid + 256 * it;
@@ -530,6 +515,24 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
             const int jr = e / UT, c = e % UT;  // R tile: panel row jr, col c
             rw[it] = (jr < nbc && C0 + c < m) ? R[(size_t)(j0 + jr) * m + C0 + c] : make_double2(0.0, 0.0);
         }
+    };
+    // this lane's elements of the output tile, fetched during the last chunk
+    double2 old[2][2][4];
+    auto load_old = [&]() {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = I0 + wr * 32 + 16 * a + 4 * r + lk;
+                    const int cp = C0 + wc * 32 + 16 * b + li;
+                    old[a][b][r] = make_double2(0.0, 0.0);
+                    if (i < n && cp < m) old[a][b][r] = Am[(size_t)i * n + cs.col(cp)];
+                }
+    };
+    const double rsign = (lk & 1) ? -1.0 : 1.0;  // kr = 4 s + lk has the parity of lk
+    auto stage_chunk = [&]() {
 #pragma unroll
         for (int it = 0; it < SIT; ++it) {
             const int e = tid + 256 * it;
@@ -540,7 +543,8 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
             Rsh[2 * jr][c] = rw[it].x;
             Rsh[2 * jr + 1][c] = rw[it].y;
         }
-        __syncthreads();
+    };
+    auto mfma_chunk = [&](int nbc) {
         const int ksteps = (2 * nbc + 3) / 4;
 #pragma unroll 4
         for (int s = 0; s < ksteps; ++s) {
@@ -563,7 +567,21 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
                     cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
                 }
         }
+    };
+    load_chunk(0);
+    int j0 = 0;
+    for (; j0 + kPanelMax < nbr; j0 += kPanelMax) {
+        stage_chunk();
+        __syncthreads();
+        load_chunk(j0 + kPanelMax);
+        mfma_chunk(kPanelMax);
+        __syncthreads();  // this chunk's LDS reads are done
     }
+    // the last chunk: the output tile's old values are fetched under its MFMAs
+    stage_chunk();
+    __syncthreads();
+    load_old();
+    mfma_chunk(nbr - j0);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
