@@ -51,7 +51,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="imag-freq-64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-pairs", type=int, default=6400)
+    ap.add_argument("--cpu-sample-pairs", type=int, default=6400,
+                    help="pairs of q0 the oracle baseline computes (0: every pair, end to end)")
     ap.add_argument("--split-reps", type=int, default=2)
     ap.add_argument("--split-omegas", type=int, default=4,
                     help="frequencies of the split-vs-FP64 comparison (evenly spread subset; 0 = all)")
@@ -102,8 +103,9 @@ def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
     K = s["nk"] * s["nv"] * s["nc"]
     ng = q["ng"]
     nw = len(s["omega"])
-    # keep the oracle's chi sample near 2e11 flops
-    pairs_sample = int(max(16, min(pairs_sample, K, 2e11 / (8.0 * ng * ng * nw))))
+    # keep the oracle's chi sample near 2e11 flops; pairs_sample <= 0: every pair (end to end)
+    full = pairs_sample <= 0
+    pairs_sample = K if full else int(max(16, min(pairs_sample, K, 2e11 / (8.0 * ng * ng * nw))))
     rng = np.random.default_rng(123)
     pairs = np.sort(rng.choice(K, size=pairs_sample, replace=False))
     t0 = time.perf_counter()
@@ -130,7 +132,8 @@ def cpu_baseline(s, pairs_sample: int, chi_flops_step: float):
         "unit": "TFLOP/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": (f"oracle on {pairs_sample} of {K} pairs of q0: M by convolution ({t_m:.2f} s) and chi over all "
+        "sample": ("end to end: " if full and nq == 1 and ni == ng else "") + (
+                   f"oracle on {pairs_sample} of {K} pairs of q0: M by convolution ({t_m:.2f} s) and chi over all "
                    f"{ng}x{ng} entries and {nw} frequencies ({t_c:.2f} s), extrapolated x{scale:.0f} and over "
                    f"{nq} q by Ng^2; inversions {t_i:.2f} s for q0"
                    + (f" (timed at {ni}x{ni}, scaled by Ng^3)" if ni != ng else "")
@@ -298,6 +301,8 @@ def bench_kx(args, wl):
         name, work, peak = "k_chi_split (Kx, BF16 MFMA, 10 x 4 K^2 Ng)", SPLIT_PRODUCTS * flops, BF16_PEAK_TFLOPS
     nl = launches.get(key, 1)
     avg = per_step[key] / nl
+    kx_tr = load_traffic(f"herk_{wl.name}", ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/common.h"])
+    kx_traffic = kx_tr["bytes_per_launch"] if (kx_tr is not None and precision == bgw.FP64) else None
     ach = work / nl / (avg * 1e-3) / 1e12
     kx_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize", "split_slice", "split_herk"))
     out = {
@@ -314,7 +319,7 @@ def bench_kx(args, wl):
         "stages": {"pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
                    "kx_ms": kx_ms, "kx_TFLOPs": flops / (kx_ms * 1e-3) / 1e12},
         "roofline": {"kernel": name, "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None, "algorithmic_per_launch": work / nl, "avg_launch_ms": avg,
+                     "frac": ach / peak, "traffic": kx_traffic, "algorithmic_per_launch": work / nl, "avg_launch_ms": avg,
                      "launches_per_step": nl},
         "split": None,
         "cpu_baseline": None,
@@ -416,6 +421,8 @@ def bench_sigma(args, wl, nouter=64):
     torch.cuda.synchronize()
     ch_ms = e0.elapsed_time(e1) / args.steps
     f_x = 4.0 * nouter * nouter * nocc * ng
+    # HBM bytes of one Coulomb-hole call (all its kernels) from the committed PMC record
+    ch_tr = load_traffic(f"sigma-ch_{wl.name}", ["paper_1111_4429_amd/csrc/chi.hip", "paper_1111_4429_amd/csrc/common.h"])
     f_w = lambda ni: 8.0 * ng * ng * ni * nouter + 8.0 * nouter * nouter * ni * ng
     flops = f_x + f_w(nocc) + f_w(ninner)
     out = {
@@ -431,7 +438,8 @@ def bench_sigma(args, wl, nouter=64):
         "stages": {"coulomb_hole_ms": ch_ms, "coulomb_hole_TFLOPs": f_w(ninner) / (ch_ms * 1e-3) / 1e12},
         "roofline": {"kernel": "k_gemm_phq (W M and the (i, G) contraction of the Coulomb hole)", "bound": "mfma",
                      "achieved": f_w(ninner) / (ch_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": f_w(ninner) / (ch_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": f_w(ninner) / (ch_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "traffic": None if ch_tr is None else ch_tr["bytes_per_launch"],
                      "algorithmic_per_launch": f_w(ninner), "avg_launch_ms": ch_ms, "launches_per_step": 1,
                      "note": "per bgw_sigma call of the Coulomb hole (its two products, regrouping and finalize)"},
         "cpu_baseline": None,
@@ -505,6 +513,7 @@ def bench_real(args, wl):
     per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
     launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
     flops = float(ng) * ng * K * nw
+    sy_tr = load_traffic(f"syrk_{wl.name}", ["paper_1111_4429_amd/csrc/real.hip", "paper_1111_4429_amd/csrc/common.h"])
     chi_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize"))
     syrk_ms = per_step["herk"] / launches["herk"]
     # the complex FP64 chi-sum of the same (real) M, cast to complex
@@ -543,7 +552,8 @@ def bench_real(args, wl):
                      "achieved": flops / launches["herk"] / (syrk_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s",
                      "frac": flops / launches["herk"] / (syrk_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                     "traffic": None, "algorithmic_per_launch": flops / launches["herk"], "avg_launch_ms": syrk_ms,
+                     "traffic": None if sy_tr is None else sy_tr["bytes_per_launch"],
+                     "algorithmic_per_launch": flops / launches["herk"], "avg_launch_ms": syrk_ms,
                      "launches_per_step": launches["herk"]},
         "kernel_share": {k: per_step[k] / ms_step for k in per_step},
         "cpu_baseline": None,
