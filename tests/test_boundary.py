@@ -151,3 +151,66 @@ def test_generator_is_deterministic():
     assert np.all(np.diff(mm) >= 0)
     e = a["ec"]
     assert np.all(np.diff(e, axis=1) >= 0) and e.min() >= 1 and e.max() <= 20
+
+
+def test_next_row_entry_points_validate_without_gpu():
+    """The self-energy, exchange-kernel and real-flavor entry points check their
+    descriptors (then the handle) on the host and return the documented codes."""
+    L = bgw.lib()
+    # self-energy: a valid bare-exchange descriptor, then one field wrong at a time
+    s = bgw.SigmaDesc()
+    s.M = s.v = s.sigma = 1
+    s.ninner, s.nouter, s.ng, s.kind, s.head, s.precision, s.prefactor = 2, 3, 10, bgw.SIGMA_X, 0, bgw.FP64, 1.0
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_ARG  # null handle
+    s.kind = 5
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_ARG  # unknown kind
+    s.kind, s.head = bgw.SIGMA_X, 10
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_ARG  # head out of range
+    s.head, s.kind, s.epsinv = -1, bgw.SIGMA_SX, None
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_ARG  # screened kinds need eps^-1
+    s.epsinv, s.precision = 1, bgw.SPLIT_BF16
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_UNSUPPORTED  # SX is FP64 only
+    s.precision, s.ng = bgw.FP64, 9000
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_UNSUPPORTED  # ng above 8192
+    # exchange kernel
+    k = bgw.KxDesc()
+    k.M = k.v = k.kx = 1
+    k.K, k.ng, k.head, k.prefactor, k.precision = 4, 10, 0, 1.0, bgw.FP64
+    assert L.bgw_bse_kx(None, ctypes.byref(k), None) == bgw.BGW_ERR_ARG  # null handle
+    k.head = 10
+    assert L.bgw_bse_kx(None, ctypes.byref(k), None) == bgw.BGW_ERR_ARG  # head out of range
+    k.head, k.precision = -1, 7
+    assert L.bgw_bse_kx(None, ctypes.byref(k), None) == bgw.BGW_ERR_ARG  # unknown precision
+    k.precision, k.K = bgw.FP64, 0
+    assert L.bgw_bse_kx(None, ctypes.byref(k), None) == bgw.BGW_ERR_UNSUPPORTED  # no pairs
+    # real flavor: FP64, imaginary axis, no graph capture
+    q = (bgw.ChiQ * 1)()
+    q[0].ng, q[0].nk, q[0].nv, q[0].nc = 10, 1, 1, 1
+    q[0].M = q[0].ev = q[0].ec = q[0].chi = 1
+    q[0].head, q[0].prefactor = 0, 1.0
+    om = (ctypes.c_double * 1)(0.0)
+    d = bgw.ChiDesc()
+    d.nq, d.q, d.nw, d.omega, d.precision = 1, q, 1, om, bgw.FP64
+    assert L.bgw_chi0_real(None, ctypes.byref(d), None) == bgw.BGW_ERR_ARG  # null handle
+    d.precision = bgw.SPLIT_BF16
+    assert L.bgw_chi0_real(None, ctypes.byref(d), None) == bgw.BGW_ERR_UNSUPPORTED
+    d.precision, d.axis, d.broadening = bgw.FP64, bgw.AXIS_RETARDED, 0.5
+    assert L.bgw_chi0_real(None, ctypes.byref(d), None) == bgw.BGW_ERR_UNSUPPORTED
+    d.axis, d.use_graph = bgw.AXIS_IMAG, 1
+    assert L.bgw_chi0_real(None, ctypes.byref(d), None) == bgw.BGW_ERR_UNSUPPORTED
+    gw = synth.gvector_list(27)
+    pd = bgw.make_pair_desc(8, gw, gw, nk=1, nv=1, nc=1)
+    assert L.bgw_pair_density_real(None, ctypes.byref(pd), None, None) == bgw.BGW_ERR_ARG
+
+
+def test_bench_refuses_several_gpus():
+    """One GPU only: --gpus above 1 ends with a message and a nonzero status."""
+    import json
+    import subprocess
+    import sys
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
