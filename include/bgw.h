@@ -44,7 +44,7 @@ extern "C" {
 #define BGW_ERR_SHAPE (-3)       /* duplicate G, component outside [-n/2, n/2), |q+G| = 0 */
 #define BGW_ERR_HIP (-4)         /* a HIP runtime call failed */
 #define BGW_ERR_NOMEM (-5)       /* workspace could not be allocated (or exceeds BGW_WORKSPACE_LIMIT) */
-#define BGW_ERR_UNSUPPORTED (-6) /* e.g. an FFT length that is not 2^a 3^b in [4, 128] */
+#define BGW_ERR_UNSUPPORTED (-6) /* e.g. an FFT grid length that is not 2^a 3^b in [4, 1024] */
 
 #define BGW_AXIS_IMAG 0          /* chi0 at imaginary frequencies i|omega| (omega = 0: static) */
 #define BGW_AXIS_RETARDED 1      /* chi0^r at real frequencies E >= 0 with broadening delta */
@@ -95,10 +95,12 @@ size_t bgw_workspace_bytes(bgw_handle_t h);
  * 128} (equal along y and z) when they fit in n, which have register-resident
  * kernels, else the least 2^a 3^b length per axis.  Setting the environment
  * variable BGW_FFT_BOX=full makes the library use n itself;
- * bgw_pair_transform_box reports the box.
+ * bgw_pair_transform_box reports the box.  The box must be at most 128 on
+ * every axis (BGW_ERR_UNSUPPORTED otherwise); the caller's grid itself may
+ * be up to 1024 per axis.
  * ---------------------------------------------------------------------- */
 typedef struct {
-    int n[3];          /* FFT grid; each n_i = 2^a 3^b with 4 <= n_i <= 128 */
+    int n[3];          /* FFT grid; each n_i = 2^a 3^b with 4 <= n_i <= 1024 */
     int ngw;           /* wavefunction sphere size */
     const int *gw;     /* HOST int32 [ngw][3] Miller indices of the coefficients */
     int ng;            /* dielectric sphere size (columns of M) */

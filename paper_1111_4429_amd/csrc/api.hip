@@ -106,13 +106,20 @@ static int check_glist(const int *g, int count, const int n[3], const char *what
 
 using namespace bgw;
 
+namespace bgw {
+static void transform_box(const bgw_pair_desc *d, int box[3]);
+// Largest caller grid per axis; the transform itself runs on the smallest
+// alias-free box, which must fit the transform kernels (kMaxFFT per axis).
+constexpr int kMaxGrid = 1024;
+}  // namespace bgw
+
 extern "C" int bgw_pair_desc_check(const bgw_pair_desc *d) {
     clear_error();
     if (!d) return fail(BGW_ERR_ARG, "null descriptor");
     for (int i = 0; i < 3; ++i) {
         if (d->n[i] < 1) return fail(BGW_ERR_ARG, "FFT grid dimensions must be positive");
-        if (!is_2a3b(d->n[i]) || d->n[i] < 4 || d->n[i] > kMaxFFT)
-            return fail(BGW_ERR_UNSUPPORTED, "FFT grid dimensions must be 2^a 3^b in [4, 128]");
+        if (!is_2a3b(d->n[i]) || d->n[i] < 4 || d->n[i] > kMaxGrid)
+            return fail(BGW_ERR_UNSUPPORTED, "FFT grid dimensions must be 2^a 3^b in [4, 1024]");
     }
     if (d->ngw < 1 || d->ng < 1 || d->nk < 1 || d->nv < 1 || d->nc < 1)
         return fail(BGW_ERR_ARG, "ngw, ng, nk, nv, nc must be >= 1");
@@ -124,6 +131,11 @@ extern "C" int bgw_pair_desc_check(const bgw_pair_desc *d) {
     for (int i = 0; i < 3; ++i)
         if (d->n[i] <= 2 * mw[i] + me[i])
             return fail(BGW_ERR_ALIAS, "FFT grid too small: need n_i > 2 max|gw_i| + max|ge_i| on every axis");
+    int box[3];
+    transform_box(d, box);
+    for (int i = 0; i < 3; ++i)
+        if (box[i] > kMaxFFT)
+            return fail(BGW_ERR_UNSUPPORTED, "the alias-free transform box needs more than 128 points on an axis");
     return BGW_OK;
 }
 

@@ -46,7 +46,7 @@ def test_pair_desc_validation_codes():
     assert bgw.pair_desc_check((16, 16, 12), gw, ge) == bgw.BGW_ERR_ALIAS
     # unsupported grid lengths
     assert bgw.pair_desc_check(20, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
-    assert bgw.pair_desc_check(256, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
+    assert bgw.pair_desc_check(2048, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
     assert bgw.pair_desc_check((0, 16, 16), gw, ge) == bgw.BGW_ERR_ARG
     # duplicate G and out-of-range component
     dup = np.concatenate([ge[:10], ge[3:4]])
@@ -214,3 +214,21 @@ def test_bench_refuses_several_gpus():
     assert r.returncode != 0
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_large_grids_transform_on_the_small_box(monkeypatch):
+    """A caller grid above 128 is accepted while the alias-free box fits the
+    transform kernels (at most 128 per axis); the box does not depend on the
+    grid; a sphere whose box needs more, or the full-grid mode on such a grid,
+    is refused."""
+    gw = synth.gvector_list(300)
+    ge = synth.gvector_list(300)
+    assert bgw.pair_desc_check(256, gw, ge) == bgw.BGW_OK
+    assert bgw.pair_desc_check((192, 256, 1024), gw, ge) == bgw.BGW_OK
+    assert bgw.pair_transform_box(256, gw, ge) == bgw.pair_transform_box(16, gw, ge)
+    far = np.array([[0, 0, 0], [43, 0, 0]], dtype=np.int32)  # 2*43 + 43 + 1 = 130 points needed along x
+    assert bgw.pair_desc_check(256, far, far) == bgw.BGW_ERR_UNSUPPORTED
+    assert "128" in bgw.lib().bgw_last_error().decode()
+    monkeypatch.setenv("BGW_FFT_BOX", "full")
+    assert bgw.pair_desc_check(256, gw, ge) == bgw.BGW_ERR_UNSUPPORTED
+    assert bgw.pair_desc_check(64, gw, ge) == bgw.BGW_OK

@@ -477,3 +477,17 @@ def test_pipeline_bitwise_deterministic(torch_dev, handle, tiny):
     assert np.array_equal(M.cpu().numpy(), tiny["M"])
     assert np.array_equal(chi.cpu().numpy(), tiny["chi"])
     assert np.array_equal(einv.cpu().numpy(), tiny["einv"])
+
+
+def test_pair_density_large_caller_grid(torch_dev, handle):
+    """A 256^3 (and a non-cubic 192 x 256 x 1024) caller grid with small
+    spheres: the transform runs on the same small alias-free box, and M agrees
+    with the oracle's convolution as on the smallest grid."""
+    s = synth.small_system(n=16, ngw=300, ng=181, nv=3, nc=5, nk=2, seed=4)
+    q = s["qs"][0]
+    Mo = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"])
+    M16 = gpu_M(handle, torch_dev, s, n=16).cpu().numpy()
+    for n in (256, (192, 256, 1024)):
+        M = gpu_M(handle, torch_dev, s, n=n).cpu().numpy()
+        assert rel(M, Mo) <= TOL
+        assert np.array_equal(M, M16)
