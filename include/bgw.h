@@ -157,7 +157,7 @@ int bgw_pair_density_workspace(bgw_handle_t h, const bgw_pair_desc *d, size_t *b
  * them.
  * ---------------------------------------------------------------------- */
 typedef struct {
-    int ng;              /* rows/cols of chi for this q (uneven across q allowed) */
+    int ng;              /* rows/cols of chi for this q, 1 .. 12288 (uneven across q allowed) */
     int nk, nv, nc;      /* pair count K = nk*nv*nc, t = (k*nv + v)*nc + c */
     const double *M;     /* DEVICE complex128 [K][ng], e.g. from bgw_pair_density */
     const double *ev;    /* DEVICE f64 [nk][nv], valence energies at k+q (eV) */
@@ -304,7 +304,7 @@ int bgw_bse_kx_workspace(bgw_handle_t h, const bgw_kx_desc *d, size_t *bytes);
 typedef struct {
     const double *M;      /* DEVICE complex128 [ninner][nouter][ng] */
     int ninner, nouter;   /* inner states (>= 1), outer states (1 .. 65536) */
-    int ng;               /* G vectors, 1 .. 8192 */
+    int ng;               /* G vectors, 1 .. 12288 */
     int kind;             /* BGW_SIGMA_X, BGW_SIGMA_SX or BGW_SIGMA_CH */
     int head;             /* BGW_SIGMA_X: index of G = 0 left out, -1 none; ignored otherwise */
     int precision;        /* BGW_SIGMA_X: BGW_FP64 or BGW_SPLIT_BF16; SX and CH: BGW_FP64 */
@@ -335,9 +335,10 @@ int bgw_sigma_workspace(bgw_handle_t h, const bgw_sigma_desc *d, size_t *bytes);
  * first index on ties).  info[w] = 0 on success, i > 0 if the i-th pivot
  * (1-based) is exactly zero; epsinv[w] is then unspecified; info[w] = -1000
  * if an internal wait between workgroups gave up (the call still returns).
- * For ng <= 1536 each panel is eliminated by one workgroup per matrix; the
- * environment variable BGW_GJE_PATH=coop selects the cooperative
- * multi-workgroup panels used above that size (same results to rounding).
+ * ng is 1 .. 12288.  For ng <= 1536 each panel is eliminated by one
+ * workgroup per matrix; the environment variable BGW_GJE_PATH=coop selects
+ * the cooperative multi-workgroup panels used above that size (same results
+ * to rounding).
  * ---------------------------------------------------------------------- */
 /* vcoul: DEVICE f64 [ng]; chi: DEVICE complex128 [nw][ng][ng];
  * epsinv: DEVICE complex128 [nw][ng][ng], may be the same pointer as chi
@@ -356,8 +357,8 @@ int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes);
  * is a fixed 32 MiB device array inside the library, one per device, held
  * until the process ends (its address is taken by bgw_create); the matrices
  * are inverted in launches of as many as that scratch holds.  Fails with
- * BGW_ERR_UNSUPPORTED if one matrix needs more (not the case for ng <= 8192,
- * about 0.5 KiB per unit of ng).  Every call on one device shares that
+ * BGW_ERR_UNSUPPORTED if one matrix needs more (not the case for ng <= 12288:
+ * about 1 KiB per unit of ng below 3000, 2 KiB from there).  Every call on one device shares that
  * device's scratch: calls that overlap on one device (other streams, other
  * threads, other handles) race and must be serialised by the caller. */
 int bgw_eps_inv_noalloc(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,

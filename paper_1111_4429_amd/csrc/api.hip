@@ -124,7 +124,7 @@ extern "C" int bgw_pair_desc_check(const bgw_pair_desc *d) {
     if (d->ngw < 1 || d->ng < 1 || d->nk < 1 || d->nv < 1 || d->nc < 1)
         return fail(BGW_ERR_ARG, "ngw, ng, nk, nv, nc must be >= 1");
     if (!d->gw || !d->ge || !d->cv || !d->cc) return fail(BGW_ERR_ARG, "null pointer in descriptor");
-    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "dielectric sphere larger than 8192 G-vectors");
+    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "dielectric sphere larger than 12288 G-vectors");
     int mw[3], me[3];
     BGW_TRY(check_glist(d->gw, d->ngw, d->n, "wavefunction sphere", mw));
     BGW_TRY(check_glist(d->ge, d->ng, d->n, "dielectric sphere", me));
@@ -664,7 +664,7 @@ static void eps_plan(int ng, int nw, int *group, size_t *gws, size_t *need) {
 extern "C" int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes) {
     clear_error();
     if (!h || ng < 1 || nw < 1 || !bytes) return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_workspace");
-    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 12288");
     BGW_TRY(set_device(h));
     int group = 0;
     size_t gws = 0;
@@ -677,7 +677,7 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
     clear_error();
     if (!h || ng < 1 || nw < 1 || !vcoul || !chi || !epsinv || !info)
         return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv");
-    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 12288");
     BGW_TRY(set_device(h));
     hipStream_t st = (hipStream_t)stream;
     int group = 0;
@@ -702,7 +702,7 @@ extern "C" int bgw_eps_inv_noalloc(bgw_handle_t h, int ng, int nw, const double 
     clear_error();
     if (!h || ng < 1 || nw < 1 || !vcoul || !chi || !epsinv || !info)
         return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_noalloc");
-    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 8192");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 12288");
     BGW_TRY(set_device(h));
     void *ws = g_scratch_ptr[h->device];
     if (!ws) return fail(BGW_ERR_HIP, "no scratch address for this device");

@@ -175,7 +175,7 @@ int check_chi_desc(const bgw_chi_desc *d) {
     for (int i = 0; i < d->nq; ++i) {
         const bgw_chi_q &q = d->q[i];
         if (q.ng < 1 || q.nk < 1 || q.nv < 1 || q.nc < 1) return fail(BGW_ERR_ARG, "chi q entry: sizes must be >= 1");
-        if (q.ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "chi q entry: ng > 8192");
+        if (q.ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "chi q entry: ng > 12288");
         if (!q.M || !q.ev || !q.ec || !q.chi) return fail(BGW_ERR_ARG, "chi q entry: null pointer");
         if (q.head < -1 || q.head >= q.ng) return fail(BGW_ERR_ARG, "chi q entry: head index out of range");
     }
@@ -860,7 +860,7 @@ int check_sigma_desc(const bgw_sigma_desc *d) {
         return fail(BGW_ERR_ARG, "unknown self-energy kind");
     if (d->ninner < 1 || d->nouter < 1 || d->nouter > 65536 || d->ng < 1)
         return fail(BGW_ERR_ARG, "self-energy: sizes out of range");
-    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "self-energy: ng > 8192");
+    if (d->ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "self-energy: ng > 12288");
     if ((long long)d->ninner * d->ng > 0x7fffffffll) return fail(BGW_ERR_UNSUPPORTED, "self-energy: ninner * ng too large");
     if (d->precision != BGW_FP64 && d->precision != BGW_SPLIT_BF16) return fail(BGW_ERR_ARG, "unknown precision");
     if (d->kind != BGW_SIGMA_X) {

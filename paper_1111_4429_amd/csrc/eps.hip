@@ -40,7 +40,8 @@ namespace bgw {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kPanelMax = 32;
-constexpr int kGjeMaxR = 32;                // workgroups per matrix (n <= 8192, 256 rows each)
+constexpr int kGjeMaxR = 48;                // workgroups per matrix (n <= 12288, 256 rows each; the narrow
+                                            // panel's LDS, 256 x 33 + 64 + 48 x 32 complex, fits 160 KB)
 constexpr int kInfoBarrierTimeout = -1000;  // info value when a grid barrier wait gave up
 
 struct GjeScratch {
@@ -631,6 +632,29 @@ __global__ void k_gje_colperm(double2 *__restrict__ A, int n, const int *__restr
     for (int c = threadIdx.x; c < n; c += blockDim.x) a[c] = row[id[c]];
 }
 
+// The same for rows longer than LDS holds (n > 8192): every thread gathers
+// its outputs' sources from the row in global memory into registers, waits
+// for them, the block meets, then the row is overwritten.  n <= 256 * 48.
+constexpr int kColPermPer = 48;
+__global__ __launch_bounds__(256) void k_gje_colperm_reg(double2 *__restrict__ A, int n, const int *__restrict__ idx) {
+    const int mat = blockIdx.y;
+    double2 *a = A + ((size_t)mat * n + blockIdx.x) * n;
+    const int *id = idx + (size_t)mat * n;
+    double2 v[kColPermPer];
+#pragma unroll
+    for (int j = 0; j < kColPermPer; ++j) {
+        const int c = threadIdx.x + 256 * j;
+        v[j] = c < n ? a[id[c]] : make_double2(0.0, 0.0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // every read of the row has returned
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kColPermPer; ++j) {
+        const int c = threadIdx.x + 256 * j;
+        if (c < n) a[c] = v[j];
+    }
+}
+
 // ------------------------------------------------------- one-workgroup panels
 //
 // Matrices with n <= kWgThreads * kWgMaxRows take their panels from one
@@ -1056,6 +1080,12 @@ static int launch_gje_unpermute(double2 *A, int n, int nmat, const int *ipiv, in
     const size_t plds = sizeof(int) * 2 * (size_t)n;
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_perm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plds));
     hipLaunchKernelGGL(k_gje_perm, dim3(nmat), dim3(256), plds, st, ipiv, n, idx);
+    if (n > 8192) {
+        if (n > 256 * kColPermPer) return BGW_ERR_UNSUPPORTED;
+        hipLaunchKernelGGL(k_gje_colperm_reg, dim3(n, nmat), dim3(256), 0, st, A, n, idx);
+        BGW_HIP(hipGetLastError());
+        return BGW_OK;
+    }
     const size_t rlds = sizeof(double2) * (size_t)n;
     BGW_HIP(hipFuncSetAttribute((const void *)k_gje_colperm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
     hipLaunchKernelGGL(k_gje_colperm, dim3(n, nmat), dim3(256), rlds, st, A, n, idx);

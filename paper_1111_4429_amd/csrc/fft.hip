@@ -288,7 +288,8 @@ int launch_pair_fft(const double2 *gv, const double2 *gc, int nkb, int nv, int n
     if (per <= 8) return launch_pair_t<8>(gv, gc, nkb, nv, nc, px, py, pz, sm, lc, M, row0, st);
     if (per <= 16) return launch_pair_t<16>(gv, gc, nkb, nv, nc, px, py, pz, sm, lc, M, row0, st);
     if (per <= 32) return launch_pair_t<32>(gv, gc, nkb, nv, nc, px, py, pz, sm, lc, M, row0, st);
-    set_error("dielectric sphere larger than 8192 G-vectors is not supported");
+    set_error("dielectric sphere larger than 8192 G-vectors on the generic transform path (a box outside the "
+              "register-resident lengths) is not supported");
     return BGW_ERR_UNSUPPORTED;
 }
 

@@ -59,7 +59,7 @@ struct bgw_handle_s {
 
 namespace bgw {
 
-constexpr int kMaxNg = 8192;
+constexpr int kMaxNg = 12288;
 
 int fail(int code, const std::string &msg);
 bool is_2a3b(int n);

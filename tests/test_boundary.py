@@ -60,9 +60,9 @@ def test_pair_desc_validation_codes():
     # sizes
     assert bgw.pair_desc_check(16, gw, ge, nk=0) == bgw.BGW_ERR_ARG
     assert bgw.pair_desc_check(16, gw, ge, nv=-1) == bgw.BGW_ERR_ARG
-    big = synth.gvector_list(8193)
+    big = synth.gvector_list(12289)
     assert bgw.pair_desc_check(128, big, big) == bgw.BGW_ERR_UNSUPPORTED
-    assert "8192" in bgw.lib().bgw_last_error().decode()
+    assert "12288" in bgw.lib().bgw_last_error().decode()
     # the message names the failing check
     dup = gw.copy()
     dup[7] = dup[3]
@@ -170,8 +170,8 @@ def test_next_row_entry_points_validate_without_gpu():
     assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_ARG  # screened kinds need eps^-1
     s.epsinv, s.precision = 1, bgw.SPLIT_BF16
     assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_UNSUPPORTED  # SX is FP64 only
-    s.precision, s.ng = bgw.FP64, 9000
-    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_UNSUPPORTED  # ng above 8192
+    s.precision, s.ng = bgw.FP64, 13000
+    assert L.bgw_sigma(None, ctypes.byref(s), None) == bgw.BGW_ERR_UNSUPPORTED  # ng above 12288
     # exchange kernel
     k = bgw.KxDesc()
     k.M = k.v = k.kx = 1
