@@ -60,8 +60,11 @@ def test_noalloc_rejects_oversize(torch_dev):
     torch, d = torch_dev
     h = bgw.Handle(0)
     z = torch.zeros(1, dtype=torch.float64, device=d)
+    # an Ng above the library's largest (12288): refused on the host before any
+    # launch, so the one-element buffers are never touched
     with pytest.raises(bgw.BgwError) as e:
-        bgw._check(bgw.lib().bgw_eps_inv_noalloc(h._h, 9000, 1, bgw._dptr(z), bgw._dptr(z), bgw._dptr(z),
+        bgw._check(bgw.lib().bgw_eps_inv_noalloc(h._h, 13000, 1, bgw._dptr(z), bgw._dptr(z), bgw._dptr(z),
                                                  bgw._dptr(z), bgw._stream()))
     assert e.value.code == bgw.BGW_ERR_UNSUPPORTED
+    assert "12288" in str(e.value)
     h.close()
