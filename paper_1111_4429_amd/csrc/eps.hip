@@ -545,28 +545,34 @@ __global__ __launch_bounds__(256, 2) void k_gje_update(double2 *__restrict__ A, 
             Rsh[2 * jr + 1][c] = rw[it].y;
         }
     };
-    auto mfma_chunk = [&](int nbc) {
-        const int ksteps = (2 * nbc + 3) / 4;
-#pragma unroll 4
-        for (int s = 0; s < ksteps; ++s) {
-            const int kr = 4 * s + lk;
-            double av[2], bre[2], bim[2];
+    auto mfma_step = [&](int s) {
+        const int kr = 4 * s + lk;
+        double av[2], bre[2], bim[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = Ps[kr][wr * 32 + 16 * a + li];
+        for (int a = 0; a < 2; ++a) av[a] = Ps[kr][wr * 32 + 16 * a + li];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = wc * 32 + 16 * b + li;
+            // odd rows (imaginary parts): Bre = -Im R, Bim = Re R; even: Re R, Im R
+            bre[b] = rsign * Rsh[kr][col];
+            bim[b] = Rsh[kr ^ 1][col];
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                const int col = wc * 32 + 16 * b + li;
-                // odd rows (imaginary parts): Bre = -Im R, Bim = Re R; even: Re R, Im R
-                bre[b] = rsign * Rsh[kr][col];
-                bim[b] = Rsh[kr ^ 1][col];
+                cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
+                cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
             }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bre[b], cre[a][b], 0, 0, 0);
-                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bim[b], cim[a][b], 0, 0, 0);
-                }
+    };
+    // a full chunk has a compile-time step count; the last one may be narrower
+    auto mfma_chunk = [&](int nbc) {
+        if (nbc == kPanelMax) {
+#pragma unroll 4
+            for (int s = 0; s < 2 * kPanelMax / 4; ++s) mfma_step(s);
+        } else {
+            const int ksteps = (2 * nbc + 3) / 4;
+            for (int s = 0; s < ksteps; ++s) mfma_step(s);
         }
     };
     load_chunk(0);
