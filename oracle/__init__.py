@@ -76,6 +76,7 @@ def lib():
         L.orc_ff_grid.argtypes = [D, D, D, D, I, P]
         L.orc_bse_kx.argtypes = [Lg, I, P, P, I, D, I, P, P]
         L.orc_sigma.argtypes = [I, I, I, I, P, I, P, P, D, P]
+        L.orc_realify.argtypes = [I, I, I, P, P, D, P]
         for f in (L.orc_pair_density, L.orc_weights, L.orc_chi, L.orc_vcoul, L.orc_eps, L.orc_inverse,
                   L.orc_num_threads, L.orc_weights_real, L.orc_chi_cw, L.orc_ff_grid, L.orc_bse_kx, L.orc_sigma):
             f.restype = I
@@ -226,6 +227,21 @@ def sigma(kind: str, M: np.ndarray, v: np.ndarray, pf: float, einv: Optional[np.
     if rc != 0:
         raise ValueError(f"orc_sigma failed: {rc}")
     return out
+
+
+def realify(c: np.ndarray, e: np.ndarray, tol: float):
+    """Real coefficients [nk][nb][ngw] from complex ones (real flavor): Gram-Schmidt, largest remaining
+    vector first, over Re and Im of each group of degenerate states (energies within tol of their
+    neighbour).  Returns (r, number of groups that are not real up to a unitary)."""
+    c = np.ascontiguousarray(c, dtype=np.complex128)
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    nk, nb, ngw = c.shape
+    assert e.shape == (nk, nb)
+    r = np.zeros((nk, nb, ngw))
+    bad = lib().orc_realify(nk, nb, ngw, _p(c), _p(e), float(tol), _p(r))
+    if bad < 0:
+        raise ValueError("orc_realify: bad arguments")
+    return r, bad
 
 
 def vcoul(bvec: np.ndarray, q: Sequence[float], ge: np.ndarray) -> np.ndarray:

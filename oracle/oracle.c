@@ -23,6 +23,9 @@
  *   orc_inverse       Gaussian elimination with partial pivoting on [A | I]
  *                     (the ZGESV semantics the paper names for the
  *                     inversion), LAPACK INFO convention.
+ *   orc_realify       real coefficients from complex ones (real flavor):
+ *                     Gram-Schmidt over the real and imaginary parts of
+ *                     each degenerate group of states.
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
  */
@@ -541,4 +544,93 @@ int orc_inverse(int n, const double *A, double *Ainv)
     }
     free(T);
     return info;
+}
+
+/*
+ * Real coefficients from complex ones (the real and complex flavors): with
+ * inversion and time-reversal symmetry every state can be chosen with real
+ * plane-wave coefficients.  A non-degenerate state is real times a global
+ * phase; a group of d degenerate states spans d real dimensions.  Bands of
+ * one k are grouped by degeneracy (consecutive bands whose energies differ
+ * by at most tol from their neighbour).  For each group the 2d real vectors
+ * Re c_b, Im c_b (b in the group, in that order) go through Gram-Schmidt:
+ * at each of d steps the remaining vector of largest norm is taken (lowest
+ * index on ties), normalised, written as the next real state of the group,
+ * and projected out of the remaining vectors.  For one state this divides
+ * out its phase (up to sign).
+ * c: complex128 [nk][nb][ngw]; e: [nk][nb] (ascending per k); r: real
+ * [nk][nb][ngw] out.  Returns the number of groups whose vectors span more
+ * than d real dimensions (a remaining norm above 1e-6 after the d steps:
+ * the input was not real up to a unitary within the group) or that span
+ * fewer, or -1 on bad arguments.
+ */
+int orc_realify(int nk, int nb, int ngw, const double *c, const double *e, double tol, double *r)
+{
+    if (nk < 1 || nb < 1 || ngw < 1 || !(tol >= 0.0) || !c || !e || !r) return -1;
+    double *v = malloc(sizeof(double) * 2 * (size_t)nb * ngw);
+    char *used = malloc((size_t)2 * nb);
+    if (!v || !used) {
+        free(v);
+        free(used);
+        return -1;
+    }
+    int bad = 0;
+    for (int k = 0; k < nk; ++k) {
+        const double *ek = e + (size_t)k * nb;
+        int b0 = 0;
+        while (b0 < nb) {
+            int b1 = b0 + 1;
+            while (b1 < nb && ek[b1] - ek[b1 - 1] <= tol) ++b1;
+            const int d = b1 - b0, m = 2 * d;
+            for (int i = 0; i < d; ++i) {
+                const double *cb = c + 2 * ((size_t)k * nb + b0 + i) * ngw;
+                for (int g = 0; g < ngw; ++g) {
+                    v[(size_t)(2 * i) * ngw + g] = cb[2 * g];
+                    v[(size_t)(2 * i + 1) * ngw + g] = cb[2 * g + 1];
+                }
+            }
+            memset(used, 0, (size_t)m);
+            int deficient = 0;
+            for (int s = 0; s < d; ++s) {
+                int p = -1;
+                double best = -1.0;
+                for (int j = 0; j < m; ++j) {
+                    if (used[j]) continue;
+                    double nn = 0.0;
+                    for (int g = 0; g < ngw; ++g) nn += v[(size_t)j * ngw + g] * v[(size_t)j * ngw + g];
+                    if (nn > best) {
+                        best = nn;
+                        p = j;
+                    }
+                }
+                used[p] = 1;
+                double *q = r + ((size_t)k * nb + b0 + s) * ngw;
+                if (!(best > 0.0)) {
+                    deficient = 1;
+                    for (int g = 0; g < ngw; ++g) q[g] = 0.0;
+                    continue;
+                }
+                const double inv = 1.0 / sqrt(best);
+                for (int g = 0; g < ngw; ++g) q[g] = v[(size_t)p * ngw + g] * inv;
+                for (int j = 0; j < m; ++j) {
+                    if (used[j]) continue;
+                    double dot = 0.0;
+                    for (int g = 0; g < ngw; ++g) dot += q[g] * v[(size_t)j * ngw + g];
+                    for (int g = 0; g < ngw; ++g) v[(size_t)j * ngw + g] -= dot * q[g];
+                }
+            }
+            double rest = 0.0;
+            for (int j = 0; j < m; ++j) {
+                if (used[j]) continue;
+                double nn = 0.0;
+                for (int g = 0; g < ngw; ++g) nn += v[(size_t)j * ngw + g] * v[(size_t)j * ngw + g];
+                if (nn > rest) rest = nn;
+            }
+            if (deficient || sqrt(rest) > 1e-6) ++bad;
+            b0 = b1;
+        }
+    }
+    free(v);
+    free(used);
+    return bad;
 }

@@ -644,3 +644,88 @@ def test_real_flavor_pair_density_and_chi_are_real():
     assert np.all(chi.imag == 0.0)
     asym = np.abs(chi.real - np.transpose(chi.real, (0, 2, 1))).max()
     assert asym <= 1e-14 * np.abs(chi.real).max()
+
+
+# ---------------------------------------------------------------- real-flavor phase fixing
+
+
+def _real_states(rng, nb, ngw):
+    return np.linalg.qr(rng.standard_normal((ngw, nb)))[0].T  # orthonormal real rows
+
+
+def _unitary(rng, d):
+    q, r = np.linalg.qr(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def test_realify_removes_phases_of_nondegenerate_states():
+    """One state alone: real times a phase, including nearly imaginary and
+    sign-flipped ones, comes back as the real state up to its sign."""
+    rng = np.random.default_rng(1)
+    R = _real_states(rng, 6, 80)
+    th = np.array([0.0, np.pi / 2, np.pi, 1.0, np.pi / 2 - 1e-9, 4.0])
+    C = (R * np.exp(1j * th)[:, None])[None]
+    r, bad = oracle.realify(C, np.arange(6.0)[None], 1e-6)
+    assert bad == 0
+    dots = (r[0] * R).sum(-1)
+    assert np.abs(np.abs(dots) - 1.0).max() <= 1e-14
+    assert np.abs(r[0] - np.sign(dots)[:, None] * R).max() <= 1e-14
+
+
+def test_realify_degenerate_groups_span_the_same_real_subspace():
+    """Groups of degenerate states mixed by complex unitaries: the real states
+    are orthonormal and span each group's subspace (equal projectors)."""
+    rng = np.random.default_rng(2)
+    R = _real_states(rng, 7, 90)
+    e = np.array([-3.0, -1.0, -1.0, -1.0 + 1e-9, 2.0, 5.0, 5.0])  # groups of 1, 3, 1, 2
+    C = R.astype(np.complex128)
+    for b0, d in ((1, 3), (5, 2)):
+        C[b0:b0 + d] = _unitary(rng, d) @ R[b0:b0 + d]
+    C[0] *= np.exp(0.7j)
+    C[4] *= np.exp(-2.1j)
+    r, bad = oracle.realify(C[None], e[None], 1e-6)
+    assert bad == 0
+    out = r[0]
+    assert np.abs(out @ out.T - np.eye(7)).max() <= 1e-14
+    for b0, d in ((0, 1), (1, 3), (4, 1), (5, 2)):
+        P1 = out[b0:b0 + d].T @ out[b0:b0 + d]
+        P2 = R[b0:b0 + d].T @ R[b0:b0 + d]
+        assert np.abs(P1 - P2).max() <= 1e-14
+
+
+def test_realify_flags_states_that_are_not_real_up_to_a_unitary():
+    """Generic complex states: alone, each state's real and imaginary parts
+    are independent; as one group of 2 they span 4 real dimensions."""
+    rng = np.random.default_rng(3)
+    Z = np.linalg.qr(rng.standard_normal((60, 2)) + 1j * rng.standard_normal((60, 2)))[0].T
+    assert oracle.realify(Z[None], np.array([[0.0, 1.0]]), 1e-6)[1] == 2
+    assert oracle.realify(Z[None], np.array([[0.0, 0.0]]), 1e-6)[1] == 1
+
+
+def test_realify_keeps_chi():
+    """Realifying rotates each degenerate group within itself and weights
+    depend only on energies, so chi of the real states equals chi of the
+    complex ones, and is real."""
+    s = synth.small_system(n=16, ngw=200, ng=90, nv=3, nc=6, nk=1, seed=9, flavor="real")
+    q = s["qs"][0]
+    cv, cc = q["cv"][0], s["cc"][0]
+    ev, ec = q["ev"][0].copy(), s["ec"][0].copy()
+    ev[1] = ev[0]          # valence 0-1 degenerate
+    ec[2:4] = ec[1]        # conduction 1-3 degenerate
+    rng = np.random.default_rng(4)
+    Cv = cv.astype(np.complex128)
+    Cv[0:2] = _unitary(rng, 2) @ cv[0:2]
+    Cv[2] *= np.exp(1.3j)
+    Cc = cc.astype(np.complex128)
+    Cc[1:4] = _unitary(rng, 3) @ cc[1:4]
+    Cc[0] *= np.exp(-0.4j)
+    Cc[4] *= 1j
+    Cc[5] *= np.exp(2.0j)
+    rv, bv = oracle.realify(Cv[None], ev[None], 1e-9)
+    rc, bc = oracle.realify(Cc[None], ec[None], 1e-9)
+    assert bv == 0 and bc == 0
+    w = oracle.weights(ev[None], ec[None], [0.0, 5.0])
+    chi_c = oracle.chi(oracle.pair_density(s["gw"], q["ge"], Cv[None], Cc[None]), w, 0.01)
+    chi_r = oracle.chi(oracle.pair_density(s["gw"], q["ge"], rv, rc), w, 0.01)
+    assert np.all(chi_r.imag == 0.0)
+    assert np.linalg.norm(chi_r - chi_c) <= 1e-12 * np.linalg.norm(chi_c)
