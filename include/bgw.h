@@ -236,12 +236,37 @@ int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, double *M, voi
  * [nw][ng][ng] (real symmetric, written in full); FP64 on the imaginary axis
  * only (BGW_ERR_UNSUPPORTED otherwise), no graph capture, `head` ignored.
  * One weights launch, one persistent real rank-K-update launch over every
- * (q, frequency, K range, 64 x 64 upper tile) item, one finalize. */
+ * (q, frequency, K range, 128 x 128 upper tile) item, one finalize. */
 int bgw_chi0_real(bgw_handle_t h, const bgw_chi_desc *d, void *stream);
 
 /* Device workspace bgw_chi0_real(h, d, ...) needs, in bytes (HOST *bytes).
  * Allocates nothing. */
 int bgw_chi0_real_workspace(bgw_handle_t h, const bgw_chi_desc *d, size_t *bytes);
+
+/* Real coefficients from complex ones (the same section): a plane-wave code
+ * returns a non-degenerate state as real times a global phase, and a group
+ * of d degenerate states as any orthonormal basis of its subspace; the real
+ * and imaginary parts of the group's states then span d real dimensions.
+ * Bands of one k whose energies differ by at most tol from their neighbour
+ * form a group; Gram-Schmidt over the group's 2d vectors Re c_b, Im c_b (in
+ * that order), the remaining vector of largest norm first (lowest index on
+ * ties), gives its d real orthonormal states (for one state: the phase
+ * divided out, up to sign).
+ * c: DEVICE complex128 [nk][nb][ngw]; e: HOST f64 [nk][nb], ascending within
+ * each k; r: DEVICE f64 [nk][nb][ngw], output (not aliasing c); nbad:
+ * DEVICE int32 [1], set to the number of groups that were not real up to a
+ * unitary (more than d real dimensions left a norm above 1e-6, or fewer than
+ * d were found).  BGW_ERR_ARG for bad arguments or unsorted energies,
+ * BGW_ERR_UNSUPPORTED for a group of more than 32 states (both checked
+ * before the handle).  Workspace: 16 nk nb ngw bytes plus the group table,
+ * which is uploaded on `stream`; the call waits for that upload, so the
+ * stream's earlier work finishes before it returns. */
+int bgw_realify(bgw_handle_t h, int nk, int nb, int ngw, const double *c, const double *e, double tol, double *r,
+                int *nbad, void *stream);
+
+/* Device workspace bgw_realify(h, nk, nb, ngw, e, tol, ...) needs, in bytes
+ * (HOST *bytes).  Allocates nothing. */
+int bgw_realify_workspace(bgw_handle_t h, int nk, int nb, int ngw, const double *e, double tol, size_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Exchange kernel of the Bethe-Salpeter equation

@@ -603,13 +603,13 @@ int orc_realify(int nk, int nb, int ngw, const double *c, const double *e, doubl
                         p = j;
                     }
                 }
-                used[p] = 1;
                 double *q = r + ((size_t)k * nb + b0 + s) * ngw;
-                if (!(best > 0.0)) {
+                if (p < 0 || !(best > 0.0)) { /* no vector left (or only NaN norms): not d real dimensions */
                     deficient = 1;
                     for (int g = 0; g < ngw; ++g) q[g] = 0.0;
                     continue;
                 }
+                used[p] = 1;
                 const double inv = 1.0 / sqrt(best);
                 for (int g = 0; g < ngw; ++g) q[g] = v[(size_t)p * ngw + g] * inv;
                 for (int j = 0; j < m; ++j) {

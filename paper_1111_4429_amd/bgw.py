@@ -39,7 +39,8 @@ EXPORTS = [
     "bgw_set_timing", "bgw_get_timing", "bgw_reset_timing", "bgw_pair_transform_box", "bgw_autotune",
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
     "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace", "bgw_sigma",
-    "bgw_sigma_workspace", "bgw_pair_density_real", "bgw_chi0_real", "bgw_chi0_real_workspace",
+    "bgw_sigma_workspace", "bgw_pair_density_real", "bgw_chi0_real", "bgw_chi0_real_workspace", "bgw_realify",
+    "bgw_realify_workspace",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -169,6 +170,8 @@ def lib():
         L.bgw_pair_density_real.argtypes = [P, ctypes.POINTER(PairDesc), P, P]
         L.bgw_chi0_real.argtypes = [P, ctypes.POINTER(ChiDesc), P]
         L.bgw_chi0_real_workspace.argtypes = [P, ctypes.POINTER(ChiDesc), ctypes.POINTER(ctypes.c_size_t)]
+        L.bgw_realify.argtypes = [P, I, I, I, P, P, D, P, P, P]
+        L.bgw_realify_workspace.argtypes = [P, I, I, I, P, D, ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_sigma_workspace.argtypes = [P, ctypes.POINTER(SigmaDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_bse_kx_workspace.argtypes = [P, ctypes.POINTER(KxDesc), ctypes.POINTER(ctypes.c_size_t)]
         L.bgw_vcoul_bulk.argtypes = [P, P, I, P, P]
@@ -188,7 +191,7 @@ def lib():
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
                   "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx",
                   "bgw_bse_kx_workspace", "bgw_sigma", "bgw_sigma_workspace", "bgw_pair_density_real",
-                  "bgw_chi0_real", "bgw_chi0_real_workspace"):
+                  "bgw_chi0_real", "bgw_chi0_real_workspace", "bgw_realify", "bgw_realify_workspace"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -433,6 +436,30 @@ class Handle:
         out = ctypes.c_size_t()
         _check(lib().bgw_chi0_real_workspace(self._h, ctypes.byref(d), ctypes.byref(out)))
         del keep
+        return int(out.value)
+
+    def realify(self, c, e, tol: float, r=None):
+        """Real flavor: real coefficients [nk][nb][ngw] (float64, device) from complex ones (complex128,
+        device) with energies e (host [nk][nb], ascending per k): Gram-Schmidt over Re and Im of each
+        group of degenerate states (energies within tol of their neighbour).  Returns (r, number of
+        groups that were not real up to a unitary)."""
+        import torch
+        assert c.dtype == torch.complex128 and c.is_contiguous() and c.dim() == 3
+        nk, nb, ngw = (int(x) for x in c.shape)
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        assert e.shape == (nk, nb)
+        if r is None:
+            r = torch.empty((nk, nb, ngw), dtype=torch.float64, device=c.device)
+        assert r.shape == (nk, nb, ngw) and r.dtype == torch.float64 and r.is_contiguous()
+        nbad = torch.empty(1, dtype=torch.int32, device=c.device)
+        _check(lib().bgw_realify(self._h, nk, nb, ngw, _dptr(c), e.ctypes.data, float(tol), _dptr(r), _dptr(nbad),
+                                 _stream()))
+        return r, int(nbad.cpu()[0])
+
+    def realify_workspace(self, nk: int, nb: int, ngw: int, e, tol: float) -> int:
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        out = ctypes.c_size_t()
+        _check(lib().bgw_realify_workspace(self._h, nk, nb, ngw, e.ctypes.data, float(tol), ctypes.byref(out)))
         return int(out.value)
 
     def autotune(self, qs: Sequence[dict], omega: Sequence[float], precision: int = FP64,

@@ -15,7 +15,8 @@ LIB = os.path.join(HERE, "libbgw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.hip", "chi_api.hip", "fft.hip", "fft2.hip", "chi.hip", "split.hip", "eps.hip", "real.hip"]
+SOURCES = ["api.hip", "chi_api.hip", "fft.hip", "fft2.hip", "chi.hip", "split.hip", "eps.hip", "real.hip",
+           "realify.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}",

@@ -201,6 +201,23 @@ def test_next_row_entry_points_validate_without_gpu():
     gw = synth.gvector_list(27)
     pd = bgw.make_pair_desc(8, gw, gw, nk=1, nv=1, nc=1)
     assert L.bgw_pair_density_real(None, ctypes.byref(pd), None, None) == bgw.BGW_ERR_ARG
+    # real coefficients from complex ones: energies, then group size, then the handle
+    e = np.zeros((2, 40))
+    e[0] = np.arange(40.0)
+    e[1, :33] = 0.0
+    e[1, 33:] = np.arange(1.0, 8.0)
+    ep = e.ctypes.data
+    assert L.bgw_realify(None, 2, 40, 50, 1, ep, 1e-6, 1, 1, None) == bgw.BGW_ERR_UNSUPPORTED  # group of 33
+    e[1, 32] = 0.5
+    assert L.bgw_realify(None, 2, 40, 50, 1, ep, 1e-6, 1, 1, None) == bgw.BGW_ERR_ARG  # null handle
+    e[1, 32] = -0.5
+    assert L.bgw_realify(None, 2, 40, 50, 1, ep, 1e-6, 1, 1, None) == bgw.BGW_ERR_ARG  # energies descend
+    assert b"ascend" in L.bgw_last_error()
+    e[1, 32] = 0.5
+    assert L.bgw_realify(None, 2, 40, 50, 1, ep, -1.0, 1, 1, None) == bgw.BGW_ERR_ARG  # negative tol
+    assert L.bgw_realify(None, 0, 40, 50, 1, ep, 1e-6, 1, 1, None) == bgw.BGW_ERR_ARG  # no k
+    nbytes = ctypes.c_size_t()
+    assert L.bgw_realify_workspace(None, 2, 40, 50, ep, 1e-6, ctypes.byref(nbytes)) == bgw.BGW_ERR_ARG
 
 
 def test_bench_refuses_several_gpus():

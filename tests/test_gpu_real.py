@@ -138,3 +138,167 @@ def test_silicon_like_real_sampled(torch_dev, handle):
     ref = oracle.chi(sub, w, pf, rows=[pos[int(r)] for r in rows], cols=[pos[int(c)] for c in cols])[0]
     got = cr[0][torch.from_numpy(rows).to(M.device)][:, torch.from_numpy(cols).to(M.device)].cpu().numpy()
     assert rel(got, ref.real) <= TOL
+
+
+# --- real coefficients from complex ones -----------------------------------
+
+def _unitary(rng, d):
+    q, r = np.linalg.qr(rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d)))
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _groups(e, tol):
+    """(b0, d) of every degenerate group of one k: neighbours within tol."""
+    out, b0 = [], 0
+    while b0 < len(e):
+        b1 = b0 + 1
+        while b1 < len(e) and e[b1] - e[b1 - 1] <= tol:
+            b1 += 1
+        out.append((b0, b1 - b0))
+        b0 = b1
+    return out
+
+
+def _complexify(R, e, tol, seed):
+    """Complex states a plane-wave code could return for the real states R
+    [nk][nb][ngw]: a random phase on each state, a random unitary within each
+    degenerate group."""
+    rng = np.random.default_rng(seed)
+    C = R * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi, R.shape[:2]))[..., None]
+    for k in range(R.shape[0]):
+        for b0, d in _groups(e[k], tol):
+            if d > 1:
+                C[k, b0:b0 + d] = _unitary(rng, d) @ R[k, b0:b0 + d]
+    return C
+
+
+def _same_group_bases(torch_dev, a, b, e, tol, atol):
+    """a and b (device f64 [nk][nb][ngw]) are orthonormal per k and span the
+    same subspace for every degenerate group: S = a b^T is orthogonal and zero
+    outside the group blocks."""
+    torch = torch_dev[0]
+    S = torch.bmm(a, b.transpose(1, 2).contiguous())
+    nk, nb = S.shape[:2]
+    mask = np.zeros((nk, nb, nb), dtype=bool)
+    for k in range(nk):
+        for b0, d in _groups(e[k], tol):
+            mask[k, b0:b0 + d, b0:b0 + d] = True
+    off = S.masked_fill(torch.from_numpy(mask).to(S.device), 0.0)
+    eye = torch.eye(nb, dtype=S.dtype, device=S.device).expand(nk, nb, nb)
+    assert float(off.abs().max()) <= atol
+    assert float((torch.bmm(S, S.transpose(1, 2).contiguous()) - eye).abs().max()) <= atol
+    assert float((torch.bmm(a, a.transpose(1, 2).contiguous()) - eye).abs().max()) <= atol
+
+
+def test_realify_matches_oracle(torch_dev, handle):
+    """Groups of 1 .. 32 states (the largest supported) at ngw = 300, not a
+    multiple of the block size: the same real groups as the oracle's, phases
+    of single states removed up to sign."""
+    torch = torch_dev[0]
+    s = synth.small_system(n=16, ngw=300, ng=181, nv=2, nc=40, nk=3, seed=23, flavor="real")
+    R = s["cc"]
+    e = s["ec"].reshape(3, 40).copy()
+    for k, b0, d in ((0, 1, 2), (0, 4, 3), (0, 10, 5), (0, 39, 1), (1, 4, 32), (2, 38, 2)):
+        e[k, b0:b0 + d] = e[k, b0]
+    tol = 1e-9
+    C = _complexify(R, e, tol, 5)
+    ro, bad = oracle.realify(C, e, tol)
+    assert bad == 0
+    r, nbad = handle.realify(dev(torch_dev, C), e, tol)
+    torch.cuda.synchronize()
+    assert nbad == 0
+    _same_group_bases(torch_dev, r, dev(torch_dev, ro), e, tol, 1e-12)
+    _same_group_bases(torch_dev, r, dev(torch_dev, R), e, tol, 1e-12)
+    # single states: the oracle's vector up to sign
+    got, single = r.cpu().numpy(), [(k, b0) for k in range(3) for b0, d in _groups(e[k], tol) if d == 1]
+    for k, b in single:
+        sgn = np.sign(got[k, b] @ ro[k, b])
+        assert np.abs(got[k, b] - sgn * ro[k, b]).max() <= 1e-13
+
+
+def test_realify_counts_groups_that_are_not_real(torch_dev, handle):
+    """Generic complex orthonormal states: a single state, and a group of d,
+    span more real dimensions than they have states; real states mixed by a
+    unitary do not.  The count equals the oracle's."""
+    torch = torch_dev[0]
+    rng = np.random.default_rng(8)
+    ngw = 517
+    Z = np.linalg.qr(rng.standard_normal((ngw, 12)) + 1j * rng.standard_normal((ngw, 12)))[0].T
+    R = np.linalg.qr(rng.standard_normal((ngw, 12)))[0].T
+    C = np.stack([Z, R * 1j, Z])
+    C[2, 6:] = _unitary(rng, 6) @ R[6:]
+    e = np.array([[0, 1, 2, 2, 3, 3, 3, 4, 5, 6, 7, 8],
+                  [0] * 12,
+                  [0, 0, 0, 1, 2, 3, 4, 4, 4, 4, 4, 4]], dtype=np.float64)
+    ro, bad = oracle.realify(C, e, 1e-9)
+    assert bad == 9 + 0 + 4
+    r, nbad = handle.realify(dev(torch_dev, C), e, 1e-9)
+    torch.cuda.synchronize()
+    assert nbad == bad
+    # the real groups still come out right
+    got = r.cpu().numpy()
+    P = got[1].T @ got[1]
+    assert np.abs(P - R.T @ R).max() <= 1e-12
+    assert np.abs(got[2, 6:].T @ got[2, 6:] - R[6:].T @ R[6:]).max() <= 1e-12
+
+
+def test_realify_then_real_chi_equals_complex_chi(torch_dev, handle):
+    """Complex degenerate states -> real states on the GPU -> real M -> real
+    chi, against the oracle's chi of the complex states (FP64, 1e-12): each
+    group is rotated within itself and the weights depend only on energies."""
+    torch = torch_dev[0]
+    s = synth.small_system(n=16, ngw=300, ng=181, nv=4, nc=24, nk=2, seed=31, flavor="real")
+    q = s["qs"][0]
+    nk, nv, nc = 2, 4, 24
+    ev = q["ev"].reshape(nk, nv).copy()
+    ec = s["ec"].reshape(nk, nc).copy()
+    ev[0, 1:3] = ev[0, 1]
+    ev[1, 0:4] = ev[1, 0]
+    ec[0, 3:6] = ec[0, 3]
+    ec[1, 0:2] = ec[1, 0]
+    ec[1, 10:17] = ec[1, 10]
+    tol = 1e-9
+    Cv = _complexify(q["cv"], ev, tol, 11)
+    Cc = _complexify(s["cc"], ec, tol, 12)
+    om = [0.0, 3.0]
+    pf = 1.0 / (nk * s["vol"])
+    ref = oracle.chi(oracle.pair_density(s["gw"], q["ge"], Cv, Cc), oracle.weights(ev, ec, om), pf)
+    assert np.abs(ref.imag).max() <= 1e-14 * np.abs(ref.real).max()
+    rv, bv = handle.realify(dev(torch_dev, Cv), ev, tol)
+    rc, bc = handle.realify(dev(torch_dev, Cc), ec, tol)
+    M = handle.pair_density_real(s["n"], s["gw"], q["ge"], rv, rc)
+    ent = dict(M=M, ev=dev(torch_dev, ev), ec=dev(torch_dev, ec), nk=nk, nv=nv, nc=nc, head=0, prefactor=pf)
+    (got,) = handle.chi0_real([ent], om)
+    torch.cuda.synchronize()
+    assert bv == 0 and bc == 0
+    got = got.cpu().numpy()
+    for i in range(len(om)):
+        assert rel(got[i], ref[i].real) <= TOL
+
+
+def test_realify_silicon_like_conduction_states(torch_dev, handle):
+    """The silicon-like real workload's 64 x 400 conduction states at 1500
+    plane waves, complexified with degenerate groups of 2 .. 6 every few
+    bands: GPU against the oracle and against the real states."""
+    torch = torch_dev[0]
+    s = synth.make_system(synth.WORKLOADS["silicon-like-48-real"])
+    R = s["cc"]
+    nk, nc = R.shape[:2]
+    e = s["ec"].reshape(nk, nc).copy()
+    rng = np.random.default_rng(3)
+    for k in range(nk):
+        b = int(rng.integers(0, 4))
+        while b < nc:
+            d = int(rng.integers(1, 7))
+            e[k, b:b + d] = e[k, b]
+            b += d + int(rng.integers(1, 6))
+    tol = 1e-9
+    C = _complexify(R, e, tol, 4)
+    ro, bad = oracle.realify(C, e, tol)
+    assert bad == 0
+    r, nbad = handle.realify(dev(torch_dev, C), e, tol)
+    torch.cuda.synchronize()
+    assert nbad == 0
+    _same_group_bases(torch_dev, r, dev(torch_dev, ro), e, tol, 1e-12)
+    _same_group_bases(torch_dev, r, dev(torch_dev, R), e, tol, 1e-12)
+    assert handle.workspace_bytes() >= handle.realify_workspace(nk, nc, R.shape[2], e, tol)
