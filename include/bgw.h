@@ -371,8 +371,24 @@ int bgw_sigma_workspace(bgw_handle_t h, const bgw_sigma_desc *d, size_t *bytes);
 int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
                 double *epsinv, int *info, void *stream);
 
-/* Device workspace bgw_eps_inv(h, ng, nw, ...) needs, in bytes (HOST
- * *bytes).  Allocates nothing. */
+/* bgw_eps_inv for chi Hermitian and negative semidefinite, as chi0 is at
+ * zero and at imaginary frequency (every weight of the chi sum is negative),
+ * with v > 0.  Then epsilon = S (1 - S chi S) S^-1 with S = diag(v^1/2), the
+ * middle factor Hermitian with eigenvalues >= 1, so every elimination pivot
+ * is real and >= 1 and the elimination needs no row interchanges: only the
+ * 64 x 64 diagonal block of each panel is eliminated column by column, the
+ * rest is parallel.  Same arguments and results (to rounding) as
+ * bgw_eps_inv.  The precondition is checked: info[w] = -2 when chi[w] is
+ * not Hermitian to 1e-8 relative on the scale sqrt(v_G v_G') (or some v <= 0,
+ * or a value is not finite), -3 when a pivot has real part below 1/2 or is
+ * not real to half of that (chi not negative semidefinite); epsinv[w] is
+ * then unspecified and the caller inverts the original chi with
+ * bgw_eps_inv. */
+int bgw_eps_inv_nsd(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi, double *epsinv,
+                    int *info, void *stream);
+
+/* Device workspace bgw_eps_inv(h, ng, nw, ...) or bgw_eps_inv_nsd(h, ng, nw,
+ * ...) needs, in bytes (HOST *bytes).  Allocates nothing. */
 int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes);
 
 /* bgw_eps_inv for callers that cannot allocate device memory: code under HIP

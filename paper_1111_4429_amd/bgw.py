@@ -40,7 +40,7 @@ EXPORTS = [
     "bgw_tuned_config", "bgw_pair_density_workspace", "bgw_chi0_workspace", "bgw_eps_inv_workspace",
     "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx", "bgw_bse_kx_workspace", "bgw_sigma",
     "bgw_sigma_workspace", "bgw_pair_density_real", "bgw_chi0_real", "bgw_chi0_real_workspace", "bgw_realify",
-    "bgw_realify_workspace",
+    "bgw_realify_workspace", "bgw_eps_inv_nsd",
 ]
 
 KERNELS = ["band", "pair", "weights", "herk", "finalize", "split_slice", "split_herk", "headwing", "eps_build",
@@ -165,6 +165,7 @@ def lib():
         L.bgw_chi0.argtypes = [P, ctypes.POINTER(ChiDesc), P]
         L.bgw_eps_inv.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_eps_inv_noalloc.argtypes = [P, I, I, P, P, P, P, P]
+        L.bgw_eps_inv_nsd.argtypes = [P, I, I, P, P, P, P, P]
         L.bgw_bse_kx.argtypes = [P, ctypes.POINTER(KxDesc), P]
         L.bgw_sigma.argtypes = [P, ctypes.POINTER(SigmaDesc), P]
         L.bgw_pair_density_real.argtypes = [P, ctypes.POINTER(PairDesc), P, P]
@@ -191,7 +192,7 @@ def lib():
                   "bgw_pair_transform_box", "bgw_autotune", "bgw_tuned_config", "bgw_pair_density_workspace",
                   "bgw_chi0_workspace", "bgw_eps_inv_workspace", "bgw_ff_grid", "bgw_eps_inv_noalloc", "bgw_bse_kx",
                   "bgw_bse_kx_workspace", "bgw_sigma", "bgw_sigma_workspace", "bgw_pair_density_real",
-                  "bgw_chi0_real", "bgw_chi0_real_workspace", "bgw_realify", "bgw_realify_workspace"):
+                  "bgw_chi0_real", "bgw_chi0_real_workspace", "bgw_realify", "bgw_realify_workspace", "bgw_eps_inv_nsd"):
             getattr(L, f).restype = I
         _lib = L
     return _lib
@@ -477,8 +478,10 @@ class Handle:
         return {"tile": cfg[0], "items_per_cu": cfg[1], "split_nsplit": cfg[2], "tuned": bool(cfg[3])}
 
     # ---------------------------------------------------------------- eps^-1
-    def eps_inv(self, vcoul, chi, epsinv=None, info=None):
-        """epsilon^-1 for every frequency; returns (epsinv, info) device tensors."""
+    def eps_inv(self, vcoul, chi, epsinv=None, info=None, nsd=False):
+        """epsilon^-1 for every frequency; returns (epsinv, info) device tensors.  nsd: chi is Hermitian
+        negative semidefinite (zero or imaginary frequency), inverted without row interchanges
+        (bgw_eps_inv_nsd; info -2 / -3 when that does not hold)."""
         import torch
         if chi.dim() == 2:
             chi = chi.unsqueeze(0)
@@ -489,8 +492,8 @@ class Handle:
             epsinv = torch.empty_like(chi)
         if info is None:
             info = torch.empty(nw, dtype=torch.int32, device=chi.device)
-        _check(lib().bgw_eps_inv(self._h, ng, nw, _dptr(vcoul.contiguous()), _dptr(chi), _dptr(epsinv),
-                                 _dptr(info), _stream()))
+        fn = lib().bgw_eps_inv_nsd if nsd else lib().bgw_eps_inv
+        _check(fn(self._h, ng, nw, _dptr(vcoul.contiguous()), _dptr(chi), _dptr(epsinv), _dptr(info), _stream()))
         return epsinv, info
 
     # ---------------------------------------------------------------- BSE exchange kernel

@@ -48,6 +48,9 @@ size_t gje_workspace_bytes(int n, int nmat, int R);
 int gje_rows_per_wg(int n);
 int gje_max_group(int n);
 int launch_gje_invert(double2 *A, int n, int nmat, int *info, void *ws, int *ipiv_ws, hipStream_t);
+size_t nsd_workspace_bytes(int n, int nmat, int nall);
+int launch_nsd_check(const double2 *chi, const double *v, int n, int nall, int nmat, void *ws, hipStream_t);
+int launch_nsd_invert(double2 *A, int n, int nmat, int m0, int nall, int *info, void *ws, hipStream_t);
 
 namespace {
 thread_local std::string g_err;
@@ -659,6 +662,18 @@ static void eps_plan(int ng, int nw, int *group, size_t *gws, size_t *need) {
     *gws = gje_workspace_bytes(ng, *group, R);
     *need = *gws + sizeof(int) * 2 * (size_t)*group * ng + 512;
 }
+
+// The interchange-free path: up to 64 matrices per group, all nw checked at once.
+static int nsd_group(int nw) { return std::max(1, std::min(nw, 64)); }
+
+// Both inversion paths take the larger of their two needs, so that the
+// workspace query answers for either call.
+static size_t eps_need(int ng, int nw) {
+    int group = 0;
+    size_t gws = 0, need = 0;
+    eps_plan(ng, nw, &group, &gws, &need);
+    return std::max(need, nsd_workspace_bytes(ng, nsd_group(nw), nw));
+}
 }  // namespace bgw
 
 extern "C" int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *bytes) {
@@ -666,9 +681,7 @@ extern "C" int bgw_eps_inv_workspace(bgw_handle_t h, int ng, int nw, size_t *byt
     if (!h || ng < 1 || nw < 1 || !bytes) return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_workspace");
     if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 12288");
     BGW_TRY(set_device(h));
-    int group = 0;
-    size_t gws = 0;
-    eps_plan(ng, nw, &group, &gws, bytes);
+    *bytes = eps_need(ng, nw);
     return BGW_OK;
 }
 
@@ -683,7 +696,7 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
     int group = 0;
     size_t gws = 0, need = 0;
     eps_plan(ng, nw, &group, &gws, &need);
-    BGW_TRY(ensure_ws(h, need, st));
+    BGW_TRY(ensure_ws(h, eps_need(ng, nw), st));
     int *ipiv = (int *)((char *)h->ws.p + ((gws + 255) / 256) * 256);
     {
         Timed tm(h, BGW_KERNEL_EPS_BUILD, st);
@@ -693,6 +706,30 @@ extern "C" int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, 
     for (int w0 = 0; w0 < nw; w0 += group) {
         const int gn = std::min(group, nw - w0);
         BGW_TRY(launch_gje_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, info + w0, h->ws.p, ipiv, st));
+    }
+    return BGW_OK;
+}
+
+extern "C" int bgw_eps_inv_nsd(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi,
+                               double *epsinv, int *info, void *stream) {
+    clear_error();
+    if (!h || ng < 1 || nw < 1 || !vcoul || !chi || !epsinv || !info)
+        return fail(BGW_ERR_ARG, "bad arguments to bgw_eps_inv_nsd");
+    if (ng > kMaxNg) return fail(BGW_ERR_UNSUPPORTED, "ng > 12288");
+    BGW_TRY(set_device(h));
+    hipStream_t st = (hipStream_t)stream;
+    BGW_TRY(ensure_ws(h, eps_need(ng, nw), st));
+    const int group = nsd_group(nw);
+    {
+        Timed tm(h, BGW_KERNEL_EPS_BUILD, st);
+        // chi is read before epsilon overwrites it (the call may be in place)
+        BGW_TRY(launch_nsd_check((const double2 *)chi, vcoul, ng, nw, group, h->ws.p, st));
+        BGW_TRY(launch_eps_build((const double2 *)chi, vcoul, ng, nw, (double2 *)epsinv, st));
+    }
+    Timed tm(h, BGW_KERNEL_INVERT, st);
+    for (int w0 = 0; w0 < nw; w0 += group) {
+        const int gn = std::min(group, nw - w0);
+        BGW_TRY(launch_nsd_invert((double2 *)epsinv + (size_t)w0 * ng * ng, ng, gn, w0, nw, info + w0, h->ws.p, st));
     }
     return BGW_OK;
 }

@@ -29,6 +29,7 @@
 //
 // Barrier waits are bounded: a wait that exceeds its spin budget stores
 // info = -1000 for that matrix and gives up, so the kernel always terminates.
+#include <cfloat>
 #include <cstdlib>
 #include <cstring>
 #include <utility>
@@ -444,18 +445,19 @@ struct GjeCols {
     }
 };
 
-// For every column of cs: apply the interchanges ipiv[r0 .. r0+nbr) in order,
-// copy rows r0 .. r0+nbr-1 to Rs [nbr][m] and zero them in A.
+// For every column of cs: apply the interchanges ipiv[r0 .. r0+nbr) in order
+// (none when ipiv is null), copy rows r0 .. r0+nbr-1 to Rs [nbr][m] and zero
+// them in A.
 __global__ __launch_bounds__(64) void k_gje_swap_save(double2 *__restrict__ A, int n, int r0, int nbr, GjeCols cs,
                                                       const int *__restrict__ ipiv, double2 *__restrict__ Rs) {
     const int mat = blockIdx.y;
     double2 *Am = A + (size_t)mat * n * n;
-    const int *ip = ipiv + (size_t)mat * n;
+    const int *ip = ipiv ? ipiv + (size_t)mat * n : nullptr;
     const int m = cs.count();
     double2 *R = Rs + (size_t)mat * nbr * m;
     for (int cp = blockIdx.x * blockDim.x + threadIdx.x; cp < m; cp += gridDim.x * blockDim.x) {
         const int c = cs.col(cp);
-        for (int j = 0; j < nbr; ++j) {
+        for (int j = 0; ip && j < nbr; ++j) {
             const int p = ip[r0 + j];
             if (p > r0 + j && p < n) {
                 const double2 t = Am[(size_t)(r0 + j) * n + c];
@@ -1120,6 +1122,280 @@ int gje_max_group(int n) {
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const long long slots = (long long)per_cu * cus;
     return (int)std::max<long long>(1, slots / R);
+}
+
+
+// ---------------------------------------------------------------------------
+// Inversion without row interchanges, for chi Hermitian and negative
+// semidefinite: chi0 at zero and at imaginary frequency, where every weight
+// of the chi sum is negative.  With S = diag(v^1/2) (v > 0),
+//   eps = 1 - v chi = S epst S^-1,   epst = 1 - S chi S,
+// and epst is Hermitian with every eigenvalue >= 1.  Every leading principal
+// block of epst is then >= 1 as well, so each elimination pivot (the ratio
+// of consecutive leading minors, the same for eps and epst because a
+// diagonal similarity keeps every principal minor) is real and >= 1:
+// elimination needs no interchanges, and without them Gauss-Jordan is
+// exactly as stable as on the Hermitian positive definite epst.  The column
+// steps then need no search over the rows, and only the diagonal block of a
+// panel is eliminated step by step:
+//   k_nsd_check  max over (G, G') of sqrt(v_G v_G') |chi_GG' - conj chi_G'G|
+//                and of sqrt(v_G v_G') |chi_GG'| (read before epsilon is
+//                built in place), +inf when some v <= 0 or a value is not
+//                finite;
+//   k_nsd_diag   one workgroup per matrix inverts the panel's diagonal block
+//                D (kNsdNb x kNsdNb, registers, one barrier per step) in
+//                place and into Dinv, watching every pivot;
+//   k_nsd_rows   the panel's other rows become -A[i, K] D^-1, all rows in
+//                parallel;
+// then the pivoted path's save (without interchanges) and rank update.  A
+// matrix whose chi is not Hermitian to 1e-8 (relative, on the symmetrised
+// scale) or has v <= 0 gets info = -2; one with a pivot whose real part is
+// below 1/2, or that is not real to half of it, gets info = -3 (chi not
+// negative semidefinite).  Either way epsinv is unspecified.
+constexpr int kNsdNb = 64;        // panel width (diagonal block size)
+constexpr int kNsdDiagThreads = 512;
+constexpr int kNsdRowsPer = 32;   // rows of one k_nsd_rows workgroup
+constexpr int kNsdTile = 32;      // tile of the Hermitian check
+constexpr double kNsdHermTol = 1e-8;
+
+__device__ __forceinline__ void atomic_max_nonneg(double *p, double x) {
+    // non-negative doubles order like their bit patterns
+    atomicMax((unsigned long long *)p, (unsigned long long)__double_as_longlong(x));
+}
+
+// Upper tile pairs (I <= J) of each matrix; chk[mat] = {non-Hermiticity, max}.
+__global__ __launch_bounds__(256) void k_nsd_check(const double2 *__restrict__ chi, const double *__restrict__ v,
+                                                   int n, int tiles, double *__restrict__ chk) {
+    __shared__ double2 T[kNsdTile][kNsdTile + 1];
+    __shared__ double red[2][4];
+    const int mat = blockIdx.y;
+    // blockIdx.x enumerates the pairs I <= J row by row
+    int I = 0, rem = blockIdx.x;
+    while (rem >= tiles - I) {
+        rem -= tiles - I;
+        ++I;
+    }
+    const int J = I + rem;
+    const double2 *C = chi + (size_t)mat * n * n;
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    const int I0 = I * kNsdTile, J0 = J * kNsdTile;
+#pragma unroll
+    for (int r = 0; r < kNsdTile; r += 8) {  // T[a][b] = chi[J0 + a][I0 + b]
+        const int a = ty + r, row = J0 + a, col = I0 + tx;
+        T[a][tx] = (row < n && col < n) ? C[(size_t)row * n + col] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    double nh = 0.0, mx = 0.0;
+    const int j = J0 + tx;
+    const double vj = j < n ? v[j] : 1.0;
+#pragma unroll
+    for (int r = 0; r < kNsdTile; r += 8) {
+        const int i = I0 + ty + r;
+        if (i < n && j < n) {
+            const double vi = v[i];
+            const double2 x = C[(size_t)i * n + j];
+            const double2 y = T[tx][ty + r];  // chi[j][i]
+            const double sc = sqrt(vi * vj);
+            double d = sc * sqrt((x.x - y.x) * (x.x - y.x) + (x.y + y.y) * (x.y + y.y));
+            double m = sc * fmax(sqrt(x.x * x.x + x.y * x.y), sqrt(y.x * y.x + y.y * y.y));
+            if (!(vi > 0.0) || !(vj > 0.0) || !(d <= DBL_MAX) || !(m <= DBL_MAX)) d = m = INFINITY;
+            nh = fmax(nh, d);
+            mx = fmax(mx, m);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        nh = fmax(nh, __shfl_xor(nh, off, 64));
+        mx = fmax(mx, __shfl_xor(mx, off, 64));
+    }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = nh;
+        red[1][tid >> 6] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 4; ++w) {
+            nh = fmax(nh, red[0][w]);
+            mx = fmax(mx, red[1][w]);
+        }
+        atomic_max_nonneg(chk + 2 * mat, nh);
+        atomic_max_nonneg(chk + 2 * mat + 1, mx);
+    }
+}
+
+// Gauss-Jordan without interchanges on D = A[K, K], K = [ks, ks + nb),
+// padded to kNsdNb with the identity.  Thread t holds column t % 64 of the
+// rows t / 64 + 8 r; per step the pivot row and the pivot column go through
+// LDS (double-buffered: one barrier per step).
+__global__ __launch_bounds__(kNsdDiagThreads) void k_nsd_diag(double2 *__restrict__ A, int n, int ks, int nb,
+                                                              double2 *__restrict__ Dinv,
+                                                              const double *__restrict__ chk, int *__restrict__ info) {
+    constexpr int RW = kNsdDiagThreads / 64;  // rows held per column
+    constexpr int RPT = kNsdNb / RW;          // rows per thread
+    __shared__ double2 rowb[2][kNsdNb], colb[2][kNsdNb];
+    const int mat = blockIdx.x;
+    double2 *Am = A + (size_t)mat * n * n;
+    const int t = threadIdx.x, j = t & 63, rw = t >> 6;
+    double2 d[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = rw + RW * r;
+        d[r] = (i < nb && j < nb) ? Am[(size_t)(ks + i) * n + ks + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    bool bad = false;
+    for (int c = 0; c < nb; ++c) {
+        const int b = c & 1;
+        if (rw == (c % RW)) {
+            double2 x = d[0];
+#pragma unroll
+            for (int r = 1; r < RPT; ++r)
+                if (r == c / RW) x = d[r];
+            rowb[b][j] = x;
+        }
+        if (j == c) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) colb[b][rw + RW * r] = d[r];
+        }
+        __syncthreads();
+        const double2 p = colb[b][c];
+        bad |= !(p.x >= 0.5 && fabs(p.y) <= 0.5 * p.x);
+        const double den = p.x * p.x + p.y * p.y;
+        const double2 inv = make_double2(p.x / den, -p.y / den);
+        const double2 sj = j == c ? inv : cmul(inv, rowb[b][j]);  // new row c
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = rw + RW * r;
+            const double2 f = colb[b][i];
+            if (i == c) {
+                d[r] = sj;
+            } else if (j == c) {
+                const double2 fi = cmul(f, inv);
+                d[r] = make_double2(-fi.x, -fi.y);
+            } else {
+                d[r] = cfms(d[r], f, sj);
+            }
+        }
+    }
+    double2 *Dm = Dinv + (size_t)mat * kNsdNb * kNsdNb;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+        const int i = rw + RW * r;
+        if (i < nb && j < nb) {
+            Am[(size_t)(ks + i) * n + ks + j] = d[r];
+            Dm[i * kNsdNb + j] = d[r];
+        }
+    }
+    if (t == 0) {
+        if (ks == 0) {
+            const double nh = chk[2 * mat], mx = chk[2 * mat + 1];
+            if (!(mx <= DBL_MAX && nh <= kNsdHermTol * mx)) info[mat] = -2;
+        }
+        if (bad && info[mat] == 0) info[mat] = -3;
+    }
+}
+
+// A[i, K] = -A[i, K] Dinv for the rows i outside K of one block of kNsdRowsPer
+// rows.  Thread t: row t / 8, columns t % 8 + 8 q.
+__global__ __launch_bounds__(256) void k_nsd_rows(double2 *__restrict__ A, int n, int ks, int nb,
+                                                  const double2 *__restrict__ Dinv) {
+    extern __shared__ double2 nsd_lds[];
+    double2 *Ds = nsd_lds;                        // [kNsdNb][kNsdNb]
+    double2 *As = nsd_lds + kNsdNb * kNsdNb;      // [kNsdRowsPer][kNsdNb + 1]
+    constexpr int ALD = kNsdNb + 1;
+    const int mat = blockIdx.y;
+    double2 *Am = A + (size_t)mat * n * n;
+    const double2 *Dm = Dinv + (size_t)mat * kNsdNb * kNsdNb;
+    const int i0 = blockIdx.x * kNsdRowsPer, tid = threadIdx.x;
+    for (int e = tid; e < kNsdNb * kNsdNb; e += 256) {
+        const int k = e / kNsdNb, jj = e % kNsdNb;
+        Ds[e] = (k < nb && jj < nb) ? Dm[e] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < kNsdRowsPer * kNsdNb; e += 256) {
+        const int il = e / kNsdNb, k = e % kNsdNb, i = i0 + il;
+        As[il * ALD + k] = (i < n && k < nb) ? Am[(size_t)i * n + ks + k] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int il = tid >> 3, cg = tid & 7;
+    double2 acc[kNsdNb / 8];
+#pragma unroll
+    for (int q = 0; q < kNsdNb / 8; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int k = 0; k < nb; ++k) {
+        const double2 a = As[il * ALD + k];
+#pragma unroll
+        for (int q = 0; q < kNsdNb / 8; ++q) {
+            const double2 x = Ds[k * kNsdNb + cg + 8 * q];
+            acc[q].x = fma(a.x, x.x, fma(-a.y, x.y, acc[q].x));
+            acc[q].y = fma(a.x, x.y, fma(a.y, x.x, acc[q].y));
+        }
+    }
+    const int i = i0 + il;
+    if (i < n && (i < ks || i >= ks + nb)) {
+#pragma unroll
+        for (int q = 0; q < kNsdNb / 8; ++q) {
+            const int jj = cg + 8 * q;
+            if (jj < nb) Am[(size_t)i * n + ks + jj] = make_double2(-acc[q].x, -acc[q].y);
+        }
+    }
+}
+
+namespace {
+struct NsdWs {
+    double2 *Rs, *Dinv;
+    double *chk;
+};
+NsdWs nsd_layout(void *ws, int n, int nmat, int nall) {
+    char *p = align256((char *)ws);
+    NsdWs w;
+    w.chk = (double *)p; p = align256(p + sizeof(double) * 2 * (size_t)nall);
+    w.Dinv = (double2 *)p; p = align256(p + sizeof(double2) * (size_t)nmat * kNsdNb * kNsdNb);
+    w.Rs = (double2 *)p;
+    return w;
+}
+}  // namespace
+
+// Workspace of the interchange-free inversion: nmat matrices per group,
+// nall matrices checked at once.
+size_t nsd_workspace_bytes(int n, int nmat, int nall) {
+    return 256 + ((sizeof(double) * 2 * (size_t)nall + 255) / 256) * 256 +
+           ((sizeof(double2) * (size_t)nmat * kNsdNb * kNsdNb + 255) / 256) * 256 +
+           sizeof(double2) * (size_t)nmat * gje_outer_nb(n) * n + 256;
+}
+
+int launch_nsd_check(const double2 *chi, const double *v, int n, int nall, int nmat, void *ws, hipStream_t st) {
+    NsdWs w = nsd_layout(ws, n, nmat, nall);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, (unsigned int *)w.chk, (size_t)4 * nall, 0u);
+    const int tiles = (n + kNsdTile - 1) / kNsdTile;
+    const long long pairs = (long long)tiles * (tiles + 1) / 2;
+    for (int m0 = 0; m0 < nall; m0 += 65535) {
+        const int mm = std::min(65535, nall - m0);
+        hipLaunchKernelGGL(k_nsd_check, dim3((unsigned)pairs, mm), dim3(256), 0, st, chi + (size_t)m0 * n * n, v, n,
+                           tiles, w.chk + 2 * (size_t)m0);
+    }
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+// In place: A[nmat][n][n] (matrices m0 .. m0 + nmat of the checked set).
+int launch_nsd_invert(double2 *A, int n, int nmat, int m0, int nall, int *info, void *ws, hipStream_t st) {
+    NsdWs w = nsd_layout(ws, n, nmat, nall);
+    const double *chk = w.chk + 2 * (size_t)m0;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (unsigned int *)info, (size_t)nmat, 0u);
+    const size_t rlds = sizeof(double2) * ((size_t)kNsdNb * kNsdNb + (size_t)kNsdRowsPer * (kNsdNb + 1));
+    BGW_HIP(hipFuncSetAttribute((const void *)k_nsd_rows, hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds));
+    const int nbo = gje_outer_nb(n);
+    for (int k = 0; k < n; k += nbo) {
+        const int ke = std::min(n, k + nbo);
+        for (int ks = k; ks < ke; ks += kNsdNb) {
+            const int nb = std::min(kNsdNb, ke - ks);
+            hipLaunchKernelGGL(k_nsd_diag, dim3(nmat), dim3(kNsdDiagThreads), 0, st, A, n, ks, nb, w.Dinv, chk, info);
+            hipLaunchKernelGGL(k_nsd_rows, dim3((n + kNsdRowsPer - 1) / kNsdRowsPer, nmat), dim3(256), rlds, st, A, n,
+                               ks, nb, (const double2 *)w.Dinv);
+            BGW_TRY(gje_apply(A, n, nmat, ks, nb, GjeCols{k, ke, ks, ks + nb}, nullptr, w.Rs, st));
+        }
+        BGW_TRY(gje_apply(A, n, nmat, k, ke - k, GjeCols{0, n, k, ke}, nullptr, w.Rs, st));
+    }
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
 }
 
 }  // namespace bgw

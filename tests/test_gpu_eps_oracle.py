@@ -64,22 +64,26 @@ def chi_of(handle, torch_dev, s, q, omega, precision):
 
 
 def compare(handle, torch_dev, s, q, chi, label):
-    """GPU eps^-1 of every frequency of chi against the oracle's."""
+    """GPU eps^-1 of every frequency of chi against the oracle's, by the
+    pivoted path and by the interchange-free one (chi is Hermitian negative
+    semidefinite at zero and imaginary frequency)."""
     torch = torch_dev[0]
     v = bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])
     einv, info = handle.eps_inv(dev(torch_dev, v), chi)
+    ensd, info_nsd = handle.eps_inv(dev(torch_dev, v), chi, nsd=True)
     torch.cuda.synchronize()
-    assert np.all(info.cpu().numpy() == 0)
+    assert np.all(info.cpu().numpy() == 0) and np.all(info_nsd.cpu().numpy() == 0)
     for w in range(chi.shape[0]):
         say(f"{label}: oracle inverse of frequency {w}, Ng = {chi.shape[-1]}")
         ref, rinfo = oracle.eps_inv(v, chi[w].cpu().numpy())
         assert rinfo[0] == 0
-        got = einv[w].cpu().numpy()
-        err = rel(got, ref[0])
-        say(f"{label}: frequency {w}: relative error {err:.3e}")
-        assert err <= TOL, (label, w, err)
-        for blk in BLOCKS:
-            assert rel(got[blk], ref[0][blk]) <= 10 * TOL, (label, w, blk)
+        for path, res in (("pivoted", einv), ("nsd", ensd)):
+            got = res[w].cpu().numpy()
+            err = rel(got, ref[0])
+            say(f"{label}: frequency {w}, {path}: relative error {err:.3e}")
+            assert err <= TOL, (label, path, w, err)
+            for blk in BLOCKS:
+                assert rel(got[blk], ref[0][blk]) <= 10 * TOL, (label, path, w, blk)
 
 
 def test_eps_inv_cooperative_on_silicon_like(torch_dev, handle, monkeypatch):
