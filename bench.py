@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "split"], default=None,
                     help="chi-sum precision of the step (default: the workload's)")
     ap.add_argument("--graph", action="store_true", help="chi0 through HIP-graph replay")
+    ap.add_argument("--eps-path", choices=["nsd", "pivoted"], default="nsd",
+                    help="epsilon^-1 without row interchanges (chi Hermitian negative semidefinite, as at zero and "
+                         "imaginary frequency) or with partial pivoting")
     ap.add_argument("--no-graph-compare", action="store_true", help="skip the graph-vs-eager comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (PMC byte-counter calibration)")
@@ -681,7 +684,7 @@ def main():
             h.chi0(be, omega, precision=precision, chis=bc, use_graph=graph)
             for i in bt:
                 x = Q[i]
-                h.eps_inv(x["v"], x["chi"], epsinv=x["einv"], info=x["info"])
+                h.eps_inv(x["v"], x["chi"], epsinv=x["einv"], info=x["info"], nsd=args.eps_path == "nsd")
 
     if args.autotune:
         print("[bench] autotune", file=sys.stderr, flush=True)
@@ -749,6 +752,7 @@ def main():
         "pair_fft_nominal_TFLOPs": sum(5.0 * b[0] * b[1] * b[2] * np.log2(b[0] * b[1] * b[2]) * K for b in boxes)
         / (pair_t * 1e-3) / 1e12,
         "eps_inv_TFLOPs": lu_flops / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
+        "eps_inv_path": args.eps_path,
     }
     ptr = load_traffic(f"pair_{wl.name}", ["paper_1111_4429_amd/csrc/fft2.hip", "paper_1111_4429_amd/csrc/common.h"])
     if ptr is not None and len(Q) == 1 and pair_t > 0:
@@ -774,7 +778,7 @@ def main():
         "herk": ("k_herk_f64", "mfma", chi_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
         "split_herk": ("k_chi_split (BF16 MFMA, 10 x 4 Ng^2 K per frequency)", "mfma", split_bf16, "TFLOP/s",
                        BF16_PEAK_TFLOPS),
-        "invert": ("Gauss-Jordan inversion (k_gje_*)", "mfma", lu_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
+        "invert": ("Gauss-Jordan inversion (k_gje_* or k_nsd_*)", "mfma", lu_flops, "TFLOP/s", FP64_PEAK_TFLOPS),
     }
     dominant = max(work, key=lambda k: per_step.get(k, 0))
     name, bound, per_step_work, unit, peak = work[dominant]

@@ -1154,7 +1154,7 @@ int gje_max_group(int n) {
 // negative semidefinite).  Either way epsinv is unspecified.
 constexpr int kNsdNb = 64;        // panel width (diagonal block size)
 constexpr int kNsdDiagThreads = 512;
-constexpr int kNsdRowsPer = 32;   // rows of one k_nsd_rows workgroup
+constexpr int kNsdRowsPer = 16;   // rows of one k_nsd_rows workgroup
 constexpr int kNsdTile = 32;      // tile of the Hermitian check
 constexpr double kNsdHermTol = 1e-8;
 
@@ -1224,62 +1224,71 @@ __global__ __launch_bounds__(256) void k_nsd_check(const double2 *__restrict__ c
 }
 
 // Gauss-Jordan without interchanges on D = A[K, K], K = [ks, ks + nb),
-// padded to kNsdNb with the identity.  Thread t holds column t % 64 of the
-// rows t / 64 + 8 r; per step the pivot row and the pivot column go through
-// LDS (double-buffered: one barrier per step).
+// padded to kNsdNb with the identity.  Thread t holds column t / 8 of the
+// rows 8 (t % 8) + r, so the eight threads of the pivot column sit in one
+// wavefront and, with the steps unrolled by eight, the pivot row's register
+// is known at compile time.  A step is one complex FMA per entry,
+// d -= f_i s_j with f the old pivot column and s the new pivot row
+// (inv * old row); the pivot row and column are then set exactly: row c to
+// s, column c to -f inv, (c, c) to inv.  The pivot row and column go
+// through LDS, double-buffered (one barrier per step), and every LDS read of
+// a step is issued before its arithmetic.
 __global__ __launch_bounds__(kNsdDiagThreads) void k_nsd_diag(double2 *__restrict__ A, int n, int ks, int nb,
                                                               double2 *__restrict__ Dinv,
                                                               const double *__restrict__ chk, int *__restrict__ info) {
-    constexpr int RW = kNsdDiagThreads / 64;  // rows held per column
-    constexpr int RPT = kNsdNb / RW;          // rows per thread
+    constexpr int CPT = kNsdDiagThreads / kNsdNb;  // threads per column
+    constexpr int RPT = kNsdNb / CPT;              // rows per thread
     __shared__ double2 rowb[2][kNsdNb], colb[2][kNsdNb];
     const int mat = blockIdx.x;
     double2 *Am = A + (size_t)mat * n * n;
-    const int t = threadIdx.x, j = t & 63, rw = t >> 6;
+    const int t = threadIdx.x, j = t / CPT, rg = t % CPT;  // rows RPT rg + r
     double2 d[RPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int i = rw + RW * r;
+        const int i = RPT * rg + r;
         d[r] = (i < nb && j < nb) ? Am[(size_t)(ks + i) * n + ks + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
     }
     bool bad = false;
-    for (int c = 0; c < nb; ++c) {
-        const int b = c & 1;
-        if (rw == (c % RW)) {
-            double2 x = d[0];
+    for (int cb = 0; cb * RPT < nb; ++cb) {
+        const bool holder = rg == cb;  // this thread holds the pivot rows of these RPT steps
 #pragma unroll
-            for (int r = 1; r < RPT; ++r)
-                if (r == c / RW) x = d[r];
-            rowb[b][j] = x;
-        }
-        if (j == c) {
+        for (int cr = 0; cr < RPT; ++cr) {
+            const int c = cb * RPT + cr;
+            if (c >= nb) break;
+            const int b = c & 1;
+            if (holder) rowb[b][j] = d[cr];
+            if (j == c) {
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) colb[b][rw + RW * r] = d[r];
-        }
-        __syncthreads();
-        const double2 p = colb[b][c];
-        bad |= !(p.x >= 0.5 && fabs(p.y) <= 0.5 * p.x);
-        const double den = p.x * p.x + p.y * p.y;
-        const double2 inv = make_double2(p.x / den, -p.y / den);
-        const double2 sj = j == c ? inv : cmul(inv, rowb[b][j]);  // new row c
+                for (int r = 0; r < RPT; ++r) colb[b][RPT * rg + r] = d[r];
+            }
+            __syncthreads();
+            const double2 p = rowb[b][c];
+            const double2 rj = rowb[b][j];
+            double2 f[RPT];
 #pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            const int i = rw + RW * r;
-            const double2 f = colb[b][i];
-            if (i == c) {
-                d[r] = sj;
-            } else if (j == c) {
-                const double2 fi = cmul(f, inv);
-                d[r] = make_double2(-fi.x, -fi.y);
-            } else {
-                d[r] = cfms(d[r], f, sj);
+            for (int r = 0; r < RPT; ++r) f[r] = colb[b][RPT * rg + r];
+            __builtin_amdgcn_sched_barrier(0);
+            bad |= !(p.x >= 0.5 && fabs(p.y) <= 0.5 * p.x);
+            const double rden = 1.0 / (p.x * p.x + p.y * p.y);
+            const double2 inv = make_double2(p.x * rden, -p.y * rden);
+            const double2 sj = cmul(inv, rj);
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) d[r] = cfms(d[r], f[r], sj);
+            if (holder) d[cr] = sj;
+            if (j == c) {
+#pragma unroll
+                for (int r = 0; r < RPT; ++r) {
+                    const double2 fi = cmul(f[r], inv);
+                    d[r] = make_double2(-fi.x, -fi.y);
+                }
+                if (holder) d[cr] = inv;
             }
         }
     }
     double2 *Dm = Dinv + (size_t)mat * kNsdNb * kNsdNb;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-        const int i = rw + RW * r;
+        const int i = RPT * rg + r;
         if (i < nb && j < nb) {
             Am[(size_t)(ks + i) * n + ks + j] = d[r];
             Dm[i * kNsdNb + j] = d[r];
@@ -1295,13 +1304,15 @@ __global__ __launch_bounds__(kNsdDiagThreads) void k_nsd_diag(double2 *__restric
 }
 
 // A[i, K] = -A[i, K] Dinv for the rows i outside K of one block of kNsdRowsPer
-// rows.  Thread t: row t / 8, columns t % 8 + 8 q.
+// rows.  Thread t: row t / 16, columns t % 16 + 16 q.
 __global__ __launch_bounds__(256) void k_nsd_rows(double2 *__restrict__ A, int n, int ks, int nb,
                                                   const double2 *__restrict__ Dinv) {
     extern __shared__ double2 nsd_lds[];
-    double2 *Ds = nsd_lds;                        // [kNsdNb][kNsdNb]
-    double2 *As = nsd_lds + kNsdNb * kNsdNb;      // [kNsdRowsPer][kNsdNb + 1]
     constexpr int ALD = kNsdNb + 1;
+    constexpr int CG = 256 / kNsdRowsPer;  // column groups
+    constexpr int NQ = kNsdNb / CG;
+    double2 *Ds = nsd_lds;                        // [kNsdNb][kNsdNb]
+    double2 *As = nsd_lds + kNsdNb * kNsdNb;      // [kNsdRowsPer][ALD]
     const int mat = blockIdx.y;
     double2 *Am = A + (size_t)mat * n * n;
     const double2 *Dm = Dinv + (size_t)mat * kNsdNb * kNsdNb;
@@ -1315,15 +1326,15 @@ __global__ __launch_bounds__(256) void k_nsd_rows(double2 *__restrict__ A, int n
         As[il * ALD + k] = (i < n && k < nb) ? Am[(size_t)i * n + ks + k] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const int il = tid >> 3, cg = tid & 7;
-    double2 acc[kNsdNb / 8];
+    const int il = tid / CG, cg = tid % CG;
+    double2 acc[NQ];
 #pragma unroll
-    for (int q = 0; q < kNsdNb / 8; ++q) acc[q] = make_double2(0.0, 0.0);
+    for (int q = 0; q < NQ; ++q) acc[q] = make_double2(0.0, 0.0);
     for (int k = 0; k < nb; ++k) {
         const double2 a = As[il * ALD + k];
 #pragma unroll
-        for (int q = 0; q < kNsdNb / 8; ++q) {
-            const double2 x = Ds[k * kNsdNb + cg + 8 * q];
+        for (int q = 0; q < NQ; ++q) {
+            const double2 x = Ds[k * kNsdNb + cg + CG * q];
             acc[q].x = fma(a.x, x.x, fma(-a.y, x.y, acc[q].x));
             acc[q].y = fma(a.x, x.y, fma(a.y, x.x, acc[q].y));
         }
@@ -1331,11 +1342,24 @@ __global__ __launch_bounds__(256) void k_nsd_rows(double2 *__restrict__ A, int n
     const int i = i0 + il;
     if (i < n && (i < ks || i >= ks + nb)) {
 #pragma unroll
-        for (int q = 0; q < kNsdNb / 8; ++q) {
-            const int jj = cg + 8 * q;
+        for (int q = 0; q < NQ; ++q) {
+            const int jj = cg + CG * q;
             if (jj < nb) Am[(size_t)i * n + ks + jj] = make_double2(-acc[q].x, -acc[q].y);
         }
     }
+}
+
+// Rows r0 .. r0 + nbr of the columns cs copied to Rs [nbr][m] and zeroed in A
+// (the save of k_gje_swap_save without interchanges), one row per blockIdx.y.
+__global__ __launch_bounds__(256) void k_nsd_save(double2 *__restrict__ A, int n, int r0, int nbr, GjeCols cs,
+                                                  double2 *__restrict__ Rs) {
+    const int mat = blockIdx.z, jr = blockIdx.y;
+    const int m = cs.count();
+    const int cp = blockIdx.x * 256 + threadIdx.x;
+    if (cp >= m) return;
+    double2 *a = A + (size_t)mat * n * n + (size_t)(r0 + jr) * n + cs.col(cp);
+    Rs[(size_t)mat * nbr * m + (size_t)jr * m + cp] = *a;
+    *a = make_double2(0.0, 0.0);
 }
 
 namespace {
@@ -1375,6 +1399,17 @@ int launch_nsd_check(const double2 *chi, const double *v, int n, int nall, int n
     return BGW_OK;
 }
 
+// Rank-nbr update of the columns cs by the panel [r0, r0 + nbr), no interchanges.
+static int nsd_apply(double2 *A, int n, int nmat, int r0, int nbr, GjeCols cs, double2 *Rs, hipStream_t st) {
+    const int m = cs.count();
+    if (m <= 0) return BGW_OK;
+    hipLaunchKernelGGL(k_nsd_save, dim3((m + 255) / 256, nbr, nmat), dim3(256), 0, st, A, n, r0, nbr, cs, Rs);
+    hipLaunchKernelGGL(k_gje_update, dim3((n + UT - 1) / UT, (m + UT - 1) / UT, nmat), dim3(256), 0, st, A, n, r0,
+                       nbr, cs, (const double2 *)Rs);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
 // In place: A[nmat][n][n] (matrices m0 .. m0 + nmat of the checked set).
 int launch_nsd_invert(double2 *A, int n, int nmat, int m0, int nall, int *info, void *ws, hipStream_t st) {
     NsdWs w = nsd_layout(ws, n, nmat, nall);
@@ -1390,9 +1425,9 @@ int launch_nsd_invert(double2 *A, int n, int nmat, int m0, int nall, int *info, 
             hipLaunchKernelGGL(k_nsd_diag, dim3(nmat), dim3(kNsdDiagThreads), 0, st, A, n, ks, nb, w.Dinv, chk, info);
             hipLaunchKernelGGL(k_nsd_rows, dim3((n + kNsdRowsPer - 1) / kNsdRowsPer, nmat), dim3(256), rlds, st, A, n,
                                ks, nb, (const double2 *)w.Dinv);
-            BGW_TRY(gje_apply(A, n, nmat, ks, nb, GjeCols{k, ke, ks, ks + nb}, nullptr, w.Rs, st));
+            BGW_TRY(nsd_apply(A, n, nmat, ks, nb, GjeCols{k, ke, ks, ks + nb}, w.Rs, st));
         }
-        BGW_TRY(gje_apply(A, n, nmat, k, ke - k, GjeCols{0, n, k, ke}, nullptr, w.Rs, st));
+        BGW_TRY(nsd_apply(A, n, nmat, k, ke - k, GjeCols{0, n, k, ke}, w.Rs, st));
     }
     BGW_HIP(hipGetLastError());
     return BGW_OK;
