@@ -227,9 +227,12 @@ int bgw_tuned_config(bgw_handle_t h, int precision, int ng, long long K, int *cf
 /* bgw_pair_density for real coefficients: d->cv and d->cc point to DEVICE
  * f64 [nk][nv][ngw] and [nk][nc][ngw]; M is DEVICE f64 [K][ng].  The
  * transforms run in the complex pipeline (its workspace as for
- * bgw_pair_density) on complex copies held, with the complex M, in a second
- * handle buffer of 16 (nk (nv + nc) ngw + K ng) bytes.  Errors as
- * bgw_pair_density. */
+ * bgw_pair_density) with the conduction bands two to a complex band
+ * (c_2j + i c_2j+1): M is linear in the conduction state and real, so the
+ * complex result for (v, j) is M_v,2j + i M_v,2j+1, half the transforms of
+ * one band at a time.  The complex copies and that complex M are held in a
+ * second handle buffer of 16 (nk (nv + ceil(nc/2)) ngw + nk nv ceil(nc/2) ng)
+ * bytes.  Errors as bgw_pair_density. */
 int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, double *M, void *stream);
 
 /* bgw_chi0 for real M: q[i].M is DEVICE f64 [K][ng], q[i].chi DEVICE f64

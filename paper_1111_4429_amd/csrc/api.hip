@@ -624,9 +624,11 @@ extern "C" int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, dou
     if (!h || !M) return fail(BGW_ERR_ARG, "null handle or output");
     BGW_TRY(set_device(h));
     hipStream_t st = (hipStream_t)stream;
-    // complex copies of the real coefficients and the complex M in the second buffer
-    const long long nvw = (long long)d->nk * d->nv * d->ngw, ncw = (long long)d->nk * d->nc * d->ngw;
-    const long long nm = (long long)d->nk * d->nv * d->nc * d->ng;
+    // complex copies of the real valence coefficients, the conduction bands two to a
+    // complex band, and the complex M of (valence, band pair)
+    const int ncp = (d->nc + 1) / 2;
+    const long long nvw = (long long)d->nk * d->nv * d->ngw, ncw = (long long)d->nk * ncp * d->ngw;
+    const long long nm = (long long)d->nk * d->nv * ncp * d->ng;
     auto al256 = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t off_cc = al256(sizeof(double2) * nvw), off_m = off_cc + al256(sizeof(double2) * ncw);
     const size_t need = off_m + al256(sizeof(double2) * nm);
@@ -644,12 +646,13 @@ extern "C" int bgw_pair_density_real(bgw_handle_t h, const bgw_pair_desc *d, dou
     }
     char *a = (char *)h->aux.p;
     BGW_TRY(launch_real_to_complex(d->cv, nvw, (double2 *)a, st));
-    BGW_TRY(launch_real_to_complex(d->cc, ncw, (double2 *)(a + off_cc), st));
+    BGW_TRY(launch_pack_band_pairs(d->cc, d->nk, d->nc, d->ngw, (double2 *)(a + off_cc), st));
     bgw_pair_desc dc = *d;
     dc.cv = (const double *)a;
     dc.cc = (const double *)(a + off_cc);
+    dc.nc = ncp;
     BGW_TRY(bgw_pair_density(h, &dc, (double *)(a + off_m), stream));
-    return launch_complex_real_part((const double2 *)(a + off_m), nm, M, st);
+    return launch_unpack_pair_halves((const double2 *)(a + off_m), d->nk * d->nv, d->nc, d->ng, M, st);
 }
 
 

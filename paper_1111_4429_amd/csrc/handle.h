@@ -107,7 +107,8 @@ int launch_transpose_pairs(const double2 *M, long long K, int ng, int head, doub
 int launch_gemm_phq(const GemmProb &G, int tile, hipStream_t);
 // ---- real flavor (real.hip)
 int launch_real_to_complex(const double *src, long long n, double2 *dst, hipStream_t);
-int launch_complex_real_part(const double2 *src, long long n, double *dst, hipStream_t);
+int launch_pack_band_pairs(const double *src, int nk, int nc, int ngw, double2 *dst, hipStream_t);
+int launch_unpack_pair_halves(const double2 *Mp, int nkv, int nc, int ng, double *M, hipStream_t);
 int launch_syrk_batch(const SyrkProb *probs, int nprob, long long nitems, int grid, hipStream_t);
 int syrk_blocks_per_cu();
 int launch_syrk_finalize(const SyrkFin *probs, int nprob, int maxng, hipStream_t);

@@ -16,9 +16,40 @@ __global__ void k_real_to_complex(const double *__restrict__ src, long long n, d
         dst[e] = make_double2(src[e], 0.0);
 }
 
-__global__ void k_complex_real_part(const double2 *__restrict__ src, long long n, double *__restrict__ dst) {
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
-        dst[e] = src[e].x;
+// Two real conduction bands as one complex band: dst[k][j] = src[k][2j] +
+// i src[k][2j + 1] (the second zero past nc), ncp = ceil(nc / 2) per k.  M is
+// linear in the conduction state and real for real coefficients, so the
+// complex pair density of (v, j) is M_v,2j + i M_v,2j+1: one transform for two
+// pairs.
+__global__ void k_pack_band_pairs(const double *__restrict__ src, int nk, int nc, int ngw,
+                                  double2 *__restrict__ dst) {
+    const int ncp = (nc + 1) / 2;
+    const long long n = (long long)nk * ncp * ngw;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int g = (int)(e % ngw);
+        const long long r = e / ngw;
+        const int j = (int)(r % ncp), k = (int)(r / ncp);
+        const double *sk = src + (size_t)k * nc * ngw;
+        const double a = sk[(size_t)(2 * j) * ngw + g];
+        const double b = 2 * j + 1 < nc ? sk[(size_t)(2 * j + 1) * ngw + g] : 0.0;
+        dst[e] = make_double2(a, b);
+    }
+}
+
+// The real pair densities from the packed ones: M[(k nv + v) nc + c][G] is
+// the real part of Mp[(k nv + v) ncp + c / 2][G] for even c, the imaginary
+// part for odd c.
+__global__ void k_unpack_pair_halves(const double2 *__restrict__ Mp, int nkv, int nc, int ng, double *__restrict__ M) {
+    const int ncp = (nc + 1) / 2;
+    const long long n = (long long)nkv * nc * ng;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+        const int G = (int)(e % ng);
+        const long long r = e / ng;
+        const int c = (int)(r % nc);
+        const long long kv = r / nc;
+        const double2 z = Mp[((size_t)kv * ncp + c / 2) * ng + G];
+        M[e] = (c & 1) ? z.y : z.x;
+    }
 }
 
 namespace {
@@ -166,9 +197,18 @@ int launch_real_to_complex(const double *src, long long n, double2 *dst, hipStre
     return BGW_OK;
 }
 
-int launch_complex_real_part(const double2 *src, long long n, double *dst, hipStream_t st) {
-    hipLaunchKernelGGL(k_complex_real_part, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0,
-                       st, src, n, dst);
+int launch_pack_band_pairs(const double *src, int nk, int nc, int ngw, double2 *dst, hipStream_t st) {
+    const long long n = (long long)nk * ((nc + 1) / 2) * ngw;
+    hipLaunchKernelGGL(k_pack_band_pairs, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0,
+                       st, src, nk, nc, ngw, dst);
+    BGW_HIP(hipGetLastError());
+    return BGW_OK;
+}
+
+int launch_unpack_pair_halves(const double2 *Mp, int nkv, int nc, int ng, double *M, hipStream_t st) {
+    const long long n = (long long)nkv * nc * ng;
+    hipLaunchKernelGGL(k_unpack_pair_halves, dim3((unsigned)std::min<long long>((n + 255) / 256, 8192)), dim3(256), 0,
+                       st, Mp, nkv, nc, ng, M);
     BGW_HIP(hipGetLastError());
     return BGW_OK;
 }
