@@ -92,6 +92,8 @@ def test_null_arguments_rejected_without_gpu():
     assert L.bgw_pair_density(None, ctypes.byref(d), None, None) == bgw.BGW_ERR_ARG
     assert L.bgw_chi0(None, None, None) == bgw.BGW_ERR_ARG
     assert L.bgw_eps_inv(None, 10, 1, None, None, None, None, None) == bgw.BGW_ERR_ARG
+    assert L.bgw_eps_inv_nsd(None, 10, 1, None, None, None, None, None) == bgw.BGW_ERR_ARG
+    assert L.bgw_eps_inv_nsd(None, 0, 1, 1, 1, 1, 1, None) == bgw.BGW_ERR_ARG
     assert L.bgw_destroy(None) == bgw.BGW_OK
     h = ctypes.c_void_p()
     assert L.bgw_create(None, 0) == bgw.BGW_ERR_ARG
