@@ -64,11 +64,12 @@ constexpr int WR = 32, WC = 64;  // wave block edges (rows G, columns H)
 // A 128-wide tile gives the real product the same flops per loaded byte as
 // the 64-wide complex tile; 8 waves of 64 accumulators each let two blocks
 // share a CU (four waves per SIMD to cover the loads).  The next stage's
-// values are loaded into registers while the current one feeds the MFMAs.
+// values are loaded into registers while the current one feeds the MFMAs,
+// then stored into the other of two LDS stages: one barrier per stage.
 // Raw sums to o (rows/columns >= ng dropped).
 __device__ __forceinline__ void syrk_tile(const double *__restrict__ M, int ng, const double *__restrict__ w,
                                           int G0, int H0, long long k0, long long k1, double *__restrict__ o,
-                                          double (*As)[RLDA], double (*Bs)[RLDA]) {
+                                          double (*As)[RKC][RLDA], double (*Bs)[RKC][RLDA]) {
     constexpr int NR = WR / 16, NC = WC / 16, LR = RTHREADS / RT, SL = RKC / LR;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
@@ -95,31 +96,38 @@ __device__ __forceinline__ void syrk_tile(const double *__restrict__ M, int ng, 
             bv[s] = (in && hin) ? r[H0 + lcol] : 0.0;
         }
     };
-    load_stage(k0);
-    for (long long kk = k0; kk < k1; kk += RKC) {
-        __syncthreads();  // the previous stage's reads are done
+    auto store_stage = [&](int sb) {
 #pragma unroll
         for (int s = 0; s < SL; ++s) {
-            As[lrow + LR * s][lcol] = av[s];
-            Bs[lrow + LR * s][lcol] = bv[s];
+            As[sb][lrow + LR * s][lcol] = av[s];
+            Bs[sb][lrow + LR * s][lcol] = bv[s];
         }
-        __syncthreads();
-        if (kk + RKC < k1) load_stage(kk + RKC);
+    };
+    load_stage(k0);
+    store_stage(0);
+    __syncthreads();
+    int cur = 0;
+    for (long long kk = k0; kk < k1; kk += RKC) {
+        const bool more = kk + RKC < k1;
+        if (more) load_stage(kk + RKC);
 #pragma unroll
         for (int s = 0; s < RKC / 4; ++s) {
             const int kr = 4 * s + lk;
             double x[NR], y[NC];
 #pragma unroll
-            for (int a = 0; a < NR; ++a) x[a] = As[kr][wr * WR + 16 * a + li];
+            for (int a = 0; a < NR; ++a) x[a] = As[cur][kr][wr * WR + 16 * a + li];
 #pragma unroll
-            for (int b = 0; b < NC; ++b) y[b] = Bs[kr][wc * WC + 16 * b + li];
+            for (int b = 0; b < NC; ++b) y[b] = Bs[cur][kr][wc * WC + 16 * b + li];
 #pragma unroll
             for (int a = 0; a < NR; ++a)
 #pragma unroll
                 for (int b = 0; b < NC; ++b) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[a], y[b], c[a][b], 0, 0, 0);
         }
+        // the other stage was last read before the previous barrier
+        if (more) store_stage(cur ^ 1);
+        __syncthreads();
+        cur ^= 1;
     }
-    __syncthreads();  // the LDS tiles are reused by the block's next item
     // D layout of v_mfma_f64_16x16x4: lane l, register r -> row 4r + l/16, col l%16
 #pragma unroll
     for (int a = 0; a < NR; ++a)
@@ -140,8 +148,8 @@ __device__ __forceinline__ void syrk_tile(const double *__restrict__ M, int ng, 
 // complex chi sum.
 __global__ __launch_bounds__(512, 4) void k_syrk_f64(const SyrkProb *__restrict__ probs, int nprob, long long i0,
                                                   long long i1) {
-    __shared__ double As[RKC][RLDA];
-    __shared__ double Bs[RKC][RLDA];
+    __shared__ double As[2][RKC][RLDA];
+    __shared__ double Bs[2][RKC][RLDA];
     for (long long item = i0 + blockIdx.x; item < i1; item += gridDim.x) {
         int lo = 0, hi = nprob - 1;
         while (lo < hi) {
