@@ -1147,7 +1147,10 @@ int gje_max_group(int n) {
 //                place and into Dinv, watching every pivot;
 //   k_nsd_rows   the panel's other rows become -A[i, K] D^-1, all rows in
 //                parallel;
-// then the pivoted path's save (without interchanges) and rank update.  A
+//   k_nsd_save   the panel rows of the other columns copied and zeroed, one
+//                workgroup row per panel row;
+// then the pivoted path's rank update (k_gje_update), in the same two-level
+// outer blocks.  A
 // matrix whose chi is not Hermitian to 1e-8 (relative, on the symmetrised
 // scale) or has v <= 0 gets info = -2; one with a pivot whose real part is
 // below 1/2, or that is not real to half of it, gets info = -3 (chi not
