@@ -587,6 +587,153 @@ def bench_real(args, wl):
     print(json.dumps(out), flush=True)
 
 
+# Real-axis workload: the paper's full-frequency grid (uniform 0.5 eV up to
+# 10 eV, then a spacing growing by 0.5 eV per point up to 40 eV: 30
+# frequencies) and a broadening of 0.1 eV.
+REALAXIS_GRID = (0.5, 10.0, 40.0, 0.5)
+REALAXIS_DELTA = 0.1
+
+
+def bench_realaxis(args, wl):
+    """Real frequency axis: one step = pair densities of every pair -> the
+    retarded chi^r(E) for every E of the grid (two Hermitian sums per E, of
+    Re w and Im w) -> epsilon^-1(E) by elimination with partial pivoting
+    (chi^r is not Hermitian).  value = FP64-equivalent chi flops (2 x 4 Ng^2 K
+    per frequency) / step time."""
+    import torch
+
+    from paper_1111_4429_amd import bgw, synth
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {wl.name}", file=sys.stderr, flush=True)
+    s = synth.make_system(wl)
+    q = s["qs"][0]
+    n, nk, nv, nc, ng = s["n"], s["nk"], s["nv"], s["nc"], q["ng"]
+    K = nk * nv * nc
+    E = bgw.ff_grid(*REALAXIS_GRID)
+    nE = len(E)
+    delta = REALAXIS_DELTA
+    precision = bgw.FP64 if (args.precision or wl.precision) == "fp64" else bgw.SPLIT_BF16
+    pf = 1.0 / (nk * s["vol"])
+    h = bgw.Handle(0)
+    cv = torch.from_numpy(q["cv"]).to(dev)
+    cc = torch.from_numpy(s["cc"]).to(dev)
+    ev = torch.from_numpy(q["ev"]).to(dev)
+    ec = torch.from_numpy(s["ec"]).to(dev)
+    v = torch.from_numpy(bgw.vcoul_bulk(s["bmat"], q["q"], q["ge"])).to(dev)
+    M = torch.empty((K, ng), dtype=torch.complex128, device=dev)
+    chi = torch.empty((nE, ng, ng), dtype=torch.complex128, device=dev)
+    einv = torch.empty_like(chi)
+    info = torch.empty(nE, dtype=torch.int32, device=dev)
+    ent = dict(M=M, ev=ev, ec=ec, nk=nk, nv=nv, nc=nc, head=0, prefactor=pf)
+
+    def step():
+        h.pair_density(n, s["gw"], q["ge"], cv, cc, M=M)
+        h.chi0([ent], E, precision=precision, chis=[chi], axis="retarded", broadening=delta)
+        h.eps_inv(v, chi, epsinv=einv, info=info)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    h.reset_timing()
+    h.set_timing(True)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    h.set_timing(False)
+    assert int(info.abs().max()) == 0
+    tm = h.timing()
+    per_step = {k: tm[k][0] / args.steps for k in tm if tm[k][1]}
+    launches = {k: tm[k][1] / args.steps for k in tm if tm[k][1]}
+    flops = 2.0 * 4.0 * ng * ng * K * nE
+    gemm = "split_herk" if precision == bgw.SPLIT_BF16 else "herk"
+    chi_ms = sum(per_step.get(k, 0) for k in ("weights", "herk", "finalize", "split_slice", "split_herk", "headwing"))
+    nl = launches[gemm]
+    g_ms = per_step[gemm] / nl
+    work = SPLIT_PRODUCTS * flops if gemm == "split_herk" else flops
+    peak = BF16_PEAK_TFLOPS if gemm == "split_herk" else FP64_PEAK_TFLOPS
+    ach = work / nl / (g_ms * 1e-3) / 1e12
+    src = "split.hip" if gemm == "split_herk" else "chi.hip"
+    tr = load_traffic(f"{gemm}_{wl.name}", [f"paper_1111_4429_amd/csrc/{src}", "paper_1111_4429_amd/csrc/common.h"])
+    # split against FP64 on four frequencies of the grid (both timed), and their difference
+    pick = [0, nE // 3, 2 * nE // 3, nE - 1]
+    cmp = {}
+    if precision == bgw.SPLIT_BF16:
+        E4 = E[pick]
+        c64 = torch.empty((4, ng, ng), dtype=torch.complex128, device=dev)
+        csp = torch.empty_like(c64)
+        times = {}
+        for name, prec, out in (("fp64", bgw.FP64, c64), ("split", bgw.SPLIT_BF16, csp)):
+            h.chi0([ent], E4, precision=prec, chis=[out], axis="retarded", broadening=delta)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.split_reps):
+                h.chi0([ent], E4, precision=prec, chis=[out], axis="retarded", broadening=delta)
+            torch.cuda.synchronize()
+            times[name] = (time.perf_counter() - t0) * 1e3 / args.split_reps
+        err = float(torch.linalg.vector_norm(csp - c64) / torch.linalg.vector_norm(c64))
+        cmp = {"frequencies_eV": [float(x) for x in E4], "fp64_chi_ms": times["fp64"], "split_chi_ms": times["split"],
+               "speedup": times["fp64"] / times["split"], "rel_err_vs_fp64": err, "bar": 1e-9, "meets_bar": err <= 1e-9}
+        del c64, csp
+    out = {
+        "metric": "chi-sum TFLOP/s + pair-FFT GB/s; split vs FP64 speedup at rel err <=1e-9",
+        "value": flops / (ms_step * 1e-3) / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-split/f32-acc/f64-recombined" if gemm == "split_herk" else "f64",
+        "data": "synthetic (seeded generator: orthonormal plane-wave coefficients, uniform band energies)",
+        "config": {"workload": wl.name, "axis": "retarded", "grid": f"{n}^3", "ng": ng, "nv": nv, "nc": nc, "nk": nk,
+                   "npairs": K, "nE": nE, "E_grid": list(REALAXIS_GRID), "broadening_eV": delta,
+                   "precision": "split" if gemm == "split_herk" else "fp64",
+                   "flops": "2 x 4 Ng^2 K per frequency (Hermitian sums of Re w and Im w)"},
+        "stages": {"pair_density_ms": per_step.get("band", 0) + per_step.get("pair", 0) + per_step.get("pair_x", 0),
+                   "chi_ms": chi_ms, "chi_sum_TFLOPs": flops / (chi_ms * 1e-3) / 1e12,
+                   "eps_inv_ms": per_step.get("eps_build", 0) + per_step.get("invert", 0),
+                   "eps_inv_TFLOPs": 8.0 * ng ** 3 * nE / (per_step.get("invert", float("nan")) * 1e-3) / 1e12,
+                   "eps_inv_path": "pivoted"},
+        "split": cmp or None,
+        "roofline": {"kernel": "k_chi_split (BF16 MFMA, 10 x 4 Ng^2 K per weight vector)" if gemm == "split_herk"
+                     else "k_herk_f64", "bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None if tr is None else tr["bytes_per_launch"],
+                     "algorithmic_per_launch": work / nl, "avg_launch_ms": g_ms, "launches_per_step": nl},
+        "kernel_share": {k: per_step[k] / ms_step for k in per_step},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        import oracle
+
+        sample = int(max(16, min(args.cpu_sample_pairs, K, 2e11 / (16.0 * ng * ng * nE))))
+        pairs = np.sort(np.random.default_rng(123).choice(K, size=sample, replace=False))
+        t0 = time.perf_counter()
+        Ms = oracle.pair_density(s["gw"], q["ge"], q["cv"], s["cc"], pairs=pairs)
+        t_m = time.perf_counter() - t0
+        w = oracle.weights_real(q["ev"], s["ec"], E, delta, "retarded")[:, pairs]
+        t0 = time.perf_counter()
+        chi_s = oracle.chi(Ms, w, pf)
+        t_c = time.perf_counter() - t0
+        vo = oracle.vcoul(s["bmat"], q["q"], q["ge"])
+        t0 = time.perf_counter()
+        oracle.eps_inv(vo, np.ascontiguousarray(chi_s[:1]))
+        t_i = (time.perf_counter() - t0) * nE
+        t_step = (t_m + t_c) * K / sample + t_i
+        out["cpu_baseline"] = {"value": flops / t_step / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"oracle on {sample} of {K} pairs: M by convolution ({t_m:.2f} s) and chi^r "
+                                         f"with complex weights over all {ng}x{ng} entries and {nE} frequencies "
+                                         f"({t_c:.2f} s), extrapolated x{K / sample:.0f}; one inversion x {nE} "
+                                         f"({t_i:.1f} s); {t_step:.0f} s per step", "cpu": _cpu_model()}
+    h.close()
+    del M, chi, einv, cv, cc, ev, ec, ent
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -618,6 +765,9 @@ def main():
         return
     if wl.flavor == "real":
         bench_real(args, wl)
+        return
+    if wl.name.startswith("realaxis"):
+        bench_realaxis(args, wl)
         return
     q_subset = None
     if wl.nq > 1 and args.q_subset != "all":

@@ -81,6 +81,8 @@ WORKLOADS: Dict[str, Workload] = {
     "bse-kx-48": Workload("bse-kx-48", n=48, ng=1500, ngw=1500, nv=4, nc=64, nk=64),
     # static self-energy of the silicon-like cell: 404 inner states (4 occupied), 64 outer states, one q
     "sigma-48": Workload("sigma-48", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=1),
+    # the silicon-like cell on the real frequency axis (retarded chi on the full-frequency grid)
+    "realaxis-48": Workload("realaxis-48", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=64, precision="split"),
     # the silicon-like workload in the real flavor (real coefficients)
     "silicon-like-48-real": Workload("silicon-like-48-real", n=48, ng=1500, ngw=1500, nv=4, nc=400, nk=64,
                                      flavor="real"),
