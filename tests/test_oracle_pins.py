@@ -729,3 +729,44 @@ def test_realify_keeps_chi():
     chi_r = oracle.chi(oracle.pair_density(s["gw"], q["ge"], rv, rc), w, 0.01)
     assert np.all(chi_r.imag == 0.0)
     assert np.linalg.norm(chi_r - chi_c) <= 1e-12 * np.linalg.norm(chi_c)
+
+
+def test_nsd_chi_gives_pivots_of_at_least_one():
+    """The premise of the interchange-free inversion: for chi Hermitian
+    negative semidefinite and v > 0, elimination of eps = 1 - v chi without
+    row interchanges meets only real pivots >= 1 (they are those of the
+    Hermitian 1 - v^1/2 chi v^1/2 >= 1), and the inverse it gives equals the
+    oracle's (partial pivoting); an indefinite chi breaks the premise."""
+    rng = np.random.default_rng(21)
+    n = 60
+    X = rng.standard_normal((n, 3 * n)) + 1j * rng.standard_normal((n, 3 * n))
+    chi = -(X @ X.conj().T) / n
+    v = rng.uniform(0.05, 40.0, n)
+    v[0] = 1e4
+    eps = np.eye(n) - v[:, None] * chi
+    A = eps.copy()
+    piv = []
+    for c in range(n):
+        piv.append(A[c, c])
+        A[c + 1:, c:] -= np.outer(A[c + 1:, c] / A[c, c], A[c, c:])
+    piv = np.array(piv)
+    assert piv.real.min() >= 1.0 - 1e-9
+    assert np.abs(piv.imag).max() <= 1e-9 * np.abs(piv.real).max()
+    # Gauss-Jordan without interchanges gives the oracle's inverse
+    G = np.concatenate([eps, np.eye(n)], axis=1)
+    for c in range(n):
+        G[c] /= G[c, c]
+        for i in range(n):
+            if i != c:
+                G[i] -= G[i, c] * G[c]
+    ref, info = oracle.eps_inv(v, chi[None])
+    assert info[0] == 0
+    assert np.linalg.norm(G[:, n:] - ref[0]) <= 1e-12 * np.linalg.norm(ref[0])
+    # chi with a positive direction large enough: some pivot falls below 1/2
+    chi_bad = chi + 5.0 * np.outer(X[:, 0], X[:, 0].conj()) / n
+    A = np.eye(n) - v[:, None] * chi_bad
+    low = False
+    for c in range(n):
+        low |= A[c, c].real < 0.5
+        A[c + 1:, c:] -= np.outer(A[c + 1:, c] / A[c, c], A[c, c:])
+    assert low
