@@ -24,6 +24,20 @@
  *     thread-local message readable with bgw_last_error(); no C++ exception
  *     crosses this interface.
  *
+ * Environment switches, read at each call.  The first two are limits a
+ * deployment may set; the others force one of the library's own code paths
+ * (for tests and comparisons) and change no result beyond rounding order:
+ *   BGW_WORKSPACE_LIMIT=<bytes>    cap on the handle's device workspace;
+ *   BGW_TUNE_CACHE=<file>          JSON-lines cache of bgw_autotune choices;
+ *   BGW_FFT_BOX=full               transform on the caller's grid, not the
+ *                                  smallest alias-free box;
+ *   BGW_GENERIC_FFT=1              generic 2^a 3^b transform kernels only;
+ *   BGW_HERK_TILE=32|64            FP64 chi-sum output tile;
+ *   BGW_SPLIT_SLICE_BYTES=<bytes>  split chi-sum slice budget per launch
+ *                                  (a smaller one cuts K into more launches);
+ *   BGW_GJE_PATH=coop              cooperative panels in bgw_eps_inv also
+ *                                  for ng <= 1536.
+ *
  * Units: energies and frequencies in eV (converted with 1 Ha =
  * 27.211386245988 eV), lengths in bohr, Miller indices in reciprocal-
  * lattice units with components in [-n/2, n/2) (paper, Appendix on file
