@@ -30,6 +30,7 @@
  * Build: gcc -O2 -fopenmp -shared -fPIC oracle.c -o liboracle.so -lm
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -471,6 +472,8 @@ int orc_eps(int ng, int nw, const double *v, const double *chi, double *eps)
 int orc_inverse(int n, const double *A, double *Ainv)
 {
     const long w = 2L * n; /* augmented width in complex entries */
+    /* BGW_ORACLE_PROGRESS set: one line on stderr every 512 rows (long runs) */
+    const int progress = getenv("BGW_ORACLE_PROGRESS") != NULL;
     double *T = (double *)malloc(sizeof(double) * 2 * (size_t)n * w);
     if (!T) return -5;
     for (long i = 0; i < n; ++i) {
@@ -483,6 +486,10 @@ int orc_inverse(int n, const double *A, double *Ainv)
     }
     int info = 0;
     for (long k = 0; k < n && !info; ++k) {
+        if (progress && k % 512 == 0) {
+            fprintf(stderr, "[oracle] inverse n=%d: elimination row %ld\n", n, k);
+            fflush(stderr);
+        }
         long p = k;
         double best = fabs(T[2 * (k * w + k)]) + fabs(T[2 * (k * w + k) + 1]);
         for (long i = k + 1; i < n; ++i) {
@@ -518,6 +525,10 @@ int orc_inverse(int n, const double *A, double *Ainv)
         /* back substitution, all n right-hand sides at once (row-oriented:
          * X[k][:] = (B[k][:] - sum_{m>k} U[k][m] X[m][:]) / U[k][k]) */
         for (long k = n - 1; k >= 0; --k) {
+            if (progress && k % 512 == 0) {
+                fprintf(stderr, "[oracle] inverse n=%d: back substitution row %ld\n", n, k);
+                fflush(stderr);
+            }
             double pr = T[2 * (k * w + k)], pi = T[2 * (k * w + k) + 1];
             double den = pr * pr + pi * pi;
 #pragma omp parallel for schedule(static)
