@@ -7,7 +7,9 @@ per block of the q -> 0 structure (head, wing, wing', body).
 
 Oracle cost on the host (plain elimination on [eps | I], OpenMP): about
 8 s at Ng = 2000 on 8 cores, growing as Ng^3; the supercell matrix (Ng =
-8000) takes several minutes and runs only when BGW_TEST_ORACLE_SUPERCELL=1.
+8000) runs only when BGW_TEST_ORACLE_SUPERCELL=1 (about 100 s for the whole
+test with 16 host threads, several minutes on fewer; BGW_ORACLE_PROGRESS=1
+makes the oracle report its progress on stderr).
 """
 
 import os
