@@ -400,7 +400,9 @@ int bgw_eps_inv(bgw_handle_t h, int ng, int nw, const double *vcoul, const doubl
  * or a value is not finite), -3 when a pivot has real part below 1/2 or is
  * not real to half of that (chi not negative semidefinite); epsinv[w] is
  * then unspecified and the caller inverts the original chi with
- * bgw_eps_inv. */
+ * bgw_eps_inv.  That fallback needs chi intact: an in-place call (epsinv ==
+ * chi) has overwritten it with epsilon, so a caller that may need the
+ * fallback passes a separate epsinv. */
 int bgw_eps_inv_nsd(bgw_handle_t h, int ng, int nw, const double *vcoul, const double *chi, double *epsinv,
                     int *info, void *stream);
 
